@@ -51,6 +51,8 @@ def load(path=None):
     lib.orc_spmv.argtypes = [ctypes.c_int, i64, _P, _P, _P, _P, _P]
     lib.orc_dot.argtypes = [i64, _P, _P]
     lib.orc_dot.restype = ctypes.c_double
+    lib.orc_dot_plain.argtypes = [i64, _P, _P]
+    lib.orc_dot_plain.restype = ctypes.c_double
     lib.orc_nrm2.argtypes = [i64, _P]
     lib.orc_nrm2.restype = ctypes.c_double
     lib.orc_transpose.argtypes = [i64, _P, _P, _P, _P, _P, _P]
@@ -62,7 +64,7 @@ def load(path=None):
     lib.orc_validate.argtypes = [ctypes.c_int, i64, _P, _P, _P, ctypes.c_int, ctypes.c_uint32]
     lib.orc_validate.restype = ctypes.c_int
     lib.orc_cg.argtypes = [ctypes.c_int, i64, _P, _P, _P, _P, _P, ctypes.c_double, i32,
-                           ctypes.POINTER(OrcInfo), _P, _P, _P, i32, _P, i32, i32]
+                           ctypes.POINTER(OrcInfo), _P, _P, _P, i32, _P, i32, i32, ctypes.c_int]
     lib.orc_cg.restype = ctypes.c_int
     if path is None:
         _lib = lib
@@ -91,10 +93,11 @@ def spmv(fmt, ptr, idx, val, x, lib=None):
     return y
 
 
-def dot(a, b, lib=None):
+def dot(a, b, lib=None, plain=False):
+    """a'b: the exact value rounded once (default) or the plain left-to-right loop."""
     lib = lib or load()
     a, b = _f64(a), _f64(b)
-    return lib.orc_dot(a.size, _p(a), _p(b))
+    return (lib.orc_dot_plain if plain else lib.orc_dot)(a.size, _p(a), _p(b))
 
 
 def transpose(ptr, idx, val, lib=None):
@@ -138,8 +141,10 @@ def validate(fmt, ptr, idx, val, base=0, flags=0, n=None, lib=None):
     return lib.orc_validate(fmt, n, _p(ptr), _p(idx), _p(val), base, flags)
 
 
-def cg(fmt, ptr, idx, val, b, x0=None, tol=1e-10, maxit=None, history=0, x_stride=0, x_cap=0, lib=None):
-    """Run the oracle CG; returns (x, info dict, history dict or None)."""
+def cg(fmt, ptr, idx, val, b, x0=None, tol=1e-10, maxit=None, history=0, x_stride=0, x_cap=0, lib=None,
+       plain_dots=False):
+    """Run the oracle CG; returns (x, info dict, history dict or None).
+    plain_dots selects the literal left-to-right scalar products."""
     lib = lib or load()
     ptr, idx, val, b = _i32(ptr), _i32(idx), _f64(val), _f64(b)
     n = ptr.size - 1
@@ -153,7 +158,7 @@ def cg(fmt, ptr, idx, val, b, x0=None, tol=1e-10, maxit=None, history=0, x_strid
     if x_stride and x_cap:
         xh = np.zeros((x_cap, n))
     lib.orc_cg(fmt, n, _p(ptr), _p(idx), _p(val), _p(b), _p(x), tol, maxit, ctypes.byref(info),
-               _p(ah), _p(bh), _p(rh), history, _p(xh), x_stride, x_cap)
+               _p(ah), _p(bh), _p(rh), history, _p(xh), x_stride, x_cap, 1 if plain_dots else 0)
     d = dict(iters=info.iters, status=info.status, relres=info.relres, relres_true=info.relres_true,
              ms_loop=info.ms_loop)
     hist = None

@@ -109,7 +109,33 @@ void orc_spmv(int fmt, int64_t n, const int32_t *ptr, const int32_t *idx,
 
 /* ------------------------------------------------------------- vectors */
 
+/* The scalar products r'r and p'Ap of the algorithm are taken as their exact
+ * values rounded to FP64: the paper leaves the summation order to a library
+ * routine, and a left-to-right FP64 loop over n ~ 1e4-1e6 terms is itself a
+ * source of error (up to n u sum|a_i b_i|) that moves CG's stopping step.
+ * Evaluation: Dot2 of Ogita, Rump and Oishi ("Accurate sum and dot product",
+ * SIAM J. Sci. Comput. 26(6), 2005): every product split exactly as
+ * p + pe (pe = fma(a, b, -p)), every addition split exactly as t + e (TwoSum),
+ * the error terms summed apart and added once at the end.  The result is as
+ * accurate as if computed in twice the working precision, then rounded. */
 double orc_dot(int64_t n, const double *a, const double *b)
+{
+    double s = 0.0, c = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        const double p = a[i] * b[i];
+        const double pe = fma(a[i], b[i], -p);
+        const double t = s + p;
+        const double z = t - s;
+        const double e = (s - (t - z)) + (p - z);
+        s = t;
+        c += e + pe;
+    }
+    return s + c;
+}
+
+/* The literal left-to-right loop, kept to measure how much an unspecified
+ * summation order moves the iteration (dot_mode 1 of orc_cg). */
+double orc_dot_plain(int64_t n, const double *a, const double *b)
 {
     double s = 0.0;
     for (int64_t i = 0; i < n; ++i)
@@ -291,12 +317,15 @@ static double now_ms(void)
  *   hist_* optional (NULL = off): alpha_k, beta_k and ||r_k|| per iteration
  *          (hist_cap entries), and x after every x_stride-th iteration into
  *          x_hist (x_cap snapshots of n values).
+ *   dot_mode 0: scalar products by orc_dot (exact value, rounded once);
+ *            1: the plain left-to-right loop.
  */
 int orc_cg(int fmt, int64_t n, const int32_t *ptr, const int32_t *idx, const double *val,
            const double *b, double *x, double tol, int32_t maxit, orc_info *info,
            double *alpha_hist, double *beta_hist, double *res_hist, int32_t hist_cap,
-           double *x_hist, int32_t x_stride, int32_t x_cap)
+           double *x_hist, int32_t x_stride, int32_t x_cap, int dot_mode)
 {
+    double (*dot)(int64_t, const double *, const double *) = dot_mode == 1 ? orc_dot_plain : orc_dot;
     orc_info loc;
     if (!info)
         info = &loc;
@@ -309,7 +338,7 @@ int orc_cg(int fmt, int64_t n, const int32_t *ptr, const int32_t *idx, const dou
         info->status = ORC_OK;
         return ORC_OK;
     }
-    double nb = orc_nrm2(n, b);
+    double nb = sqrt(dot(n, b, b));
     if (!isfinite(nb)) {
         info->status = ORC_ERR_NONFINITE;
         return ORC_ERR_NONFINITE;
@@ -335,7 +364,7 @@ int orc_cg(int fmt, int64_t n, const int32_t *ptr, const int32_t *idx, const dou
         r[i] = b[i] - q[i];
         p[i] = r[i];
     }
-    double rho = orc_dot(n, r, r);
+    double rho = dot(n, r, r);
     int status = ORC_NOT_CONVERGED;
     int32_t k = 0;
     if (sqrt(rho) <= tol * nb) {
@@ -344,7 +373,7 @@ int orc_cg(int fmt, int64_t n, const int32_t *ptr, const int32_t *idx, const dou
         for (k = 1; k <= maxit; ++k) {
             /* alpha = r'r / p'Ap with the iteration's single product q = Ap */
             orc_spmv(fmt, n, ptr, idx, val, p, q);
-            double sigma = orc_dot(n, p, q);
+            double sigma = dot(n, p, q);
             if (!(sigma > 0.0) || !isfinite(sigma)) {
                 status = ORC_ERR_BREAKDOWN;
                 --k;
@@ -355,7 +384,7 @@ int orc_cg(int fmt, int64_t n, const int32_t *ptr, const int32_t *idx, const dou
                 x[i] = x[i] + alpha * p[i];
             for (int64_t i = 0; i < n; ++i)
                 r[i] = r[i] - alpha * q[i];
-            double rho_new = orc_dot(n, r, r);
+            double rho_new = dot(n, r, r);
             double beta = rho_new / rho;
             if (alpha_hist && k <= hist_cap) {
                 alpha_hist[k - 1] = alpha;
@@ -383,7 +412,7 @@ int orc_cg(int fmt, int64_t n, const int32_t *ptr, const int32_t *idx, const dou
     orc_spmv(fmt, n, ptr, idx, val, x, q);
     for (int64_t i = 0; i < n; ++i)
         r[i] = b[i] - q[i];
-    info->relres_true = orc_nrm2(n, r) / nb;
+    info->relres_true = sqrt(dot(n, r, r)) / nb;
     free(r); free(p); free(q);
     return status;
 }

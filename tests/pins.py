@@ -106,6 +106,37 @@ def pin_three_formats_bitwise(lib):
     assert np.all(np.abs(y1 - A @ x) <= 2 * _row_bound(A, x) + 1e-300)
 
 
+def _exact_dot(a, b):
+    s = Fraction(0)
+    for u, v in zip(a, b):
+        s += Fraction(float(u)) * Fraction(float(v))
+    return s
+
+
+def pin_dot_exact(lib):
+    """Scalar products: the default is the exact inner product rounded once
+    (within 2 u of it even under heavy cancellation); the plain loop obeys the
+    gamma_n bound of a left-to-right sum."""
+    rng = np.random.default_rng(17)
+    for cancel in (False, True, "inexact"):
+        a = rng.uniform(-1, 1, 600)
+        b = rng.uniform(-1, 1, 600)
+        if cancel == "inexact":          # inexact products that nearly cancel pairwise
+            a = np.concatenate([a, -a])
+            b = np.concatenate([b, b * (1 + 2.0 ** -20)])
+        elif cancel:                       # condition number ~1e12: big terms that cancel exactly
+            big = rng.uniform(-1, 1, 300) * 2.0 ** 40
+            a = np.concatenate([a, big, -big])
+            b = np.concatenate([b, np.full(300, 3.0), np.full(300, 3.0)])
+            perm = rng.permutation(a.size)
+            a, b = a[perm], b[perm]
+        ex = _exact_dot(a, b)
+        got = oracle.dot(a, b, lib=lib)
+        assert abs(Fraction(got) - ex) <= 2 * U * abs(ex), "dot not within 2u of the exact value"
+        plain = oracle.dot(a, b, lib=lib, plain=True)
+        assert abs(Fraction(plain) - ex) <= Fraction(gamma(a.size)) * Fraction(float(np.sum(np.abs(a * b))) * 1.01)
+
+
 # ----------------------------------------------------------- conversions
 def pin_conversions(lib):
     """Transpose / triangle / expansion vs scipy, integer- and bit-exact."""
@@ -358,7 +389,7 @@ def pin_cg_formats_agree(lib):
     assert r1[1]["status"] == oracle.OK
 
 
-ALL_PINS = [pin_spmv_exact, pin_spmv_library, pin_three_formats_bitwise, pin_conversions, pin_validate,
+ALL_PINS = [pin_dot_exact, pin_spmv_exact, pin_spmv_library, pin_three_formats_bitwise, pin_conversions, pin_validate,
             pin_cg_cholesky, pin_cg_exact_termination, pin_cg_lanczos_spectrum, pin_cg_invariants,
             pin_cg_statuses, pin_cg_formats_agree]
 

@@ -26,8 +26,12 @@ MUTANTS = {
     "sym_missing_mirror": ("            if (j != i)\n                y[j] += val[k] * x[i];\n", ""),
     "sym_mirror_wrong_x": ("y[j] += val[k] * x[i];", "y[j] += val[k] * x[j];"),
     "sym_diagonal_twice": ("if (j != i)\n                y[j]", "if (j >= i)\n                y[j]"),
-    "dot_drops_first_term": ("for (int64_t i = 0; i < n; ++i)\n        s += a[i] * b[i];",
-                             "for (int64_t i = 1; i < n; ++i)\n        s += a[i] * b[i];"),
+    "dot_drops_first_term": ("for (int64_t i = 0; i < n; ++i) {\n        const double p = a[i] * b[i];",
+                             "for (int64_t i = 1; i < n; ++i) {\n        const double p = a[i] * b[i];"),
+    "dot_drops_product_error": ("c += e + pe;", "c += e;"),
+    "dot_drops_sum_error": ("c += e + pe;", "c += pe;"),
+    "dot_plain_drops_last_term": ("for (int64_t i = 0; i < n; ++i)\n        s += a[i] * b[i];",
+                                  "for (int64_t i = 0; i + 1 < n; ++i)\n        s += a[i] * b[i];"),
     "cg_x_update_sign": ("x[i] = x[i] + alpha * p[i];", "x[i] = x[i] - alpha * p[i];"),
     "cg_r_update_sign": ("r[i] = r[i] - alpha * q[i];", "r[i] = r[i] + alpha * q[i];"),
     "cg_beta_inverted": ("double beta = rho_new / rho;", "double beta = rho / rho_new;"),
@@ -39,7 +43,8 @@ MUTANTS = {
     "cg_no_breakdown_check": ("if (!(sigma > 0.0) || !isfinite(sigma)) {", "if (!isfinite(sigma)) {"),
     "cg_no_nonfinite_check": ("if (!isfinite(nb)) {", "if (0) {"),
     "cg_iters_off_by_one": ("info->iters = k;", "info->iters = k + 1;"),
-    "cg_true_residual_unscaled": ("info->relres_true = orc_nrm2(n, r) / nb;", "info->relres_true = orc_nrm2(n, r);"),
+    "cg_true_residual_unscaled": ("info->relres_true = sqrt(dot(n, r, r)) / nb;",
+                                  "info->relres_true = sqrt(dot(n, r, r));"),
     "transpose_wrong_index": ("tidx[dst] = (int32_t)l;", "tidx[dst] = idx[k];"),
     "upper_drops_diagonal": ("if (col[k] >= i) {", "if (col[k] > i) {"),
     "expand_drops_lower": ("if (tidx[k] < i) {", "if (tidx[k] < 0) {"),
