@@ -1,0 +1,185 @@
+/*
+ * cgmi -- conjugate gradient for sparse symmetric positive-definite systems
+ * on one MI355X (gfx950), FP64.
+ *
+ * The operation is the one of Rodrigues et al., "Parallel Sparse Matrix
+ * Solver on the GPU Applied to Simulation of Electrical Machines":
+ *   - section I: solve A x = b, A square, symmetric, positive definite and
+ *     sparse, b known;
+ *   - section III (algorithm): the conjugate-gradient iteration
+ *       alpha = r'r / p'Ap ; x += alpha p ; stop if converged ;
+ *       r -= alpha Ap ; beta = r_k'r_k / r_{k-1}'r_{k-1} ; p = r + beta p
+ *     with the single product Ap of each iteration computed by a sparse
+ *     matrix-vector product;
+ *   - section III (storage): A held in full CSR, or -- exploiting symmetry,
+ *     A = L + D + U with U' = L -- only one triangle plus the diagonal, the
+ *     product then being the stored triangle read by rows plus the same
+ *     arrays read by columns (the paper's "SCSR" and "SCSC" kernels); the
+ *     abstract also names CSC storage.
+ *
+ * Readings where the paper is silent: convergence is ||r_k||_2 <= tol*||b||_2
+ * on the recursively updated residual, tested after the r update; r0 is
+ * b - A x0; the loop bound is maxit; p'Ap <= 0 (or non-finite) stops with
+ * CG_ERR_BREAKDOWN; the iteration count is the number of products Ap made
+ * inside the loop.
+ *
+ * Conventions for every call
+ *   - indices are int32, values float64; index_base 0 or 1 (the paper's
+ *     arrays are 1-based) is converted once at creation;
+ *   - host pointers are read during the call only and never retained;
+ *   - device pointers (b, x, y) point to n float64 values in device memory
+ *     of the current HIP device (for example torch.Tensor.data_ptr() of a
+ *     ROCm tensor) and must stay valid until the work on the handle's
+ *     stream that uses them has finished;
+ *   - functions return a cg_status; no exception crosses the boundary;
+ *   - a handle is not thread-safe; distinct handles are independent.
+ */
+#ifndef CGMI_H
+#define CGMI_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct cg_handle cg_handle; /* opaque, owned by the library */
+
+/* storage formats */
+enum {
+    CG_FMT_CSR = 0,     /* full matrix by rows: ptr = rowptr[n+1], idx = column of each entry */
+    CG_FMT_SYM_CSR = 1, /* symmetric: upper triangle incl. diagonal by rows (j >= i; each row
+                           starts with its diagonal). The same arrays are the CSC of the lower
+                           triangle L + D, i.e. the paper's symmetric storage. */
+    CG_FMT_CSC = 2      /* full matrix by columns: ptr = colptr[n+1], idx = row of each entry */
+};
+
+/* status codes: 0 success, > 0 warning (x holds the last iterate), < 0 error */
+typedef enum {
+    CG_OK = 0,
+    CG_NOT_CONVERGED = 1,  /* maxit products done without meeting tol */
+    CG_ERR_ARG = -1,       /* bad argument (null pointer, bad enum, tol < 0, ...) */
+    CG_ERR_STRUCTURE = -2, /* malformed sparse structure (see cg_create) */
+    CG_ERR_BREAKDOWN = -3, /* p'Ap <= 0 or non-finite: A is not SPD (x = last iterate) */
+    CG_ERR_NONFINITE = -4, /* NaN / Inf in the values or in b */
+    CG_ERR_NOMEM = -5,     /* host or device allocation failed */
+    CG_ERR_HIP = -6,       /* a HIP runtime call failed (detail in cg_last_error) */
+    CG_ERR_UNSUPPORTED = -7 /* structure the scatter plan cannot colour (> 64 colours) */
+} cg_status;
+
+/* cg_create flags */
+#define CG_CHECK_SYMMETRY 1u /* CSR / CSC: require A == A' exactly (pattern and bits) */
+
+typedef struct {
+    int32_t iters;      /* products Ap inside the loop (0 if the start already met tol) */
+    int32_t status;     /* the cg_status also returned by cg_solve */
+    double relres;      /* ||r_k||_2 / ||b||_2 of the recursive residual */
+    double relres_true; /* ||b - A x||_2 / ||b||_2 of the returned x (one extra product) */
+    double ms;          /* host wall time of the call, milliseconds */
+} cg_info;
+
+/* Plan summary (host-side description of how the product is executed). */
+typedef struct {
+    int64_t n;
+    int64_t nnz;             /* stored entries */
+    int32_t format;
+    int32_t lanes_per_line;  /* lanes that share one row / column in the product */
+    int32_t spmv_blocks;     /* workgroups (= dot-product partials) of one product */
+    int32_t vec_blocks;      /* workgroups of the vector kernels */
+    int32_t colors;          /* scatter formats: colour phases per product; CSR: 0 */
+    int32_t max_block_entries;
+    int64_t slots;           /* scatter formats: total (block, target) write slots */
+    int64_t plan_bytes;      /* device bytes of the plan beyond ptr / idx / vals */
+} cg_plan_stats;
+
+/*
+ * cg_create -- copy A to the device and plan its product.
+ *   out         receives the handle (NULL on error; nothing is leaked)
+ *   format      CG_FMT_*
+ *   n           order of A (n >= 0; n == 0 is an empty system)
+ *   ptr         host, n+1 int32: line pointers, ptr[0] == index_base,
+ *               non-decreasing, ptr[n] - index_base = nnz < 2^31
+ *   idx         host, nnz int32: index of each entry, in [base, base+n),
+ *               strictly increasing within a line (sorted, no duplicates)
+ *   vals        host, nnz float64, all finite
+ *   index_base  0 or 1
+ *   flags       0 or CG_CHECK_SYMMETRY
+ * Errors: CG_ERR_ARG, CG_ERR_STRUCTURE (rules above; for CG_FMT_SYM_CSR every
+ * row must start with its diagonal), CG_ERR_NONFINITE, CG_ERR_NOMEM,
+ * CG_ERR_HIP, CG_ERR_UNSUPPORTED.  Blocks the host (planning and upload).
+ */
+int cg_create(cg_handle **out, int format, int64_t n, const int32_t *ptr, const int32_t *idx,
+              const double *vals, int index_base, uint32_t flags);
+
+/* Stream for all later work of the handle (a hipStream_t; NULL = the null
+ * stream).  Always stream-ordered with the caller's own work on it. */
+int cg_set_stream(cg_handle *h, void *hip_stream);
+
+/* Iterations captured per graph launch in cg_solve (default 32, 1..4096).
+ * Only affects scheduling, never the result. */
+int cg_set_batch(cg_handle *h, int32_t iters_per_launch);
+
+/*
+ * cg_solve -- CG from x0 to ||r||_2 <= tol ||b||_2 or maxit products.
+ *   b     device, n float64 (read only)
+ *   x     device, n float64: in x0, out the solution / last iterate.
+ *         Untouched on CG_ERR_ARG and CG_ERR_NONFINITE; set to 0 when b == 0.
+ *   tol   >= 0, relative to ||b||_2
+ *   maxit >= 0
+ *   info  may be NULL
+ * Returns CG_OK, CG_NOT_CONVERGED, CG_ERR_BREAKDOWN, CG_ERR_NONFINITE,
+ * CG_ERR_ARG or CG_ERR_HIP.  Blocks the host until the result is known; all
+ * device work runs on the handle's stream.
+ */
+int cg_solve(cg_handle *h, const double *b, double *x, double tol, int32_t maxit, cg_info *info);
+
+/* y = A x (device pointers, n float64 each, x and y must not overlap).
+ * Asynchronous on the handle's stream. */
+int cg_spmv(cg_handle *h, const double *x, double *y);
+
+/* Plan summary of a handle. */
+int cg_get_stats(const cg_handle *h, cg_plan_stats *stats);
+
+/* Frees every device and host resource of the handle (NULL is a no-op).
+ * Waits for the handle's outstanding work first. */
+void cg_destroy(cg_handle *h);
+
+/* Static text for a status code. */
+const char *cg_status_string(int status);
+
+/* Detail of the last error on h; with h == NULL, of the calling thread's last
+ * failed cg_create / cg_analyze.  Never NULL (empty string if none). */
+const char *cg_last_error(const cg_handle *h);
+
+/*
+ * Host-only planning, no GPU needed: validate the structure exactly as
+ * cg_create does and report the plan it would build.  vals may be NULL
+ * (then the finiteness check is skipped).  Same errors as cg_create.
+ */
+int cg_analyze(int format, int64_t n, const int32_t *ptr, const int32_t *idx, const double *vals,
+               int index_base, uint32_t flags, cg_plan_stats *stats);
+
+/*
+ * Host-only export of the scatter plan of CG_FMT_SYM_CSR / CG_FMT_CSC
+ * (colour of every block, its line and entry range, and its write slots),
+ * so the plan can be checked independently.  Arrays sized from cg_analyze:
+ *   blk_color, blk_line0, blk_line1      [spmv_blocks]  int32
+ *   blk_entry0, blk_entry1               [spmv_blocks]  int32 (0-based)
+ *   blk_slot0                            [spmv_blocks+1] int64: slots of block b
+ *                                        are [blk_slot0[b], blk_slot0[b+1])
+ *   slot_target                          [slots] int32: row of y written
+ *   slot_flags                           [slots] uint8: bit0 first writer of
+ *                                        that row, bit1 last writer
+ *   slot_count                           [slots] int32: products summed into it
+ * Returns CG_ERR_ARG for CG_FMT_CSR.
+ */
+int cg_analyze_export(int format, int64_t n, const int32_t *ptr, const int32_t *idx, int index_base,
+                      int32_t *blk_color, int32_t *blk_line0, int32_t *blk_line1, int32_t *blk_entry0,
+                      int32_t *blk_entry1, int64_t *blk_slot0, int32_t *slot_target, uint8_t *slot_flags,
+                      int32_t *slot_count);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CGMI_H */

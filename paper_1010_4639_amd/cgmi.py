@@ -1,0 +1,260 @@
+"""Python binding of libcgmi.so (ctypes; argument marshalling only).
+
+Every function of include/cgmi.h is exposed under the same name.  Device
+buffers are torch tensors on a ROCm device (float64, contiguous); their
+``data_ptr()`` is passed straight through, and the work is ordered on the
+caller's current torch stream.  Nothing here computes: if the library is not
+built, or a tensor is not on the GPU, the call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libcgmi.so")
+
+CG_FMT_CSR, CG_FMT_SYM_CSR, CG_FMT_CSC = 0, 1, 2
+FORMATS = {"csr": CG_FMT_CSR, "symcsr": CG_FMT_SYM_CSR, "csc": CG_FMT_CSC}
+CG_OK, CG_NOT_CONVERGED = 0, 1
+CG_ERR_ARG, CG_ERR_STRUCTURE, CG_ERR_BREAKDOWN, CG_ERR_NONFINITE = -1, -2, -3, -4
+CG_ERR_NOMEM, CG_ERR_HIP, CG_ERR_UNSUPPORTED = -5, -6, -7
+CG_CHECK_SYMMETRY = 1
+
+# every symbol declared in include/cgmi.h
+EXPORTS = ("cg_create", "cg_set_stream", "cg_set_batch", "cg_solve", "cg_spmv", "cg_get_stats", "cg_destroy",
+           "cg_status_string", "cg_last_error", "cg_analyze", "cg_analyze_export")
+
+
+class cg_info(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("status", ctypes.c_int32), ("relres", ctypes.c_double),
+                ("relres_true", ctypes.c_double), ("ms", ctypes.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class cg_plan_stats(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("nnz", ctypes.c_int64), ("format", ctypes.c_int32),
+                ("lanes_per_line", ctypes.c_int32), ("spmv_blocks", ctypes.c_int32),
+                ("vec_blocks", ctypes.c_int32), ("colors", ctypes.c_int32),
+                ("max_block_entries", ctypes.c_int32), ("slots", ctypes.c_int64),
+                ("plan_bytes", ctypes.c_int64)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class CgError(RuntimeError):
+    def __init__(self, status, detail):
+        super().__init__(f"{cg_status_string(status)} ({status}): {detail}")
+        self.status = status
+
+
+_lib = None
+_VP = ctypes.c_void_p
+
+
+def load():
+    """The loaded library; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                           "(there is no CPU fallback)")
+    # torch ships its own HIP runtime under the same soname (libamdhip64.so.7).
+    # Loading torch first makes the dynamic linker bind this library to that
+    # runtime, so the process has ONE HIP runtime and torch's device pointers
+    # and streams are valid handles here.  Loaded the other way round, two
+    # runtimes would compete for the device.
+    import torch  # noqa: F401
+    lib = ctypes.CDLL(LIB_PATH)
+    i32, i64, u32, dbl = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, ctypes.c_double
+    lib.cg_create.argtypes = [ctypes.POINTER(_VP), ctypes.c_int, i64, _VP, _VP, _VP, ctypes.c_int, u32]
+    lib.cg_set_stream.argtypes = [_VP, _VP]
+    lib.cg_set_batch.argtypes = [_VP, i32]
+    lib.cg_solve.argtypes = [_VP, _VP, _VP, dbl, i32, ctypes.POINTER(cg_info)]
+    lib.cg_spmv.argtypes = [_VP, _VP, _VP]
+    lib.cg_get_stats.argtypes = [_VP, ctypes.POINTER(cg_plan_stats)]
+    lib.cg_destroy.argtypes = [_VP]
+    lib.cg_destroy.restype = None
+    lib.cg_status_string.argtypes = [ctypes.c_int]
+    lib.cg_status_string.restype = ctypes.c_char_p
+    lib.cg_last_error.argtypes = [_VP]
+    lib.cg_last_error.restype = ctypes.c_char_p
+    lib.cg_analyze.argtypes = [ctypes.c_int, i64, _VP, _VP, _VP, ctypes.c_int, u32, ctypes.POINTER(cg_plan_stats)]
+    lib.cg_analyze_export.argtypes = [ctypes.c_int, i64, _VP, _VP, ctypes.c_int] + [_VP] * 9
+    for nm in ("cg_create", "cg_set_stream", "cg_set_batch", "cg_solve", "cg_spmv", "cg_get_stats",
+               "cg_analyze", "cg_analyze_export"):
+        getattr(lib, nm).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _np_ptr(a):
+    return None if a is None else a.ctypes.data_as(_VP)
+
+
+def _host_i32(a):
+    return None if a is None else np.ascontiguousarray(a, dtype=np.int32)
+
+
+def _host_f64(a):
+    return None if a is None else np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _dev(t, n, name):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a torch tensor on the GPU (no CPU fallback)")
+    if t.dtype != torch.float64 or not t.is_contiguous() or t.numel() != n:
+        raise TypeError(f"{name} must be a contiguous float64 tensor of {n} elements")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _fmt(fmt):
+    return FORMATS[fmt] if isinstance(fmt, str) else int(fmt)
+
+
+# ----------------------------------------------------------- C names
+def cg_status_string(status):
+    return load().cg_status_string(int(status)).decode()
+
+
+def cg_last_error(handle=None):
+    return load().cg_last_error(handle).decode()
+
+
+def cg_create(fmt, n, ptr, idx, vals, index_base=0, flags=0):
+    """Returns (status, handle or None).  ptr / idx / vals are host arrays."""
+    lib = load()
+    ptr, idx, vals = _host_i32(ptr), _host_i32(idx), _host_f64(vals)
+    h = _VP()
+    st = lib.cg_create(ctypes.byref(h), _fmt(fmt), int(n), _np_ptr(ptr), _np_ptr(idx), _np_ptr(vals),
+                       int(index_base), int(flags))
+    return st, (h if st == CG_OK else None)
+
+
+def cg_set_stream(handle, stream_ptr):
+    return load().cg_set_stream(handle, _VP(stream_ptr))
+
+
+def cg_set_batch(handle, iters):
+    return load().cg_set_batch(handle, int(iters))
+
+
+def cg_solve(handle, b_ptr, x_ptr, tol, maxit):
+    """Raw call on device addresses; returns (status, info dict)."""
+    info = cg_info()
+    st = load().cg_solve(handle, _VP(b_ptr), _VP(x_ptr), float(tol), int(maxit), ctypes.byref(info))
+    return st, info.as_dict()
+
+
+def cg_spmv(handle, x_ptr, y_ptr):
+    return load().cg_spmv(handle, _VP(x_ptr), _VP(y_ptr))
+
+
+def cg_get_stats(handle):
+    s = cg_plan_stats()
+    st = load().cg_get_stats(handle, ctypes.byref(s))
+    return st, s.as_dict()
+
+
+def cg_destroy(handle):
+    if handle:
+        load().cg_destroy(handle)
+
+
+def cg_analyze(fmt, n, ptr, idx, vals=None, index_base=0, flags=0):
+    """Host-only validation + plan summary: returns (status, stats dict)."""
+    ptr, idx, vals = _host_i32(ptr), _host_i32(idx), _host_f64(vals)
+    s = cg_plan_stats()
+    st = load().cg_analyze(_fmt(fmt), int(n), _np_ptr(ptr), _np_ptr(idx), _np_ptr(vals), int(index_base),
+                           int(flags), ctypes.byref(s))
+    return st, s.as_dict()
+
+
+def cg_analyze_export(fmt, n, ptr, idx, index_base=0):
+    """Host-only export of the scatter plan: returns (status, dict of arrays)."""
+    st, stats = cg_analyze(fmt, n, ptr, idx, None, index_base)
+    if st != CG_OK:
+        return st, None
+    nb, ns = stats["spmv_blocks"], stats["slots"]
+    out = dict(color=np.zeros(nb, np.int32), line0=np.zeros(nb, np.int32), line1=np.zeros(nb, np.int32),
+               entry0=np.zeros(nb, np.int32), entry1=np.zeros(nb, np.int32), slot0=np.zeros(nb + 1, np.int64),
+               target=np.zeros(ns, np.int32), flags=np.zeros(ns, np.uint8), count=np.zeros(ns, np.int32))
+    ptr, idx = _host_i32(ptr), _host_i32(idx)
+    st = load().cg_analyze_export(_fmt(fmt), int(n), _np_ptr(ptr), _np_ptr(idx), int(index_base),
+                                  *[_np_ptr(out[k]) for k in ("color", "line0", "line1", "entry0", "entry1",
+                                                              "slot0", "target", "flags", "count")])
+    out["stats"] = stats
+    return st, out
+
+
+# ------------------------------------------------------- convenience
+class Solver:
+    """A matrix on the device with its CG / SpMV entry points.
+
+    Solver(fmt, ptr, idx, vals): host arrays (numpy), fmt in {"csr",
+    "symcsr", "csc"} or CG_FMT_*.  solve(b, x0, tol, maxit) and spmv(x) take
+    and return float64 GPU tensors.
+    """
+
+    def __init__(self, fmt, ptr, idx, vals, index_base=0, flags=0, batch=None):
+        self.n = len(ptr) - 1
+        st, h = cg_create(fmt, self.n, ptr, idx, vals, index_base, flags)
+        if st != CG_OK:
+            raise CgError(st, cg_last_error(None))
+        self.h = h
+        if batch is not None:
+            cg_set_batch(h, batch)
+
+    def _stream(self):
+        import torch
+        cg_set_stream(self.h, torch.cuda.current_stream().cuda_stream)
+
+    def solve(self, b, x0=None, tol=1e-10, maxit=None, check=True):
+        import torch
+        x = torch.zeros_like(b) if x0 is None else x0.clone()
+        bp, xp = _dev(b, self.n, "b"), _dev(x, self.n, "x")
+        self._stream()
+        info = cg_info()
+        st = load().cg_solve(self.h, bp, xp, float(tol), int(self.n if maxit is None else maxit),
+                             ctypes.byref(info))
+        d = info.as_dict()
+        if check and st < 0 and st != CG_ERR_BREAKDOWN:
+            raise CgError(st, cg_last_error(self.h))
+        return x, d
+
+    def spmv(self, x, y=None):
+        import torch
+        if y is None:
+            y = torch.empty_like(x)
+        xp, yp = _dev(x, self.n, "x"), _dev(y, self.n, "y")
+        self._stream()
+        st = load().cg_spmv(self.h, xp, yp)
+        if st != CG_OK:
+            raise CgError(st, cg_last_error(self.h))
+        return y
+
+    def stats(self):
+        return cg_get_stats(self.h)[1]
+
+    def close(self):
+        if self.h:
+            cg_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

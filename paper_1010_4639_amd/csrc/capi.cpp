@@ -1,0 +1,505 @@
+// C-ABI of the cgmi library: handle lifetime, upload, the device-resident CG
+// driver and the host-only planning entry points.  Declared in include/cgmi.h.
+//
+// Solve schedule.  Initialisation (r0 = b - A x0, p0 = r0, ||b||, r0'r0) is
+// enqueued once; the iteration then runs from a HIP graph holding `batch`
+// iterations (product + fused p'q, r update + fused r'r, x/p update) and a
+// final convergence check.  All scalars stay on the device; every kernel
+// reads the device status at entry and returns at once when the loop has
+// stopped, so the host only looks at a 48-byte state copy after each graph
+// launch.  Two launches are kept in flight, so the GPU never waits for the
+// host; the extra launch issued after the stop costs only early returns.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <memory>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/cgmi.h"
+#include "kernels.h"
+#include "plan.h"
+
+using namespace cgmi;
+
+struct cg_handle {
+    Plan plan;
+    DevMatrix dm;
+    int device = 0;
+    hipStream_t stream = nullptr;  // caller's stream (null stream by default)
+    hipStream_t capture = nullptr; // private stream used only to record the graph
+    std::vector<void *> allocs;
+    double *r = nullptr, *p = nullptr, *q = nullptr, *xw = nullptr;
+    double *sig = nullptr, *sig_spmv = nullptr, *rho = nullptr, *bb = nullptr;
+    DevState *st = nullptr;
+    DevState *host_st = nullptr; // pinned, 2 entries
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    int batch = 32;
+    int graph_batch = 0;
+    std::string err;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+int hip_fail(std::string &err, hipError_t e, const char *what)
+{
+    err = std::string(what) + ": " + hipGetErrorString(e);
+    return e == hipErrorOutOfMemory ? CG_ERR_NOMEM : CG_ERR_HIP;
+}
+
+#define HIP_TRY(h, call)                                                                                           \
+    do {                                                                                                           \
+        hipError_t e_ = (call);                                                                                    \
+        if (e_ != hipSuccess)                                                                                      \
+            return hip_fail((h)->err, e_, #call);                                                                  \
+    } while (0)
+
+template <class T>
+int dalloc(cg_handle *h, T **out, size_t count)
+{
+    void *p = nullptr;
+    const size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess)
+        return hip_fail(h->err, e, "hipMalloc");
+    h->allocs.push_back(p);
+    *out = static_cast<T *>(p);
+    return CG_OK;
+}
+
+template <class T>
+int upload(cg_handle *h, T **out, const T *src, size_t count)
+{
+    int st = dalloc(h, out, count);
+    if (st != CG_OK)
+        return st;
+    if (count) {
+        hipError_t e = hipMemcpy(*out, src, count * sizeof(T), hipMemcpyHostToDevice);
+        if (e != hipSuccess)
+            return hip_fail(h->err, e, "hipMemcpy");
+    }
+    return CG_OK;
+}
+
+void release(cg_handle *h)
+{
+    if (h->gexec)
+        (void)hipGraphExecDestroy(h->gexec);
+    if (h->graph)
+        (void)hipGraphDestroy(h->graph);
+    for (auto &e : h->ev)
+        if (e)
+            (void)hipEventDestroy(e);
+    if (h->host_st)
+        (void)hipHostFree(h->host_st);
+    for (void *p : h->allocs)
+        (void)hipFree(p);
+    if (h->capture)
+        (void)hipStreamDestroy(h->capture);
+    h->allocs.clear();
+}
+
+int upload_all(cg_handle *h, const std::vector<int32_t> &ptr0, const std::vector<int32_t> &idx0, const double *vals)
+{
+    const Plan &p = h->plan;
+    DevMatrix &m = h->dm;
+    const int64_t n = p.n;
+    m.format = p.format;
+    m.n = (int)n;
+    m.lanes = p.lanes;
+    m.csr_blocks = p.csr_blocks;
+    m.csr_rows_per_block = p.csr_rows_per_block;
+    m.nblocks = p.nblocks;
+    m.ncolors = p.ncolors;
+    m.lds_entries = p.max_entries;
+    m.lds_lines = p.max_lines;
+    m.color_off = p.color_off;
+    m.vec_blocks = p.vec_blocks;
+    m.vec_chunk = p.vec_chunk;
+    int st;
+    int32_t *dptr, *didx;
+    double *dval;
+    if ((st = upload(h, &dptr, ptr0.data(), ptr0.size())) != CG_OK)
+        return st;
+    if ((st = upload(h, &didx, idx0.data(), idx0.size())) != CG_OK)
+        return st;
+    if ((st = upload(h, &dval, vals, idx0.size())) != CG_OK)
+        return st;
+    m.ptr = dptr;
+    m.idx = didx;
+    m.val = dval;
+    if (p.format != kCsr && n > 0) {
+        ScatterBlock *b;
+        int32_t *pb, *tg;
+        uint8_t *fl;
+        uint16_t *sg, *tl;
+        if ((st = upload(h, &b, p.blocks.data(), p.blocks.size())) != CG_OK ||
+            (st = upload(h, &pb, p.phase_blocks.data(), p.phase_blocks.size())) != CG_OK ||
+            (st = upload(h, &tg, p.slot_target.data(), p.slot_target.size())) != CG_OK ||
+            (st = upload(h, &fl, p.slot_flag.data(), p.slot_flag.size())) != CG_OK ||
+            (st = upload(h, &sg, p.seg.data(), p.seg.size())) != CG_OK ||
+            (st = upload(h, &tl, p.tl.data(), p.tl.size())) != CG_OK)
+            return st;
+        m.blocks = b;
+        m.phase_blocks = pb;
+        m.slot_target = tg;
+        m.slot_flag = fl;
+        m.seg = sg;
+        m.tl = tl;
+    }
+    const size_t nv = (size_t)std::max<int64_t>(n, 1);
+    if ((st = dalloc(h, &h->r, nv)) != CG_OK || (st = dalloc(h, &h->p, nv)) != CG_OK ||
+        (st = dalloc(h, &h->q, nv)) != CG_OK || (st = dalloc(h, &h->xw, nv)) != CG_OK)
+        return st;
+    const size_t ns = (size_t)std::max(1, std::max(p.spmv_blocks(), p.vec_blocks));
+    if ((st = dalloc(h, &h->sig, ns)) != CG_OK || (st = dalloc(h, &h->sig_spmv, ns)) != CG_OK ||
+        (st = dalloc(h, &h->rho, ns)) != CG_OK || (st = dalloc(h, &h->bb, ns)) != CG_OK ||
+        (st = dalloc(h, &h->st, 1)) != CG_OK)
+        return st;
+    hipError_t e = hipHostMalloc((void **)&h->host_st, 2 * sizeof(DevState), hipHostMallocDefault);
+    if (e != hipSuccess)
+        return hip_fail(h->err, e, "hipHostMalloc");
+    std::memset(h->host_st, 0, 2 * sizeof(DevState));
+    for (auto &ev : h->ev)
+        HIP_TRY(h, hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    HIP_TRY(h, hipStreamCreateWithFlags(&h->capture, hipStreamNonBlocking));
+    return CG_OK;
+}
+
+void fill_stats(const Plan &p, cg_plan_stats *s)
+{
+    std::memset(s, 0, sizeof(*s));
+    s->n = p.n;
+    s->nnz = p.nnz;
+    s->format = p.format;
+    s->lanes_per_line = p.lanes;
+    s->spmv_blocks = p.spmv_blocks();
+    s->vec_blocks = p.vec_blocks;
+    s->colors = p.ncolors;
+    s->max_block_entries = p.max_entries;
+    s->slots = (int64_t)p.slot_target.size();
+    s->plan_bytes = p.device_bytes();
+}
+
+int scatter_entries_override()
+{
+    const char *e = std::getenv("CGMI_SCATTER_ENTRIES");
+    return e ? std::atoi(e) : 0;
+}
+
+// One CG iteration on the handle's vectors, in CG (gated) mode.
+void enqueue_iteration(cg_handle *h, hipStream_t s)
+{
+    IterCtx c;
+    c.st = h->st;
+    c.rho_part = h->rho;
+    c.n_rho = h->dm.vec_blocks;
+    launch_spmv(h->dm, h->p, h->q, h->sig, c, s);
+    launch_update_r(h->dm, h->r, h->q, h->st, h->sig, h->rho, s);
+    launch_update_xp(h->dm, h->xw, h->p, h->r, h->st, h->rho, s);
+}
+
+int build_graph(cg_handle *h)
+{
+    if (h->gexec && h->graph_batch == h->batch)
+        return CG_OK;
+    if (h->gexec) {
+        (void)hipGraphExecDestroy(h->gexec);
+        h->gexec = nullptr;
+    }
+    if (h->graph) {
+        (void)hipGraphDestroy(h->graph);
+        h->graph = nullptr;
+    }
+    HIP_TRY(h, hipStreamBeginCapture(h->capture, hipStreamCaptureModeThreadLocal));
+    for (int i = 0; i < h->batch; ++i)
+        enqueue_iteration(h, h->capture);
+    launch_check(h->dm, h->st, h->rho, h->capture);
+    hipError_t e = hipStreamEndCapture(h->capture, &h->graph);
+    if (e != hipSuccess)
+        return hip_fail(h->err, e, "hipStreamEndCapture");
+    HIP_TRY(h, hipGraphInstantiate(&h->gexec, h->graph, nullptr, nullptr, 0));
+    h->graph_batch = h->batch;
+    return CG_OK;
+}
+
+int status_to_code(int32_t s)
+{
+    switch (s) {
+    case kConverged:
+    case kZeroRhs: return CG_OK;
+    case kMaxit: return CG_NOT_CONVERGED;
+    case kBreakdown: return CG_ERR_BREAKDOWN;
+    case kNonfinite: return CG_ERR_NONFINITE;
+    default: return CG_ERR_HIP;
+    }
+}
+
+} // namespace
+
+extern "C" {
+
+int cg_analyze(int format, int64_t n, const int32_t *ptr, const int32_t *idx, const double *vals, int index_base,
+               uint32_t flags, cg_plan_stats *stats)
+{
+    std::vector<int32_t> p0, i0;
+    std::string err;
+    int st;
+    try {
+        st = validate_and_normalise(format, n, ptr, idx, vals, index_base, flags, p0, i0, err);
+        if (st == CG_OK) {
+            Plan plan;
+            st = build_plan(format, n, p0.data(), i0.data(), scatter_entries_override(), plan, err);
+            if (st == CG_OK && stats)
+                fill_stats(plan, stats);
+        }
+    } catch (const std::bad_alloc &) {
+        err = "host allocation failed";
+        st = CG_ERR_NOMEM;
+    }
+    g_err = st == CG_OK ? std::string() : err;
+    return st;
+}
+
+int cg_analyze_export(int format, int64_t n, const int32_t *ptr, const int32_t *idx, int index_base,
+                      int32_t *blk_color, int32_t *blk_line0, int32_t *blk_line1, int32_t *blk_entry0,
+                      int32_t *blk_entry1, int64_t *blk_slot0, int32_t *slot_target, uint8_t *slot_flags,
+                      int32_t *slot_count)
+{
+    if (format == kCsr) {
+        g_err = "CSR has no scatter plan";
+        return CG_ERR_ARG;
+    }
+    std::vector<int32_t> p0, i0;
+    std::string err;
+    int st;
+    try {
+        st = validate_and_normalise(format, n, ptr, idx, nullptr, index_base, 0, p0, i0, err);
+        Plan plan;
+        if (st == CG_OK)
+            st = build_plan(format, n, p0.data(), i0.data(), scatter_entries_override(), plan, err);
+        if (st == CG_OK) {
+            for (int b = 0; b < plan.nblocks; ++b) {
+                const ScatterBlock &bk = plan.blocks[b];
+                if (blk_color) blk_color[b] = plan.block_color[b];
+                if (blk_line0) blk_line0[b] = bk.line0;
+                if (blk_line1) blk_line1[b] = bk.line1;
+                if (blk_entry0) blk_entry0[b] = bk.k0;
+                if (blk_entry1) blk_entry1[b] = bk.k1;
+                if (blk_slot0) blk_slot0[b] = bk.slot0;
+            }
+            if (blk_slot0) blk_slot0[plan.nblocks] = (int64_t)plan.slot_target.size();
+            const size_t ns = plan.slot_target.size();
+            if (slot_target) std::memcpy(slot_target, plan.slot_target.data(), ns * 4);
+            if (slot_flags) std::memcpy(slot_flags, plan.slot_flag.data(), ns);
+            if (slot_count) std::memcpy(slot_count, plan.slot_count.data(), ns * 4);
+        }
+    } catch (const std::bad_alloc &) {
+        err = "host allocation failed";
+        st = CG_ERR_NOMEM;
+    }
+    g_err = st == CG_OK ? std::string() : err;
+    return st;
+}
+
+int cg_create(cg_handle **out, int format, int64_t n, const int32_t *ptr, const int32_t *idx, const double *vals,
+              int index_base, uint32_t flags)
+{
+    if (!out) {
+        g_err = "out is NULL";
+        return CG_ERR_ARG;
+    }
+    *out = nullptr;
+    std::unique_ptr<cg_handle> h;
+    try {
+        h.reset(new cg_handle());
+        std::vector<int32_t> p0, i0;
+        int st = validate_and_normalise(format, n, ptr, idx, vals, index_base, flags, p0, i0, h->err);
+        if (st == CG_OK && n > 0 && p0[n] > 0 && !vals) {
+            h->err = "vals is NULL";
+            st = CG_ERR_ARG;
+        }
+        if (st == CG_OK)
+            st = build_plan(format, n, p0.data(), i0.data(), scatter_entries_override(), h->plan, h->err);
+        if (st == CG_OK) {
+            hipError_t e = hipGetDevice(&h->device);
+            st = e == hipSuccess ? upload_all(h.get(), p0, i0, vals) : hip_fail(h->err, e, "hipGetDevice");
+        }
+        if (st != CG_OK) {
+            g_err = h->err;
+            release(h.get());
+            return st;
+        }
+    } catch (const std::bad_alloc &) {
+        g_err = "host allocation failed";
+        if (h)
+            release(h.get());
+        return CG_ERR_NOMEM;
+    }
+    g_err.clear();
+    *out = h.release();
+    return CG_OK;
+}
+
+int cg_set_stream(cg_handle *h, void *hip_stream)
+{
+    if (!h)
+        return CG_ERR_ARG;
+    h->stream = static_cast<hipStream_t>(hip_stream);
+    return CG_OK;
+}
+
+int cg_set_batch(cg_handle *h, int32_t iters_per_launch)
+{
+    if (!h || iters_per_launch < 1 || iters_per_launch > 4096)
+        return CG_ERR_ARG;
+    h->batch = iters_per_launch;
+    return CG_OK;
+}
+
+int cg_spmv(cg_handle *h, const double *x, double *y)
+{
+    if (!h)
+        return CG_ERR_ARG;
+    if (h->dm.n == 0)
+        return CG_OK;
+    if (!x || !y || x == y) {
+        h->err = "x / y NULL or aliased";
+        return CG_ERR_ARG;
+    }
+    launch_spmv(h->dm, x, y, h->sig_spmv, IterCtx{}, h->stream);
+    HIP_TRY(h, hipGetLastError());
+    return CG_OK;
+}
+
+int cg_solve(cg_handle *h, const double *b, double *x, double tol, int32_t maxit, cg_info *info)
+{
+    const auto t0 = std::chrono::steady_clock::now();
+    cg_info loc{};
+    if (!info)
+        info = &loc;
+    std::memset(info, 0, sizeof(*info));
+    auto done = [&](int code) {
+        info->status = code;
+        info->ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        return code;
+    };
+    if (!h)
+        return done(CG_ERR_ARG);
+    if (!(tol >= 0.0) || maxit < 0) {
+        h->err = "tol must be >= 0 and maxit >= 0";
+        return done(CG_ERR_ARG);
+    }
+    const int n = h->dm.n;
+    if (n == 0)
+        return done(CG_OK);
+    if (!b || !x) {
+        h->err = "b / x NULL";
+        return done(CG_ERR_ARG);
+    }
+    hipStream_t s = h->stream;
+    int st = build_graph(h);
+    if (st != CG_OK)
+        return done(st);
+    // initialisation
+    launch_spmv(h->dm, x, h->q, h->sig_spmv, IterCtx{}, s);
+    launch_init_vec(h->dm, b, x, h->q, h->r, h->p, h->xw, h->rho, h->bb, s);
+    launch_init_state(h->dm, h->st, h->bb, h->rho, tol, maxit, s);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return done(hip_fail(h->err, e, "launch"));
+    // iteration: two graph launches in flight, poll the older one's state
+    auto launch = [&](int slot) -> hipError_t {
+        hipError_t r = hipGraphLaunch(h->gexec, s);
+        if (r == hipSuccess)
+            r = hipMemcpyAsync(&h->host_st[slot], h->st, sizeof(DevState), hipMemcpyDeviceToHost, s);
+        if (r == hipSuccess)
+            r = hipEventRecord(h->ev[slot], s);
+        return r;
+    };
+    if ((e = launch(0)) != hipSuccess)
+        return done(hip_fail(h->err, e, "hipGraphLaunch"));
+    int32_t status = kRun;
+    for (int i = 0;; ++i) {
+        if ((e = launch((i + 1) & 1)) != hipSuccess)
+            return done(hip_fail(h->err, e, "hipGraphLaunch"));
+        if ((e = hipEventSynchronize(h->ev[i & 1])) != hipSuccess)
+            return done(hip_fail(h->err, e, "hipEventSynchronize"));
+        status = h->host_st[i & 1].status;
+        if (status != kRun)
+            break;
+    }
+    // finish: copy x out, true residual of the returned x
+    if (status == kConverged || status == kMaxit || status == kBreakdown) {
+        e = hipMemcpyAsync(x, h->xw, sizeof(double) * (size_t)n, hipMemcpyDeviceToDevice, s);
+        if (e != hipSuccess)
+            return done(hip_fail(h->err, e, "hipMemcpyAsync"));
+        launch_spmv(h->dm, h->xw, h->q, h->sig_spmv, IterCtx{}, s);
+        launch_true_residual(h->dm, b, h->q, h->bb, h->st, s);
+    } else if (status == kZeroRhs) {
+        launch_fill(n, x, 0.0, s);
+    }
+    if ((e = hipMemcpyAsync(&h->host_st[0], h->st, sizeof(DevState), hipMemcpyDeviceToHost, s)) != hipSuccess ||
+        (e = hipStreamSynchronize(s)) != hipSuccess)
+        return done(hip_fail(h->err, e, "final state readback"));
+    const DevState &d = h->host_st[0];
+    info->iters = d.iters;
+    info->relres = d.nb > 0.0 ? std::sqrt(d.rho) / d.nb : 0.0;
+    info->relres_true = d.res_true;
+    if (d.status == kNonfinite) {
+        info->relres = 0.0;
+        h->err = "b has a non-finite entry";
+    } else if (d.status == kBreakdown) {
+        h->err = "p'Ap <= 0 or non-finite: matrix not SPD";
+    }
+    return done(status_to_code(d.status));
+}
+
+int cg_get_stats(const cg_handle *h, cg_plan_stats *stats)
+{
+    if (!h || !stats)
+        return CG_ERR_ARG;
+    fill_stats(h->plan, stats);
+    return CG_OK;
+}
+
+void cg_destroy(cg_handle *h)
+{
+    if (!h)
+        return;
+    (void)hipStreamSynchronize(h->stream);
+    release(h);
+    delete h;
+}
+
+const char *cg_status_string(int status)
+{
+    switch (status) {
+    case CG_OK: return "converged";
+    case CG_NOT_CONVERGED: return "maxit reached before tol";
+    case CG_ERR_ARG: return "invalid argument";
+    case CG_ERR_STRUCTURE: return "malformed sparse structure";
+    case CG_ERR_BREAKDOWN: return "breakdown: p'Ap <= 0 (matrix not SPD)";
+    case CG_ERR_NONFINITE: return "non-finite value";
+    case CG_ERR_NOMEM: return "out of memory";
+    case CG_ERR_HIP: return "HIP runtime error";
+    case CG_ERR_UNSUPPORTED: return "structure not supported by the scatter plan";
+    default: return "unknown status";
+    }
+}
+
+const char *cg_last_error(const cg_handle *h)
+{
+    return h ? h->err.c_str() : g_err.c_str();
+}
+
+} // extern "C"

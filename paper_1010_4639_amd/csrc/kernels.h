@@ -1,0 +1,92 @@
+// Device-side declarations shared by the kernels and the C-ABI driver.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <vector>
+
+#include "plan.h"
+
+namespace cgmi {
+
+// Iteration state kept in device memory.  Every kernel reads it at entry;
+// a field is only written by one thread (block 0, thread 0) of a kernel in
+// which no other block reads that field, so kernel boundaries are the only
+// synchronisation needed.
+enum DevStatus : int32_t {
+    kRun = 0,        // iterating
+    kConverged = 1,  // ||r|| <= tol ||b||
+    kMaxit = 2,      // maxit products done
+    kBreakdown = 3,  // p'Ap <= 0 or non-finite
+    kNonfinite = 4,  // ||b|| not finite
+    kZeroRhs = 5     // b == 0: x = 0
+};
+
+struct DevState {
+    int32_t status;
+    int32_t k;       // products Ap completed inside the loop
+    int32_t maxit;
+    int32_t iters;   // final count (set when the loop stops)
+    double tol_nb;   // tol * ||b||
+    double nb;       // ||b||
+    double rho;      // r'r of the current residual
+    double alpha;    // step of the current iteration
+    double sigma;    // p'Ap of the current iteration
+    double res_true; // ||b - A x|| / ||b|| (filled after the loop)
+};
+
+// Device image of a planned matrix.
+struct DevMatrix {
+    int format = 0;
+    int n = 0;
+    int lanes = 16;
+    const int32_t *ptr = nullptr;
+    const int32_t *idx = nullptr;
+    const double *val = nullptr;
+    // CSR
+    int csr_blocks = 0, csr_rows_per_block = 0;
+    // scatter
+    int nblocks = 0, ncolors = 0, lds_entries = 0, lds_lines = 0;
+    std::vector<int32_t> color_off; // host copy
+    const ScatterBlock *blocks = nullptr;
+    const int32_t *phase_blocks = nullptr;
+    const int32_t *slot_target = nullptr;
+    const uint8_t *slot_flag = nullptr;
+    const uint16_t *seg = nullptr;
+    const uint16_t *tl = nullptr;
+    // vectors
+    int vec_blocks = 0, vec_chunk = 0;
+    int spmv_blocks() const { return format == kCsr ? csr_blocks : nblocks; }
+};
+
+// Iteration context: null st = plain product (no gating, p'q partials still
+// written to sig_part).
+struct IterCtx {
+    DevState *st = nullptr;
+    const double *rho_part = nullptr;
+    int n_rho = 0;
+};
+
+// y = A x; writes spmv_blocks() partials of x'y into sig_part.
+void launch_spmv(const DevMatrix &m, const double *x, double *y, double *sig_part, const IterCtx &ctx,
+                 hipStream_t s);
+// r -= alpha q with alpha = rho / sum(sig_part); rho_part <- partials of r'r.
+void launch_update_r(const DevMatrix &m, double *r, const double *q, DevState *st, const double *sig_part,
+                     double *rho_part, hipStream_t s);
+// x += alpha p; p = r + beta p (unless converged) with beta = sum(rho_part) / rho.
+void launch_update_xp(const DevMatrix &m, double *x, double *p, const double *r, const DevState *st,
+                      const double *rho_part, hipStream_t s);
+// convergence / maxit test of the current residual (one workgroup).
+void launch_check(const DevMatrix &m, DevState *st, const double *rho_part, hipStream_t s);
+// r = b - q, p = r, xw = x0; partials of r'r and b'b.
+void launch_init_vec(const DevMatrix &m, const double *b, const double *x0, const double *q, double *r, double *p,
+                     double *xw, double *rho_part, double *bb_part, hipStream_t s);
+void launch_init_state(const DevMatrix &m, DevState *st, const double *bb_part, const double *rho_part, double tol,
+                       int32_t maxit, hipStream_t s);
+// res_true = ||b - q|| / ||b|| into st (two launches)
+void launch_true_residual(const DevMatrix &m, const double *b, const double *q, double *part, DevState *st,
+                          hipStream_t s);
+void launch_fill(int n, double *x, double v, hipStream_t s);
+
+} // namespace cgmi

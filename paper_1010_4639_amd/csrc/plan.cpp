@@ -1,0 +1,369 @@
+// Host planner: validation and the coloured scatter plan (see plan.h).
+#include "plan.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "../../include/cgmi.h"
+
+namespace cgmi {
+
+int64_t Plan::device_bytes() const
+{
+    if (format == kCsr)
+        return 0;
+    return (int64_t)blocks.size() * sizeof(ScatterBlock) + (int64_t)phase_blocks.size() * 4 +
+           (int64_t)slot_target.size() * 4 + (int64_t)slot_flag.size() + (int64_t)seg.size() * 2 +
+           (int64_t)tl.size() * 2;
+}
+
+int lanes_for_mean_length(double mean_len)
+{
+    int w = 4;
+    while (w < 64 && w < mean_len)
+        w *= 2;
+    return w;
+}
+
+int validate_and_normalise(int fmt, int64_t n, const int32_t *ptr, const int32_t *idx, const double *vals,
+                           int base, uint32_t flags, std::vector<int32_t> &ptr0, std::vector<int32_t> &idx0,
+                           std::string &err)
+{
+    if (fmt < 0 || fmt > 2) {
+        err = "unknown format";
+        return CG_ERR_ARG;
+    }
+    if (n < 0 || n > INT32_MAX - 1) {
+        err = "n out of range";
+        return CG_ERR_ARG;
+    }
+    if (base != 0 && base != 1) {
+        err = "index_base must be 0 or 1";
+        return CG_ERR_ARG;
+    }
+    ptr0.assign((size_t)n + 1, 0);
+    idx0.clear();
+    if (n == 0)
+        return CG_OK;
+    if (!ptr) {
+        err = "ptr is NULL";
+        return CG_ERR_ARG;
+    }
+    if (ptr[0] != base) {
+        err = "ptr[0] != index_base";
+        return CG_ERR_STRUCTURE;
+    }
+    for (int64_t i = 0; i < n; ++i)
+        if (ptr[i + 1] < ptr[i]) {
+            err = "ptr decreases at line " + std::to_string(i);
+            return CG_ERR_STRUCTURE;
+        }
+    const int64_t nnz = (int64_t)ptr[n] - base;
+    if (nnz > 0 && !idx) {
+        err = "idx is NULL";
+        return CG_ERR_ARG;
+    }
+    for (int64_t i = 0; i <= n; ++i)
+        ptr0[i] = ptr[i] - base;
+    idx0.resize((size_t)nnz);
+    for (int64_t l = 0; l < n; ++l) {
+        const int64_t b = ptr0[l], e = ptr0[l + 1];
+        for (int64_t k = b; k < e; ++k) {
+            const int64_t j = (int64_t)idx[k] - base;
+            if (j < 0 || j >= n) {
+                err = "index out of range at entry " + std::to_string(k);
+                return CG_ERR_STRUCTURE;
+            }
+            if (k > b && idx[k] <= idx[k - 1]) {
+                err = "indices not strictly increasing in line " + std::to_string(l);
+                return CG_ERR_STRUCTURE;
+            }
+            if (fmt == kSymCsr && k == b && j != l) {
+                err = "symmetric CSR row " + std::to_string(l) + " does not start with its diagonal";
+                return CG_ERR_STRUCTURE;
+            }
+            idx0[k] = (int32_t)j;
+        }
+        if (fmt == kSymCsr && e == b) {
+            err = "symmetric CSR row " + std::to_string(l) + " is empty";
+            return CG_ERR_STRUCTURE;
+        }
+    }
+    if (vals) {
+        for (int64_t k = 0; k < nnz; ++k)
+            if (!std::isfinite(vals[k])) {
+                err = "non-finite value at entry " + std::to_string(k);
+                return CG_ERR_NONFINITE;
+            }
+    }
+    if ((flags & CG_CHECK_SYMMETRY) && fmt != kSymCsr) {
+        // transpose by counting sort and compare entry by entry
+        std::vector<int32_t> tp((size_t)n + 1, 0), ti((size_t)nnz), src((size_t)nnz);
+        for (int64_t k = 0; k < nnz; ++k)
+            tp[idx0[k] + 1]++;
+        for (int64_t i = 0; i < n; ++i)
+            tp[i + 1] += tp[i];
+        std::vector<int32_t> next(tp.begin(), tp.end() - 1);
+        for (int64_t l = 0; l < n; ++l)
+            for (int64_t k = ptr0[l]; k < ptr0[l + 1]; ++k) {
+                const int32_t d = next[idx0[k]]++;
+                ti[d] = (int32_t)l;
+                src[d] = (int32_t)k;
+            }
+        for (int64_t i = 0; i <= n; ++i)
+            if (tp[i] != ptr0[i]) {
+                err = "matrix is not symmetric (pattern)";
+                return CG_ERR_STRUCTURE;
+            }
+        for (int64_t k = 0; k < nnz; ++k) {
+            if (ti[k] != idx0[k]) {
+                err = "matrix is not symmetric (pattern)";
+                return CG_ERR_STRUCTURE;
+            }
+            if (vals && std::memcmp(&vals[k], &vals[src[k]], sizeof(double)) != 0) {
+                err = "matrix is not symmetric (values)";
+                return CG_ERR_STRUCTURE;
+            }
+        }
+    }
+    return CG_OK;
+}
+
+static void plan_vectors(Plan &p)
+{
+    const int64_t n = p.n;
+    int64_t g = (n + 1023) / 1024;
+    g = std::max<int64_t>(1, std::min<int64_t>(g, kMaxVecBlocks));
+    p.vec_blocks = (int)g;
+    p.vec_chunk = (int)((n + g - 1) / g);
+}
+
+static void plan_csr(Plan &p)
+{
+    const int64_t n = p.n;
+    const int rows_per_pass = (kBlock / p.lanes) * 4; // 4 row tiles per lane group and pass
+    int64_t g = (n + rows_per_pass - 1) / rows_per_pass;
+    g = std::max<int64_t>(1, std::min<int64_t>(g, kMaxSpmvBlocks));
+    p.csr_blocks = (int)g;
+    p.csr_rows_per_block = (int)((n + g - 1) / g);
+}
+
+static int plan_scatter(Plan &p, const int32_t *ptr, const int32_t *idx, int target_entries, std::string &err)
+{
+    const int64_t n = p.n;
+    const bool sym = p.format == kSymCsr;
+    const int E = target_entries;
+
+    // 1. blocks: contiguous lines, <= E entries and <= kMaxBlockLines lines;
+    //    a line longer than E gets blocks of its own, E entries each
+    std::vector<ScatterBlock> &B = p.blocks;
+    B.clear();
+    auto push = [&](int64_t l0, int64_t l1, int64_t k0, int64_t k1) {
+        ScatterBlock b{};
+        b.line0 = (int32_t)l0;
+        b.line1 = (int32_t)l1;
+        b.k0 = (int32_t)k0;
+        b.k1 = (int32_t)k1;
+        b.id = (int32_t)B.size();
+        B.push_back(b);
+    };
+    {
+        int64_t l0 = 0;
+        for (int64_t l = 0; l < n; ++l) {
+            const int64_t len = (int64_t)ptr[l + 1] - ptr[l];
+            if (len > E) {
+                if (l > l0)
+                    push(l0, l, ptr[l0], ptr[l]);
+                for (int64_t k = ptr[l]; k < ptr[l + 1]; k += E)
+                    push(l, l + 1, k, std::min<int64_t>(k + E, ptr[l + 1]));
+                l0 = l + 1;
+                continue;
+            }
+            if (l > l0 && ((int64_t)ptr[l + 1] - ptr[l0] > E || l - l0 >= kMaxBlockLines)) {
+                push(l0, l, ptr[l0], ptr[l]);
+                l0 = l;
+            }
+        }
+        if (n > l0)
+            push(l0, n, ptr[l0], ptr[n]);
+    }
+    const int nb = (int)B.size();
+    p.nblocks = nb;
+
+    // 2. slots and contributions of every block; rows nobody writes are
+    //    attached to the block covering the same line index (they receive 0)
+    std::vector<int32_t> slot_of((size_t)n, -1);
+    std::vector<uint8_t> touched((size_t)n, 0);
+    std::vector<std::vector<int32_t>> targets(nb);
+    for (int b = 0; b < nb; ++b) {
+        const ScatterBlock &bk = B[b];
+        std::vector<int32_t> &t = targets[b];
+        if (sym) {
+            for (int32_t l = bk.line0; l < bk.line1; ++l)
+                t.push_back(l);
+            std::vector<int32_t> remote;
+            for (int64_t l = bk.line0; l < bk.line1; ++l) {
+                const int64_t s = std::max<int64_t>(ptr[l], bk.k0), e = std::min<int64_t>(ptr[l + 1], bk.k1);
+                for (int64_t k = s; k < e; ++k)
+                    if (idx[k] >= bk.line1)
+                        remote.push_back(idx[k]);
+            }
+            std::sort(remote.begin(), remote.end());
+            remote.erase(std::unique(remote.begin(), remote.end()), remote.end());
+            t.insert(t.end(), remote.begin(), remote.end());
+        } else {
+            for (int64_t k = bk.k0; k < bk.k1; ++k)
+                t.push_back(idx[k]);
+            std::sort(t.begin(), t.end());
+            t.erase(std::unique(t.begin(), t.end()), t.end());
+        }
+        for (int32_t r : t)
+            touched[r] = 1;
+    }
+    if (!sym) {
+        // a row with no entry at all (empty row of A) still needs y_i = 0
+        int b = 0;
+        for (int64_t r = 0; r < n; ++r) {
+            if (touched[r])
+                continue;
+            while (b + 1 < nb && B[b].line1 <= r)
+                ++b;
+            targets[b].push_back((int32_t)r);
+            touched[r] = 1;
+        }
+    }
+
+    // 3. greedy colouring in block order on the write-set conflict graph
+    std::vector<uint64_t> used((size_t)n, 0);
+    p.block_color.assign(nb, 0);
+    int ncol = 0;
+    for (int b = 0; b < nb; ++b) {
+        uint64_t forbid = 0;
+        for (int32_t r : targets[b])
+            forbid |= used[r];
+        if (forbid == ~0ull) {
+            err = "scatter plan needs more than 64 colours (a row shared by too many blocks); use CSR";
+            return CG_ERR_UNSUPPORTED;
+        }
+        int c = 0;
+        while (forbid & (1ull << c))
+            ++c;
+        p.block_color[b] = c;
+        ncol = std::max(ncol, c + 1);
+        for (int32_t r : targets[b])
+            used[r] |= 1ull << c;
+    }
+    p.ncolors = ncol;
+
+    // 4. slot arrays, FIRST / LAST flags, contributions (counting sort per block)
+    std::vector<int8_t> minc((size_t)n, 127), maxc((size_t)n, -1);
+    for (int b = 0; b < nb; ++b)
+        for (int32_t r : targets[b]) {
+            minc[r] = (int8_t)std::min<int>(minc[r], p.block_color[b]);
+            maxc[r] = (int8_t)std::max<int>(maxc[r], p.block_color[b]);
+        }
+    int64_t total_slots = 0, total_tl = 0;
+    for (int b = 0; b < nb; ++b) {
+        total_slots += (int64_t)targets[b].size();
+        total_tl += B[b].k1 - B[b].k0;
+    }
+    if (total_slots + nb + 1 >= INT32_MAX || total_tl >= INT32_MAX) {
+        err = "scatter plan too large for 32-bit offsets";
+        return CG_ERR_UNSUPPORTED;
+    }
+    p.slot_target.clear();
+    p.slot_flag.clear();
+    p.slot_count.clear();
+    p.seg.clear();
+    p.tl.clear();
+    p.slot_target.reserve(total_slots);
+    p.slot_flag.reserve(total_slots);
+    p.slot_count.reserve(total_slots);
+    p.seg.reserve(total_slots + nb);
+    p.tl.reserve(total_tl);
+    p.max_entries = 0;
+    p.max_lines = 0;
+    std::vector<int32_t> cnt;
+    for (int b = 0; b < nb; ++b) {
+        ScatterBlock &bk = B[b];
+        const std::vector<int32_t> &t = targets[b];
+        bk.slot0 = (int32_t)p.slot_target.size();
+        bk.nslots = (int32_t)t.size();
+        bk.tl0 = (int32_t)p.tl.size();
+        const int c = p.block_color[b];
+        for (size_t s = 0; s < t.size(); ++s) {
+            slot_of[t[s]] = (int32_t)s;
+            p.slot_target.push_back(t[s]);
+            uint8_t f = 0;
+            if (minc[t[s]] == c)
+                f |= kSlotFirst;
+            if (maxc[t[s]] == c)
+                f |= kSlotLast;
+            p.slot_flag.push_back(f);
+        }
+        // contributions: (slot, local entry) in ascending entry order
+        cnt.assign(t.size() + 1, 0);
+        auto for_each_contrib = [&](auto &&fn) {
+            for (int64_t l = bk.line0; l < bk.line1; ++l) {
+                const int64_t s = std::max<int64_t>(ptr[l], bk.k0), e = std::min<int64_t>(ptr[l + 1], bk.k1);
+                for (int64_t k = s; k < e; ++k) {
+                    if (sym && idx[k] == l)
+                        continue; // the diagonal has no mirror
+                    fn(slot_of[idx[k]], (int32_t)(k - bk.k0));
+                }
+            }
+        };
+        for_each_contrib([&](int32_t s, int32_t) { cnt[s + 1]++; });
+        for (size_t s = 0; s < t.size(); ++s)
+            cnt[s + 1] += cnt[s];
+        const size_t base = p.tl.size();
+        p.tl.resize(base + cnt[t.size()]);
+        for (size_t s = 0; s <= t.size(); ++s)
+            p.seg.push_back((uint16_t)cnt[s]);
+        for (size_t s = 0; s < t.size(); ++s)
+            p.slot_count.push_back(cnt[s + 1] - cnt[s]);
+        std::vector<int32_t> fill(cnt.begin(), cnt.end() - 1);
+        for_each_contrib([&](int32_t s, int32_t k) { p.tl[base + fill[s]++] = (uint16_t)k; });
+        for (int32_t r : t)
+            slot_of[r] = -1;
+        p.max_entries = std::max(p.max_entries, bk.k1 - bk.k0);
+        p.max_lines = std::max(p.max_lines, bk.line1 - bk.line0);
+    }
+
+    // 5. phase order: block ids sorted by colour, block order within a colour
+    p.color_off.assign(ncol + 1, 0);
+    for (int b = 0; b < nb; ++b)
+        p.color_off[p.block_color[b] + 1]++;
+    for (int c = 0; c < ncol; ++c)
+        p.color_off[c + 1] += p.color_off[c];
+    p.phase_blocks.assign(nb, 0);
+    std::vector<int32_t> pos(p.color_off.begin(), p.color_off.end() - 1);
+    for (int b = 0; b < nb; ++b)
+        p.phase_blocks[pos[p.block_color[b]]++] = b;
+    return CG_OK;
+}
+
+int build_plan(int fmt, int64_t n, const int32_t *ptr0, const int32_t *idx0, int target_entries, Plan &p,
+               std::string &err)
+{
+    p = Plan{};
+    p.format = fmt;
+    p.n = n;
+    p.nnz = n > 0 ? ptr0[n] : 0;
+    if (n == 0)
+        return CG_OK;
+    const double mean = (double)p.nnz / (double)n;
+    p.lanes = lanes_for_mean_length(mean);
+    plan_vectors(p);
+    if (fmt == kCsr) {
+        plan_csr(p);
+        return CG_OK;
+    }
+    if (target_entries <= 0)
+        target_entries = kDefaultScatterEntries;
+    target_entries = std::min(target_entries, kMaxScatterEntries);
+    return plan_scatter(p, ptr0, idx0, target_entries, err);
+}
+
+} // namespace cgmi

@@ -1,0 +1,78 @@
+// Host-side planning of the sparse product: structure validation, index-base
+// conversion, and the atomic-free scatter plan for the formats whose product
+// writes rows other than the one being read (symmetric CSR, CSC).
+//
+// Scatter plan.  The lines (rows of the stored triangle, or columns) are cut
+// into contiguous blocks of at most `target_entries` entries.  A block's write
+// set is the list of y rows it produces ("slots", sorted ascending); each slot
+// gets the list of the block's products that land on it ("contributions",
+// ascending entry order), so one workgroup can sum them in local memory with
+// no atomics and in a fixed order.  Blocks whose write sets intersect are
+// given different colours by a greedy pass in block order; the blocks of one
+// colour run as one kernel, colours one after another.  Every slot carries
+// two flags: FIRST (no earlier colour writes that row, so the block stores
+// instead of read-modify-write) and LAST (no later colour writes it, so the
+// block holds the final y_i and adds p_i y_i to the fused dot product).
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace cgmi {
+
+constexpr int kBlock = 256;             // threads per workgroup in every kernel
+constexpr int kDefaultScatterEntries = 2048;
+constexpr int kMaxScatterEntries = 6144;   // LDS: 8 B per entry + 8 B per line <= 56 KB
+constexpr int kMaxBlockLines = 1024;
+constexpr int kMaxColors = 64;
+constexpr int kMaxSpmvBlocks = 2048;    // CSR product workgroups (= dot partials)
+constexpr int kMaxVecBlocks = 1024;
+constexpr uint8_t kSlotFirst = 1;
+constexpr uint8_t kSlotLast = 2;
+
+enum Format { kCsr = 0, kSymCsr = 1, kCsc = 2 };
+
+struct ScatterBlock {
+    int32_t line0, line1;  // lines [line0, line1)
+    int32_t k0, k1;        // entries [k0, k1) (a line longer than the block limit is split)
+    int32_t slot0, nslots; // slots [slot0, slot0 + nslots); seg of this block starts at slot0 + id
+    int32_t tl0, id;       // contributions start; block id (index of its dot partial)
+};
+
+struct Plan {
+    int format = 0;
+    int64_t n = 0, nnz = 0;
+    int lanes = 16;                       // lanes sharing one line
+    // CSR
+    int csr_blocks = 0, csr_rows_per_block = 0;
+    // scatter formats
+    int nblocks = 0, ncolors = 0, max_entries = 0, max_lines = 0;
+    std::vector<ScatterBlock> blocks;     // by block id
+    std::vector<int32_t> color_off;       // ncolors + 1
+    std::vector<int32_t> phase_blocks;    // block ids ordered by colour (stable)
+    std::vector<int32_t> block_color;
+    std::vector<int32_t> slot_target;
+    std::vector<uint8_t> slot_flag;
+    std::vector<int32_t> slot_count;      // contributions per slot (export / checks only)
+    std::vector<uint16_t> seg;            // per block nslots + 1 local offsets into its contributions
+    std::vector<uint16_t> tl;             // local entry index (k - k0) of every contribution
+    // vector kernels
+    int vec_blocks = 0, vec_chunk = 0;
+
+    int spmv_blocks() const { return format == kCsr ? csr_blocks : nblocks; }
+    int64_t device_bytes() const;
+};
+
+// Validates (rules of cg_create) and returns 0-based copies.  vals may be null.
+int validate_and_normalise(int fmt, int64_t n, const int32_t *ptr, const int32_t *idx, const double *vals,
+                           int base, uint32_t flags, std::vector<int32_t> &ptr0, std::vector<int32_t> &idx0,
+                           std::string &err);
+
+// Builds the plan for 0-based arrays.  target_entries <= 0 selects the default.
+int build_plan(int fmt, int64_t n, const int32_t *ptr0, const int32_t *idx0, int target_entries, Plan &plan,
+               std::string &err);
+
+int lanes_for_mean_length(double mean_len);
+
+} // namespace cgmi

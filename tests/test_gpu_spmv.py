@@ -1,0 +1,154 @@
+"""GPU sparse products (CSR, symmetric CSR, CSC) through the C-ABI vs the oracle.
+
+Bar: |y_gpu,i - y_oracle,i| <= 1e-13 * sum_j |a_ij x_j| for every row, and
+||y_gpu - y_oracle|| <= 1e-13 ||y_oracle||.  (The rigorous bound for two
+different summation orders of m <= 15 terms is 2 gamma_15 ~ 3.3e-15, so the
+bar has a wide margin while still catching any dropped or duplicated term.)
+"""
+import numpy as np
+import pytest
+
+from paper_1010_4639_amd import cgmi
+from paper_1010_4639_amd import workload as W
+from tests.gpu_util import check_spmv, fem_cached, say, to_dev
+
+pytestmark = pytest.mark.gpu
+
+CSR, SYM, CSC = cgmi.CG_FMT_CSR, cgmi.CG_FMT_SYM_CSR, cgmi.CG_FMT_CSC
+
+
+def three_formats(s):
+    up, uc, uv = W.upper_triangle(s.rowptr, s.col, s.val)
+    return {CSR: (s.rowptr, s.col, s.val), SYM: (up, uc, uv), CSC: (s.rowptr, s.col, s.val)}
+
+
+@pytest.mark.parametrize("fmt", [CSR, SYM, CSC])
+def test_fem_small(fmt):
+    s = W.fem_p1_system(6, 5, 4, seed=11)
+    x = W.uniform_vector(s.n, seed=1)
+    check_spmv(fmt, *three_formats(s)[fmt], x, label="fem6x5x4")
+
+
+@pytest.mark.parametrize("fmt", [CSR, SYM, CSC])
+def test_fem_paper_sized(fmt):
+    s = fem_cached("fem32x32x30")
+    x = W.uniform_vector(s.n, seed=2)
+    check_spmv(fmt, *three_formats(s)[fmt], x, label="fem32x32x30")
+
+
+@pytest.mark.parametrize("fmt", [CSR, SYM, CSC])
+def test_fem_full_size_1m(fmt):
+    s = fem_cached("fem100")
+    x = W.uniform_vector(s.n, seed=3)
+    check_spmv(fmt, *three_formats(s)[fmt], x, label="fem100 (1.0M rows)")
+
+
+@pytest.mark.parametrize("fmt", [CSR, CSC])
+def test_ragged_nonsymmetric(fmt):
+    # empty rows/columns, lines far longer than a scatter block and than 64 lanes
+    ptr, col, val = W.random_sparse(3000, density=0.004, seed=4, empty_rows=60, long_rows=3, long_len=2900)
+    x = W.uniform_vector(3000, seed=5)
+    check_spmv(fmt, ptr, col, val, x, label="ragged")
+
+
+def test_csc_is_a_true_scatter():
+    # non-symmetric arrays read as CSC must give A x with A the column reading,
+    # which differs from the row reading of the same arrays
+    ptr, col, val = W.random_sparse(500, density=0.02, seed=6)
+    x = W.uniform_vector(500, seed=7)
+    y_csc, _ = check_spmv(CSC, ptr, col, val, x, label="csc")
+    y_csr, _ = check_spmv(CSR, ptr, col, val, x, label="csr")
+    assert np.linalg.norm(y_csc - y_csr) > 1e-3 * np.linalg.norm(y_csr)
+
+
+def test_sym_random_spd():
+    ptr, col, val = W.random_spd_sparse(2000, density=0.01, seed=8)
+    up, uc, uv = W.upper_triangle(ptr, col, val)
+    x = W.uniform_vector(2000, seed=9)
+    check_spmv(SYM, up, uc, uv, x, label="random spd")
+
+
+@pytest.mark.parametrize("entries", ["32", "200", "6144"])
+@pytest.mark.parametrize("fmt", [SYM, CSC])
+def test_scatter_block_sizes(monkeypatch, fmt, entries):
+    monkeypatch.setenv("CGMI_SCATTER_ENTRIES", entries)
+    s = W.fem_p1_system(14, 13, 12, seed=10)
+    x = W.uniform_vector(s.n, seed=11)
+    check_spmv(fmt, *three_formats(s)[fmt], x, label=f"entries={entries}")
+
+
+def test_split_long_row_symcsr(monkeypatch):
+    monkeypatch.setenv("CGMI_SCATTER_ENTRIES", "32")
+    n = 300
+    rows = [np.arange(n)] + [np.array([i, i + 1]) if i + 1 < n else np.array([i]) for i in range(1, n)]
+    ptr = np.zeros(n + 1, np.int32)
+    ptr[1:] = np.cumsum([len(r) for r in rows])
+    idx = np.concatenate(rows).astype(np.int32)
+    val = W.uniform_vector(len(idx), seed=12) + 3.0
+    check_spmv(SYM, ptr, idx, val, W.uniform_vector(n, seed=13), label="arrow")
+
+
+@pytest.mark.parametrize("mean_len", [2, 6, 30, 120])
+def test_lane_widths(mean_len):
+    n = 1500
+    ptr, col, val = W.random_sparse(n, density=mean_len / n, seed=mean_len)
+    st, stats = cgmi.cg_analyze(CSR, n, ptr, col, val)
+    say(f"lanes={stats['lanes_per_line']}")
+    check_spmv(CSR, ptr, col, val, W.uniform_vector(n, seed=14), label=f"mean_len={mean_len}")
+
+
+@pytest.mark.parametrize("fmt", [CSR, SYM, CSC])
+def test_one_based(fmt):
+    s = W.fem_p1_system(7, 6, 5, seed=15)
+    ptr, idx, val = three_formats(s)[fmt]
+    check_spmv(fmt, ptr + 1, idx + 1, val, W.uniform_vector(s.n, seed=16), base=1, label="1-based")
+
+
+@pytest.mark.parametrize("fmt", [CSR, SYM, CSC])
+def test_tiny_and_empty(fmt):
+    check_spmv(fmt, np.array([0, 1], np.int32), np.array([0], np.int32), np.array([2.5]), np.array([-3.0]),
+               label="1x1")
+    with cgmi.Solver(fmt, np.array([0], np.int32), np.zeros(0, np.int32), np.zeros(0)) as S:
+        assert S.n == 0
+        assert S.stats()["n"] == 0
+    if fmt != SYM:   # no entries at all: y = 0
+        n = 70
+        ptr = np.zeros(n + 1, np.int32)
+        y, _ = check_spmv(fmt, ptr, np.zeros(0, np.int32), np.zeros(0), W.uniform_vector(n, seed=17),
+                          label="all empty")
+        assert np.all(y == 0)
+
+
+@pytest.mark.parametrize("fmt", [CSR, SYM, CSC])
+def test_deterministic_and_stream_ordered(fmt):
+    import torch
+    s = W.fem_p1_system(20, 18, 16, seed=18)
+    arrs = three_formats(s)[fmt]
+    x = to_dev(W.uniform_vector(s.n, seed=19))
+    with cgmi.Solver(fmt, *arrs) as S:
+        y1 = S.spmv(x).clone()
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            y2 = S.spmv(x)
+            y3 = y2 * 1.0              # consumes y2 on the same stream
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        assert torch.equal(y1, y2) and torch.equal(y1, y3)
+
+
+def test_errors_without_fallback():
+    import torch
+    s = W.fem_p1_system(4, 4, 4, seed=20)
+    with cgmi.Solver(CSR, s.rowptr, s.col, s.val) as S:
+        with pytest.raises(TypeError):
+            S.spmv(torch.zeros(s.n, dtype=torch.float64))            # host tensor
+        with pytest.raises(TypeError):
+            S.spmv(torch.zeros(s.n, dtype=torch.float32, device="cuda"))
+        x = to_dev(np.ones(s.n))
+        assert cgmi.cg_spmv(S.h, x.data_ptr(), x.data_ptr()) == cgmi.CG_ERR_ARG   # aliased
+    for bad in [(CSR, s.rowptr, s.col[::-1].copy(), s.val), (SYM, s.rowptr, s.col, s.val)]:
+        st, h = cgmi.cg_create(bad[0], s.n, *bad[1:])
+        assert st == cgmi.CG_ERR_STRUCTURE and h is None
+    st, h = cgmi.cg_create(CSR, s.n, s.rowptr, s.col, np.full(s.nnz, np.inf))
+    assert st == cgmi.CG_ERR_NONFINITE and h is None

@@ -1,0 +1,187 @@
+"""Host logic of the HIP library, checked on the CPU (no GPU calls).
+
+* the shared library loads and exports every function include/cgmi.h declares;
+* cg_analyze validates exactly as the oracle does (same status per case);
+* the scatter plan (blocks, write slots, colours, first/last flags,
+  contribution counts) is re-derived here from the matrix and compared.
+"""
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1010_4639_amd import cgmi
+from paper_1010_4639_amd import workload as W
+from tests import pins
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    txt = open(os.path.join(ROOT, "include", "cgmi.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(cg_[a-z_]+)\s*\(", txt)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = cgmi.load()
+    declared = header_functions()
+    assert set(declared) == set(cgmi.EXPORTS)
+    for name in declared:
+        assert hasattr(lib, name), name
+
+
+def test_status_strings():
+    for st in (0, 1, -1, -2, -3, -4, -5, -6, -7):
+        assert cgmi.cg_status_string(st) != "unknown status"
+    assert cgmi.cg_status_string(99) == "unknown status"
+
+
+@pytest.mark.parametrize("case", pins.malformed_cases(), ids=lambda c: c[0])
+def test_validation_matches_oracle(case):
+    name, fmt, p, i, v, base, flags, want = case
+    st, _ = cgmi.cg_analyze(fmt, len(p) - 1, p, i, v, base, flags)
+    assert st == want == oracle.validate(fmt, p, i, v, base=base, flags=flags), (name, st)
+    if st != 0:
+        assert cgmi.cg_last_error(None) != ""
+
+
+def test_null_and_empty_arguments():
+    st, s = cgmi.cg_analyze(0, 0, None, None, None)
+    assert st == 0 and s["n"] == 0
+    st, _ = cgmi.cg_analyze(0, 3, None, None, None)
+    assert st == cgmi.CG_ERR_ARG
+    st, _ = cgmi.cg_analyze(0, -1, None, None, None)
+    assert st == cgmi.CG_ERR_ARG
+    st, _ = cgmi.cg_analyze(0, 2, np.array([0, 1, 2]), None, None)
+    assert st == cgmi.CG_ERR_ARG
+
+
+def test_csr_plan_shape():
+    s = W.fem_config("fem32x32x30")
+    st, stats = cgmi.cg_analyze(cgmi.CG_FMT_CSR, s.n, s.rowptr, s.col, s.val)
+    assert st == 0
+    assert stats["lanes_per_line"] == 16          # ~14.25 entries per row
+    assert stats["colors"] == 0 and stats["slots"] == 0
+    assert 1 <= stats["spmv_blocks"] <= 2048 and 1 <= stats["vec_blocks"] <= 1024
+
+
+def _expected_targets(fmt, ptr, idx, e0, e1, l0, l1):
+    rows = np.repeat(np.arange(len(ptr) - 1), np.diff(ptr))[e0:e1]
+    cols = idx[e0:e1]
+    if fmt == cgmi.CG_FMT_SYM_CSR:
+        off = cols != rows
+        contrib = cols[off]                        # mirror products land on column index
+        return set(range(l0, l1)) | set(contrib.tolist()), contrib
+    return set(cols.tolist()), cols
+
+
+def check_scatter_plan(fmt, ptr, idx):
+    n = len(ptr) - 1
+    st, P = cgmi.cg_analyze_export(fmt, n, ptr, idx)
+    assert st == 0, cgmi.cg_last_error(None)
+    nb = P["stats"]["spmv_blocks"]
+    assert P["stats"]["colors"] == P["color"].max() + 1
+    # blocks tile the lines and the entries contiguously (a long line may be split)
+    assert P["line0"][0] == 0 and P["line1"][-1] == n
+    assert P["entry0"][0] == 0 and P["entry1"][-1] == ptr[-1]
+    assert np.all(P["entry0"][1:] == P["entry1"][:-1])
+    assert np.all(P["line0"][1:] >= P["line0"][:-1]) and np.all(P["line1"] > P["line0"])
+    for b in range(nb):
+        assert ptr[P["line0"][b]] <= P["entry0"][b] and P["entry1"][b] <= ptr[P["line1"][b]]
+    writers = {}
+    for b in range(nb):
+        s0, s1 = P["slot0"][b], P["slot0"][b + 1]
+        tg = P["target"][s0:s1]
+        assert len(set(tg.tolist())) == len(tg), "duplicate slot in a block"
+        exp, contrib = _expected_targets(fmt, ptr, idx, P["entry0"][b], P["entry1"][b], P["line0"][b],
+                                         P["line1"][b])
+        extra = set(tg.tolist()) - exp
+        assert exp <= set(tg.tolist())
+        # extra slots only for rows that no entry at all writes (empty rows, CSC)
+        for r in extra:
+            assert fmt == cgmi.CG_FMT_CSC and not np.any(idx == r)
+        cnt = dict(zip(*np.unique(contrib, return_counts=True)))
+        for t, c in zip(tg, P["count"][s0:s1]):
+            assert c == cnt.get(t, 0)
+        for t in tg:
+            writers.setdefault(int(t), []).append(b)
+    assert set(writers) == set(range(n)), "a row of y is never written"
+    for t, bs in writers.items():
+        cols = [P["color"][b] for b in bs]
+        assert len(set(cols)) == len(cols), f"row {t} written twice in one colour"
+    # first / last writer flags
+    for b in range(nb):
+        s0, s1 = P["slot0"][b], P["slot0"][b + 1]
+        for t, f in zip(P["target"][s0:s1], P["flags"][s0:s1]):
+            cols = [P["color"][bb] for bb in writers[int(t)]]
+            assert bool(f & 1) == (P["color"][b] == min(cols))
+            assert bool(f & 2) == (P["color"][b] == max(cols))
+    return P
+
+
+def test_scatter_plan_fem_symcsr():
+    s = W.fem_p1_system(12, 10, 9, seed=3)
+    up, uc, _ = W.upper_triangle(s.rowptr, s.col, s.val)
+    P = check_scatter_plan(cgmi.CG_FMT_SYM_CSR, up, uc)
+    assert P["stats"]["colors"] <= 8
+
+
+def test_scatter_plan_fem_csc():
+    s = W.fem_p1_system(12, 10, 9, seed=3)
+    P = check_scatter_plan(cgmi.CG_FMT_CSC, s.rowptr, s.col)   # symmetric: CSC arrays == CSR arrays
+    assert P["stats"]["colors"] <= 8
+
+
+def test_scatter_plan_small_blocks_many_colours(monkeypatch):
+    monkeypatch.setenv("CGMI_SCATTER_ENTRIES", "64")
+    s = W.fem_p1_system(8, 7, 6, seed=4)
+    up, uc, _ = W.upper_triangle(s.rowptr, s.col, s.val)
+    P = check_scatter_plan(cgmi.CG_FMT_SYM_CSR, up, uc)
+    assert P["stats"]["spmv_blocks"] > 20 and P["stats"]["colors"] >= 2
+    check_scatter_plan(cgmi.CG_FMT_CSC, s.rowptr, s.col)
+
+
+def test_scatter_plan_ragged_nonsymmetric_csc(monkeypatch):
+    monkeypatch.setenv("CGMI_SCATTER_ENTRIES", "96")
+    ptr, col, val = W.random_sparse(300, density=0.03, seed=5, empty_rows=20, long_rows=2, long_len=250)
+    # read as CSC arrays: 2 columns of 250 entries (longer than a block), 20 empty columns
+    P = check_scatter_plan(cgmi.CG_FMT_CSC, ptr, col)
+    # the long columns are split over several blocks
+    assert np.any(P["line1"] - P["line0"] == 1)
+
+
+def _arrow_upper(n):
+    """Upper triangle of an arrow matrix: row 0 couples to every column,
+    the other rows to their right neighbour."""
+    rows = [np.arange(n)] + [np.array([i, i + 1]) if i + 1 < n else np.array([i]) for i in range(1, n)]
+    ptr = np.zeros(n + 1, np.int32)
+    ptr[1:] = np.cumsum([len(r) for r in rows])
+    return ptr, np.concatenate(rows).astype(np.int32)
+
+
+def test_scatter_plan_long_rows_symcsr(monkeypatch):
+    monkeypatch.setenv("CGMI_SCATTER_ENTRIES", "32")
+    up, uc = _arrow_upper(200)
+    P = check_scatter_plan(cgmi.CG_FMT_SYM_CSR, up, uc)
+    split = [b for b in range(P["stats"]["spmv_blocks"]) if P["line0"][b] == 0 and P["line1"][b] == 1]
+    assert len(split) == 7                         # 200 entries of row 0 in blocks of 32
+
+
+def test_scatter_plan_too_many_colours_is_an_error(monkeypatch):
+    monkeypatch.setenv("CGMI_SCATTER_ENTRIES", "32")
+    up, uc = _arrow_upper(4000)                   # 125 pieces of row 0 all write y_0
+    st, _ = cgmi.cg_analyze(cgmi.CG_FMT_SYM_CSR, 4000, up, uc)
+    assert st == cgmi.CG_ERR_UNSUPPORTED and "colours" in cgmi.cg_last_error(None)
+
+
+def test_one_based_input_same_plan():
+    s = W.fem_p1_system(6, 5, 4, seed=7)
+    up, uc, _ = W.upper_triangle(s.rowptr, s.col, s.val)
+    st0, P0 = cgmi.cg_analyze_export(cgmi.CG_FMT_SYM_CSR, s.n, up, uc, 0)
+    st1, P1 = cgmi.cg_analyze_export(cgmi.CG_FMT_SYM_CSR, s.n, up + 1, uc + 1, 1)
+    assert st0 == st1 == 0
+    for k in ("color", "target", "flags", "count", "slot0"):
+        assert np.array_equal(P0[k], P1[k])
