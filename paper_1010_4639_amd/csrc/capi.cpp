@@ -122,6 +122,7 @@ int upload_all(cg_handle *h, const std::vector<int32_t> &ptr0, const std::vector
     m.ncolors = p.ncolors;
     m.lds_entries = p.max_entries;
     m.lds_lines = p.max_lines;
+    m.max_slots = p.max_slots;
     m.color_off = p.color_off;
     m.vec_blocks = p.vec_blocks;
     m.vec_chunk = p.vec_chunk;
@@ -137,6 +138,14 @@ int upload_all(cg_handle *h, const std::vector<int32_t> &ptr0, const std::vector
     m.ptr = dptr;
     m.idx = didx;
     m.val = dval;
+    if (p.format == kCsr && p.csr_stream) {
+        int32_t *rb;
+        if ((st = upload(h, &rb, p.csr_rb.data(), p.csr_rb.size())) != CG_OK)
+            return st;
+        m.csr_stream = true;
+        m.csr_rb = rb;
+        m.csr_nrb = (int)p.csr_rb.size() - 1;
+    }
     if (p.format != kCsr && n > 0) {
         ScatterBlock *b;
         int32_t *pb, *tg;

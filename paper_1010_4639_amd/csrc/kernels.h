@@ -34,6 +34,9 @@ struct DevState {
     double alpha;    // step of the current iteration
     double sigma;    // p'Ap of the current iteration
     double res_true; // ||b - A x|| / ||b|| (filled after the loop)
+    double rho_next; // r'r after the latest r update (published for the next iteration's gate)
+    int32_t conv_next; // sqrt(rho_next) <= tol_nb
+    int32_t pad;
 };
 
 // Device image of a planned matrix.
@@ -46,8 +49,11 @@ struct DevMatrix {
     const double *val = nullptr;
     // CSR
     int csr_blocks = 0, csr_rows_per_block = 0;
+    bool csr_stream = false;
+    int csr_nrb = 0;
+    const int32_t *csr_rb = nullptr;
     // scatter
-    int nblocks = 0, ncolors = 0, lds_entries = 0, lds_lines = 0;
+    int nblocks = 0, ncolors = 0, lds_entries = 0, lds_lines = 0, max_slots = 0;
     std::vector<int32_t> color_off; // host copy
     const ScatterBlock *blocks = nullptr;
     const int32_t *phase_blocks = nullptr;
@@ -75,7 +81,7 @@ void launch_spmv(const DevMatrix &m, const double *x, double *y, double *sig_par
 void launch_update_r(const DevMatrix &m, double *r, const double *q, DevState *st, const double *sig_part,
                      double *rho_part, hipStream_t s);
 // x += alpha p; p = r + beta p (unless converged) with beta = sum(rho_part) / rho.
-void launch_update_xp(const DevMatrix &m, double *x, double *p, const double *r, const DevState *st,
+void launch_update_xp(const DevMatrix &m, double *x, double *p, const double *r, DevState *st,
                       const double *rho_part, hipStream_t s);
 // convergence / maxit test of the current residual (one workgroup).
 void launch_check(const DevMatrix &m, DevState *st, const double *rho_part, hipStream_t s);

@@ -60,16 +60,17 @@ __device__ __forceinline__ double reduce_partials(const double *__restrict__ par
 }
 
 // Start of an iteration (before its product): stop when the current residual
-// meets the tolerance or maxit products are done.  Every workgroup takes the
-// same decision from the same bits; only workgroup 0 records it.
-__device__ bool iter_gate(DevState *st, const double *__restrict__ rho_part, int n_rho, double *red)
+// meets the tolerance (decided and published by the previous x/p update, or by
+// the initialisation) or maxit products are done.  Every workgroup reads the
+// same state; only workgroup 0 records the decision.
+__device__ bool iter_gate(DevState *st)
 {
     if (st->status != kRun)
         return false;
-    const double rho = reduce_partials(rho_part, n_rho, red);
+    const double rho = st->rho_next;
     const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
     const int k = st->k;
-    if (sqrt(rho) <= st->tol_nb) {
+    if (st->conv_next) {
         if (lead) {
             st->rho = rho;
             st->iters = k;
@@ -104,7 +105,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv_csr(int n, int rows_per_block, 
                                                      const double *__restrict__ rho_part, int n_rho)
 {
     __shared__ double red[kWaves];
-    if (st != nullptr && !iter_gate(st, rho_part, n_rho, red))
+    if (st != nullptr && !iter_gate(st))
         return;
     constexpr int NG = kBlock / W;
     const int blk = xcd_remap(blockIdx.x, gridDim.x);
@@ -165,83 +166,212 @@ __global__ __launch_bounds__(kBlock) void k_spmv_csr(int n, int rows_per_block, 
         sig_part[blk] = sig;
 }
 
+// ------------------------------------------------- CSR row blocks
+// Short rows (the FEM case): a workgroup takes a contiguous range of row
+// blocks (<= 256 rows, <= 2048 entries each).  For each block every thread
+// first issues its 8 index / value loads (fully coalesced, non-temporal) and
+// then the 8 gathers of x, parks the products in LDS, and after one barrier
+// each row is summed left to right by one thread -- the same order as the
+// textbook loop, so y is bit-identical to a serial row-by-row product.  A row
+// longer than a block is summed by the whole workgroup (fixed tree).
+__global__ __launch_bounds__(kBlock) void k_spmv_csr_rows(int nrb, const int32_t *__restrict__ rb_row,
+                                                          const int32_t *__restrict__ ptr,
+                                                          const int32_t *__restrict__ col,
+                                                          const double *__restrict__ val,
+                                                          const double *__restrict__ x, double *__restrict__ y,
+                                                          double *__restrict__ sig_part, DevState *st,
+                                                          const double *__restrict__ rho_part, int n_rho)
+{
+    constexpr int E = kStreamPerThread;
+    __shared__ double prod[kStreamEntries];
+    __shared__ int32_t lptr[kStreamRows + 1];
+    __shared__ double red[kWaves];
+    if (st != nullptr && !iter_gate(st))
+        return;
+    const int wg = xcd_remap(blockIdx.x, gridDim.x);
+    const int b0 = (int)((int64_t)wg * nrb / gridDim.x);
+    const int b1 = (int)((int64_t)(wg + 1) * nrb / gridDim.x);
+    const int t = threadIdx.x;
+    double sig = 0.0;
+    for (int b = b0; b < b1; ++b) {
+        const int r0 = rb_row[b], r1 = rb_row[b + 1];
+        const int nr = r1 - r0;
+        const int e0 = ptr[r0], e1 = ptr[r1];
+        if (e1 - e0 > kStreamEntries) { // one long row
+            double a = 0.0;
+            for (int e = e0 + t; e < e1; e += kBlock)
+                a = fma(__builtin_nontemporal_load(val + e), x[__builtin_nontemporal_load(col + e)], a);
+            a = block_sum(a, red);
+            if (t == 0) {
+                y[r0] = a;
+                sig = fma(x[r0], a, sig);
+            }
+            continue;
+        }
+        int c[E];
+        double v[E];
+#pragma unroll
+        for (int m = 0; m < E; ++m) {
+            const int e = e0 + t + m * kBlock;
+            const bool ok = e < e1;
+            c[m] = ok ? __builtin_nontemporal_load(col + e) : -1;
+            v[m] = ok ? __builtin_nontemporal_load(val + e) : 0.0;
+        }
+        if (t < nr)
+            lptr[t + 1] = __builtin_nontemporal_load(ptr + r0 + t + 1) - e0;
+        if (t == 0)
+            lptr[0] = 0;
+#pragma unroll
+        for (int m = 0; m < E; ++m)
+            if (c[m] >= 0)
+                prod[t + m * kBlock] = v[m] * x[c[m]];
+        __syncthreads();
+        if (t < nr) {
+            double a = 0.0;
+            const int k1 = lptr[t + 1];
+            for (int k = lptr[t]; k < k1; ++k)
+                a += prod[k];
+            y[r0 + t] = a;
+            sig = fma(x[r0 + t], a, sig);
+        }
+        __syncthreads();
+    }
+    sig = block_sum(sig, red);
+    if (t == 0)
+        sig_part[wg] = sig;
+}
+
 // --------------------------------------------------- colour-phase scatter
-// One workgroup per scatter block (see plan.h).  Stage 1: lane groups walk
-// the block's lines; every product bound for another row is parked in LDS at
-// its entry's local index (symmetric CSR also gathers its own row, incl. the
-// diagonal, in registers).  Stage 2: one thread per write slot sums that
-// slot's products in the fixed order of the plan and stores (first writer) or
-// adds to (later colour) y; the last writer of a row adds p_i y_i to the dot.
-template <bool SYM, int W>
+// One workgroup per scatter block (plan.h), one launch per colour.  Every
+// global load that does not depend on another is issued first: the block's
+// line pointers, x of its own lines, its contribution list (-> LDS), its
+// <= 2048 index / value pairs (8 per thread, coalesced, non-temporal) and its
+// write-slot descriptors (SU per thread).  Then the gathers (x at the column
+// indices for the symmetric row part; y and x at the slot targets), then all
+// arithmetic from LDS:
+//   sp[e] = a_e x_line(e)   product bound for another row (mirror / column)
+//   gp[e] = a_e x_idx(e)    symmetric CSR: product of the stored row itself
+// and one thread per slot sums its products in the plan's order and stores
+// (first writer of that row) or adds (later colour) y; the last writer adds
+// x_i y_i to the workgroup's dot partial.  No atomics.
+template <bool SYM, int SU>
 __global__ __launch_bounds__(kBlock) void k_spmv_scatter(
     const int32_t *__restrict__ ptr, const int32_t *__restrict__ idx, const double *__restrict__ val,
     const double *__restrict__ x, double *__restrict__ y, double *__restrict__ sig_part,
     const ScatterBlock *__restrict__ blocks, const int32_t *__restrict__ phase_blocks,
     const int32_t *__restrict__ slot_target, const uint8_t *__restrict__ slot_flag,
-    const uint16_t *__restrict__ seg, const uint16_t *__restrict__ tl, int lds_entries, DevState *st,
-    const double *__restrict__ rho_part, int n_rho, int gate)
+    const uint16_t *__restrict__ seg, const uint16_t *__restrict__ tl, int lds_entries, int lds_lines,
+    DevState *st, int gate)
 {
+    constexpr int E = kMaxScatterEntries / kBlock; // entries per thread
     extern __shared__ double lds[];
     __shared__ double red[kWaves];
     if (st != nullptr) {
-        if (gate) {
-            if (!iter_gate(st, rho_part, n_rho, red))
-                return;
-        } else if (st->status != kRun) {
+        if (gate ? !iter_gate(st) : st->status != kRun)
             return;
-        }
     }
     const ScatterBlock bk = blocks[phase_blocks[xcd_remap(blockIdx.x, gridDim.x)]];
     double *sp = lds;
-    double *gs = lds + lds_entries;
-    constexpr int NG = kBlock / W;
-    const int g = threadIdx.x / W, lane = threadIdx.x % W;
-    for (int l = bk.line0 + g; l < bk.line1; l += NG) {
-        const int s = max(ptr[l], bk.k0), e = min(ptr[l + 1], bk.k1);
-        const double xl = x[l];
-        double ga = 0.0;
-        for (int k = s + lane; k < e; k += W) {
-            const int j = __builtin_nontemporal_load(idx + k);
-            const double v = __builtin_nontemporal_load(val + k);
+    double *gp = sp + lds_entries;
+    double *xl = gp + (SYM ? lds_entries : 0);
+    int32_t *lp = reinterpret_cast<int32_t *>(xl + lds_lines);
+    uint16_t *lm = reinterpret_cast<uint16_t *>(lp + lds_lines + 1);
+    uint16_t *tv = lm + lds_entries;
+    const int t = threadIdx.x;
+    const int nl = bk.line1 - bk.line0, ne = bk.k1 - bk.k0;
+
+    // ---- independent loads
+    for (int l = t; l <= nl; l += kBlock)
+        lp[l] = min(max(ptr[bk.line0 + l] - bk.k0, 0), ne);
+    for (int l = t; l < nl; l += kBlock)
+        xl[l] = x[bk.line0 + l];
+    for (int i = t; i < bk.ntl; i += kBlock)
+        tv[i] = tl[bk.tl0 + i];
+    int c[E];
+    double v[E];
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+        const int e = t + m * kBlock;
+        const bool ok = e < ne;
+        c[m] = ok ? __builtin_nontemporal_load(idx + bk.k0 + e) : -1;
+        v[m] = ok ? __builtin_nontemporal_load(val + bk.k0 + e) : 0.0;
+    }
+    int tg[SU], lo[SU], hi[SU];
+    unsigned fl[SU];
+    const uint16_t *sg = seg + bk.slot0 + bk.id;
+#pragma unroll
+    for (int u = 0; u < SU; ++u) {
+        const int s = t + u * kBlock;
+        const bool ok = s < bk.nslots;
+        tg[u] = ok ? slot_target[bk.slot0 + s] : -1;
+        fl[u] = ok ? slot_flag[bk.slot0 + s] : 0u;
+        lo[u] = ok ? sg[s] : 0;
+        hi[u] = ok ? sg[s + 1] : 0;
+    }
+    // ---- gathers
+    double xg[E];
+    if (SYM) {
+#pragma unroll
+        for (int m = 0; m < E; ++m)
+            xg[m] = c[m] >= 0 ? x[c[m]] : 0.0;
+    }
+    double yo[SU], xt[SU];
+#pragma unroll
+    for (int u = 0; u < SU; ++u) {
+        yo[u] = (tg[u] >= 0 && !(fl[u] & kSlotFirst)) ? y[tg[u]] : 0.0;
+        xt[u] = (tg[u] >= 0 && (fl[u] & kSlotLast)) ? x[tg[u]] : 0.0;
+    }
+    __syncthreads();
+    // ---- line of every entry
+    for (int l = t; l < nl; l += kBlock)
+        for (int k = lp[l]; k < lp[l + 1]; ++k)
+            lm[k] = (uint16_t)l;
+    __syncthreads();
+    // ---- products
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+        const int e = t + m * kBlock;
+        if (c[m] >= 0) {
+            const int l = lm[e];
             if (SYM) {
-                ga = fma(v, x[j], ga);
-                if (j != l)
-                    sp[k - bk.k0] = v * xl;
+                gp[e] = v[m] * xg[m];
+                if (c[m] != bk.line0 + l)
+                    sp[e] = v[m] * xl[l];
             } else {
-                sp[k - bk.k0] = v * xl;
+                sp[e] = v[m] * xl[l];
             }
-        }
-        if (SYM) {
-            ga = group_sum<W>(ga);
-            if (lane == 0)
-                gs[l - bk.line0] = ga;
         }
     }
     __syncthreads();
-    const int nown = SYM ? bk.line1 - bk.line0 : 0;
-    const uint16_t *sg = seg + bk.slot0 + bk.id;
-    const uint16_t *tt = tl + bk.tl0;
-    const int32_t *tg = slot_target + bk.slot0;
-    const uint8_t *fl = slot_flag + bk.slot0;
+    // ---- write slots
     double sig = 0.0;
-    for (int s = threadIdx.x; s < bk.nslots; s += kBlock) {
-        double a = s < nown ? gs[s] : 0.0;
-        const int t0 = sg[s], t1 = sg[s + 1];
-        for (int t = t0; t < t1; ++t)
-            a += sp[tt[t]];
-        const int row = tg[s];
-        const unsigned f = fl[s];
-        const double yv = (f & kSlotFirst) ? a : y[row] + a;
-        y[row] = yv;
-        if (f & kSlotLast)
-            sig = fma(x[row], yv, sig);
+#pragma unroll
+    for (int u = 0; u < SU; ++u) {
+        if (tg[u] < 0)
+            continue;
+        const int s = t + u * kBlock;
+        double a = 0.0;
+        if (SYM && s < nl) // own row: its stored entries, left to right
+            for (int k = lp[s]; k < lp[s + 1]; ++k)
+                a += gp[k];
+        for (int i = lo[u]; i < hi[u]; ++i)
+            a += sp[tv[i]];
+        const double yv = (fl[u] & kSlotFirst) ? a : yo[u] + a;
+        y[tg[u]] = yv;
+        if (fl[u] & kSlotLast)
+            sig = fma(xt[u], yv, sig);
     }
     sig = block_sum(sig, red);
-    if (threadIdx.x == 0)
+    if (t == 0)
         sig_part[bk.id] = sig;
 }
 
 // ------------------------------------------------------ vector kernels
+// Each workgroup owns a contiguous chunk (XCD-remapped).  The first kPre
+// elements per thread are loaded before the dot partials of the previous
+// kernel are reduced, so the two memory round trips overlap.
+constexpr int kPre = 4;
+
 __global__ __launch_bounds__(kBlock) void k_update_r(int n, int chunk, double *__restrict__ r,
                                                      const double *__restrict__ q, DevState *st,
                                                      const double *__restrict__ sig_part, int n_sig,
@@ -250,8 +380,18 @@ __global__ __launch_bounds__(kBlock) void k_update_r(int n, int chunk, double *_
     __shared__ double red[kWaves];
     if (st->status != kRun)
         return;
+    const int blk = xcd_remap(blockIdx.x, gridDim.x);
+    const int i0 = blk * chunk, i1 = min(n, i0 + chunk);
+    const int t = threadIdx.x;
+    double qv[kPre], rv[kPre];
+#pragma unroll
+    for (int u = 0; u < kPre; ++u) {
+        const int i = i0 + t + u * kBlock;
+        qv[u] = i < i1 ? q[i] : 0.0;
+        rv[u] = i < i1 ? r[i] : 0.0;
+    }
     const double sigma = reduce_partials(sig_part, n_sig, red);
-    const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
+    const bool lead = blockIdx.x == 0 && t == 0;
     if (!(sigma > 0.0) || !isfinite(sigma)) {
         if (lead) {
             st->iters = st->k;
@@ -266,34 +406,67 @@ __global__ __launch_bounds__(kBlock) void k_update_r(int n, int chunk, double *_
         st->sigma = sigma;
         st->k = st->k + 1;
     }
-    const int blk = xcd_remap(blockIdx.x, gridDim.x);
-    const int i0 = blk * chunk, i1 = min(n, i0 + chunk);
     double acc = 0.0;
-    for (int i = i0 + threadIdx.x; i < i1; i += kBlock) {
+#pragma unroll
+    for (int u = 0; u < kPre; ++u) {
+        const int i = i0 + t + u * kBlock;
+        if (i < i1) {
+            const double ri = fma(-alpha, qv[u], rv[u]);
+            r[i] = ri;
+            acc = fma(ri, ri, acc);
+        }
+    }
+    for (int i = i0 + t + kPre * kBlock; i < i1; i += kBlock) {
         const double ri = fma(-alpha, q[i], r[i]);
         r[i] = ri;
         acc = fma(ri, ri, acc);
     }
     acc = block_sum(acc, red);
-    if (threadIdx.x == 0)
+    if (t == 0)
         rho_part[blk] = acc;
 }
 
+// x += alpha p and p = r + beta p; workgroup 0 publishes r'r and the
+// convergence decision for the next iteration's gate (no workgroup of this
+// kernel reads those two fields).
 __global__ __launch_bounds__(kBlock) void k_update_xp(int n, int chunk, double *__restrict__ x,
                                                       double *__restrict__ p, const double *__restrict__ r,
-                                                      const DevState *st, const double *__restrict__ rho_part,
+                                                      DevState *st, const double *__restrict__ rho_part,
                                                       int n_rho)
 {
     __shared__ double red[kWaves];
     if (st->status != kRun)
         return;
+    const int blk = xcd_remap(blockIdx.x, gridDim.x);
+    const int i0 = blk * chunk, i1 = min(n, i0 + chunk);
+    const int t = threadIdx.x;
+    double pv[kPre], xv[kPre], rv[kPre];
+#pragma unroll
+    for (int u = 0; u < kPre; ++u) {
+        const int i = i0 + t + u * kBlock;
+        const bool ok = i < i1;
+        pv[u] = ok ? p[i] : 0.0;
+        xv[u] = ok ? x[i] : 0.0;
+        rv[u] = ok ? r[i] : 0.0;
+    }
     const double rho_new = reduce_partials(rho_part, n_rho, red);
     const double alpha = st->alpha;
     const double beta = rho_new / st->rho;
     const bool conv = sqrt(rho_new) <= st->tol_nb; // last step: x only
-    const int blk = xcd_remap(blockIdx.x, gridDim.x);
-    const int i0 = blk * chunk, i1 = min(n, i0 + chunk);
-    for (int i = i0 + threadIdx.x; i < i1; i += kBlock) {
+    if (blockIdx.x == 0 && t == 0) {
+        st->rho_next = rho_new;
+        st->conv_next = conv ? 1 : 0;
+    }
+#pragma unroll
+    for (int u = 0; u < kPre; ++u) {
+        const int i = i0 + t + u * kBlock;
+        if (i < i1) {
+            x[i] = fma(alpha, pv[u], xv[u]);
+            if (!conv)
+                p[i] = fma(beta, pv[u], rv[u]);
+        }
+    }
+    for (int i = i0 + t + kPre * kBlock; i < i1; i += kBlock) {
         const double pi = p[i];
         x[i] = fma(alpha, pi, x[i]);
         if (!conv)
@@ -301,10 +474,9 @@ __global__ __launch_bounds__(kBlock) void k_update_xp(int n, int chunk, double *
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k_check(DevState *st, const double *__restrict__ rho_part, int n_rho)
+__global__ __launch_bounds__(kBlock) void k_check(DevState *st)
 {
-    __shared__ double red[kWaves];
-    iter_gate(st, rho_part, n_rho, red);
+    iter_gate(st);
 }
 
 __global__ __launch_bounds__(kBlock) void k_init_vec(int n, int chunk, const double *__restrict__ b,
@@ -351,6 +523,8 @@ __global__ __launch_bounds__(kBlock) void k_init_state(DevState *st, const doubl
         st->sigma = 0.0;
         st->res_true = 0.0;
         st->tol_nb = tol * nb;
+        st->rho_next = rho;
+        st->conv_next = sqrt(rho) <= tol * nb ? 1 : 0;
         st->status = !isfinite(nb) ? kNonfinite : (nb == 0.0 ? kZeroRhs : kRun);
     }
 }
@@ -393,28 +567,31 @@ void csr_launch(const DevMatrix &m, const double *x, double *y, double *sig, con
                        m.ptr, m.idx, m.val, x, y, sig, c.st, c.rho_part, c.n_rho);
 }
 
-template <bool SYM, int W>
+template <bool SYM, int SU>
 void scatter_launch(const DevMatrix &m, const double *x, double *y, double *sig, const IterCtx &c, hipStream_t s)
 {
-    const size_t lds = (size_t)(m.lds_entries + m.lds_lines) * sizeof(double);
+    const size_t E = (size_t)m.lds_entries, R = (size_t)m.lds_lines;
+    const size_t lds = E * 8 * (SYM ? 2 : 1) + R * 8 + (R + 1) * 4 + 2 * E * 2;
     for (int col = 0; col < m.ncolors; ++col) {
         const int nb = m.color_off[col + 1] - m.color_off[col];
-        hipLaunchKernelGGL((k_spmv_scatter<SYM, W>), dim3(nb), dim3(kBlock), lds, s, m.ptr, m.idx, m.val, x, y,
+        hipLaunchKernelGGL((k_spmv_scatter<SYM, SU>), dim3(nb), dim3(kBlock), lds, s, m.ptr, m.idx, m.val, x, y,
                            sig, m.blocks, m.phase_blocks + m.color_off[col], m.slot_target, m.slot_flag, m.seg,
-                           m.tl, m.lds_entries, c.st, c.rho_part, c.n_rho, col == 0 ? 1 : 0);
+                           m.tl, m.lds_entries, m.lds_lines, c.st, col == 0 ? 1 : 0);
     }
 }
 
 template <bool SYM>
 void scatter_dispatch(const DevMatrix &m, const double *x, double *y, double *sig, const IterCtx &c, hipStream_t s)
 {
-    switch (m.lanes) {
-    case 4: scatter_launch<SYM, 4>(m, x, y, sig, c, s); break;
-    case 8: scatter_launch<SYM, 8>(m, x, y, sig, c, s); break;
-    case 16: scatter_launch<SYM, 16>(m, x, y, sig, c, s); break;
-    case 32: scatter_launch<SYM, 32>(m, x, y, sig, c, s); break;
-    default: scatter_launch<SYM, 64>(m, x, y, sig, c, s); break;
-    }
+    // write slots held in registers: SU per thread must cover the largest block
+    if (m.max_slots <= 2 * kBlock)
+        scatter_launch<SYM, 2>(m, x, y, sig, c, s);
+    else if (m.max_slots <= 4 * kBlock)
+        scatter_launch<SYM, 4>(m, x, y, sig, c, s);
+    else if (m.max_slots <= 6 * kBlock)
+        scatter_launch<SYM, 6>(m, x, y, sig, c, s);
+    else
+        scatter_launch<SYM, 9>(m, x, y, sig, c, s);
 }
 
 } // namespace
@@ -423,7 +600,10 @@ void launch_spmv(const DevMatrix &m, const double *x, double *y, double *sig_par
 {
     if (m.n == 0)
         return;
-    if (m.format == kCsr) {
+    if (m.format == kCsr && m.csr_stream) {
+        hipLaunchKernelGGL(k_spmv_csr_rows, dim3(m.csr_blocks), dim3(kBlock), 0, s, m.csr_nrb, m.csr_rb, m.ptr,
+                           m.idx, m.val, x, y, sig_part, c.st, c.rho_part, c.n_rho);
+    } else if (m.format == kCsr) {
         switch (m.lanes) {
         case 4: csr_launch<4>(m, x, y, sig_part, c, s); break;
         case 8: csr_launch<8>(m, x, y, sig_part, c, s); break;
@@ -445,7 +625,7 @@ void launch_update_r(const DevMatrix &m, double *r, const double *q, DevState *s
                        m.spmv_blocks(), rho_part);
 }
 
-void launch_update_xp(const DevMatrix &m, double *x, double *p, const double *r, const DevState *st,
+void launch_update_xp(const DevMatrix &m, double *x, double *p, const double *r, DevState *st,
                       const double *rho_part, hipStream_t s)
 {
     hipLaunchKernelGGL(k_update_xp, dim3(m.vec_blocks), dim3(kBlock), 0, s, m.n, m.vec_chunk, x, p, r, st,
@@ -454,7 +634,7 @@ void launch_update_xp(const DevMatrix &m, double *x, double *p, const double *r,
 
 void launch_check(const DevMatrix &m, DevState *st, const double *rho_part, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_check, dim3(1), dim3(kBlock), 0, s, st, rho_part, m.vec_blocks);
+    hipLaunchKernelGGL(k_check, dim3(1), dim3(kBlock), 0, s, st);
 }
 
 void launch_init_vec(const DevMatrix &m, const double *b, const double *x0, const double *q, double *r, double *p,

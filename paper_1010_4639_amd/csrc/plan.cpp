@@ -12,7 +12,7 @@ namespace cgmi {
 int64_t Plan::device_bytes() const
 {
     if (format == kCsr)
-        return 0;
+        return (int64_t)csr_rb.size() * 4;
     return (int64_t)blocks.size() * sizeof(ScatterBlock) + (int64_t)phase_blocks.size() * 4 +
            (int64_t)slot_target.size() * 4 + (int64_t)slot_flag.size() + (int64_t)seg.size() * 2 +
            (int64_t)tl.size() * 2;
@@ -139,9 +139,36 @@ static void plan_vectors(Plan &p)
     p.vec_chunk = (int)((n + g - 1) / g);
 }
 
-static void plan_csr(Plan &p)
+static void plan_csr(Plan &p, const int32_t *ptr)
 {
     const int64_t n = p.n;
+    const double mean = (double)p.nnz / (double)n;
+    if (mean <= kStreamMaxMeanRow) {
+        // row blocks: <= kStreamEntries entries and <= kStreamRows rows; a row
+        // longer than kStreamEntries is a block of its own
+        p.csr_stream = true;
+        p.csr_rb.clear();
+        p.csr_rb.push_back(0);
+        int64_t r0 = 0;
+        for (int64_t r = 0; r < n; ++r) {
+            const int64_t len = (int64_t)ptr[r + 1] - ptr[r];
+            if (r > r0 && ((int64_t)ptr[r + 1] - ptr[r0] > kStreamEntries || r - r0 >= kStreamRows ||
+                           len > kStreamEntries)) {
+                p.csr_rb.push_back((int32_t)r);
+                r0 = r;
+            }
+            if (len > kStreamEntries) {
+                p.csr_rb.push_back((int32_t)(r + 1));
+                r0 = r + 1;
+            }
+        }
+        if (p.csr_rb.back() != n)
+            p.csr_rb.push_back((int32_t)n);
+        const int64_t nrb = (int64_t)p.csr_rb.size() - 1;
+        p.csr_blocks = (int)std::max<int64_t>(1, std::min<int64_t>(nrb, kMaxSpmvBlocks));
+        p.csr_rows_per_block = 0;
+        return;
+    }
     const int rows_per_pass = (kBlock / p.lanes) * 4; // 4 row tiles per lane group and pass
     int64_t g = (n + rows_per_pass - 1) / rows_per_pass;
     g = std::max<int64_t>(1, std::min<int64_t>(g, kMaxSpmvBlocks));
@@ -284,6 +311,7 @@ static int plan_scatter(Plan &p, const int32_t *ptr, const int32_t *idx, int tar
     p.tl.reserve(total_tl);
     p.max_entries = 0;
     p.max_lines = 0;
+    p.max_slots = 0;
     std::vector<int32_t> cnt;
     for (int b = 0; b < nb; ++b) {
         ScatterBlock &bk = B[b];
@@ -327,8 +355,10 @@ static int plan_scatter(Plan &p, const int32_t *ptr, const int32_t *idx, int tar
         for_each_contrib([&](int32_t s, int32_t k) { p.tl[base + fill[s]++] = (uint16_t)k; });
         for (int32_t r : t)
             slot_of[r] = -1;
+        bk.ntl = cnt[t.size()];
         p.max_entries = std::max(p.max_entries, bk.k1 - bk.k0);
         p.max_lines = std::max(p.max_lines, bk.line1 - bk.line0);
+        p.max_slots = std::max(p.max_slots, bk.nslots);
     }
 
     // 5. phase order: block ids sorted by colour, block order within a colour
@@ -357,7 +387,7 @@ int build_plan(int fmt, int64_t n, const int32_t *ptr0, const int32_t *idx0, int
     p.lanes = lanes_for_mean_length(mean);
     plan_vectors(p);
     if (fmt == kCsr) {
-        plan_csr(p);
+        plan_csr(p, ptr0);
         return CG_OK;
     }
     if (target_entries <= 0)

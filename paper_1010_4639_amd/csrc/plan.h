@@ -23,11 +23,15 @@ namespace cgmi {
 
 constexpr int kBlock = 256;             // threads per workgroup in every kernel
 constexpr int kDefaultScatterEntries = 2048;
-constexpr int kMaxScatterEntries = 6144;   // LDS: 8 B per entry + 8 B per line <= 56 KB
-constexpr int kMaxBlockLines = 1024;
+constexpr int kMaxScatterEntries = 2048;   // 8 entries per thread held in registers
+constexpr int kMaxBlockLines = 256;
 constexpr int kMaxColors = 64;
 constexpr int kMaxSpmvBlocks = 2048;    // CSR product workgroups (= dot partials)
 constexpr int kMaxVecBlocks = 1024;
+constexpr int kStreamPerThread = 8;                    // CSR row-block kernel: entries per thread
+constexpr int kStreamEntries = kBlock * kStreamPerThread; // entries per CSR row block
+constexpr int kStreamRows = kBlock;                    // rows per CSR row block (one thread each)
+constexpr double kStreamMaxMeanRow = 32.0;             // longer mean rows use lanes-per-row
 constexpr uint8_t kSlotFirst = 1;
 constexpr uint8_t kSlotLast = 2;
 
@@ -38,16 +42,20 @@ struct ScatterBlock {
     int32_t k0, k1;        // entries [k0, k1) (a line longer than the block limit is split)
     int32_t slot0, nslots; // slots [slot0, slot0 + nslots); seg of this block starts at slot0 + id
     int32_t tl0, id;       // contributions start; block id (index of its dot partial)
+    int32_t ntl, pad;      // number of contributions
 };
 
 struct Plan {
     int format = 0;
     int64_t n = 0, nnz = 0;
     int lanes = 16;                       // lanes sharing one line
-    // CSR
+    // CSR: either row blocks (short rows: entries staged in LDS, one thread
+    // sums each row) or `lanes` lanes per row over contiguous row ranges
     int csr_blocks = 0, csr_rows_per_block = 0;
+    bool csr_stream = false;
+    std::vector<int32_t> csr_rb;          // row-block starts (nrb + 1), stream mode
     // scatter formats
-    int nblocks = 0, ncolors = 0, max_entries = 0, max_lines = 0;
+    int nblocks = 0, ncolors = 0, max_entries = 0, max_lines = 0, max_slots = 0;
     std::vector<ScatterBlock> blocks;     // by block id
     std::vector<int32_t> color_off;       // ncolors + 1
     std::vector<int32_t> phase_blocks;    // block ids ordered by colour (stable)

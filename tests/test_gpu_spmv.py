@@ -68,7 +68,7 @@ def test_sym_random_spd():
     check_spmv(SYM, up, uc, uv, x, label="random spd")
 
 
-@pytest.mark.parametrize("entries", ["32", "200", "6144"])
+@pytest.mark.parametrize("entries", ["32", "200", "2048", "9000"])
 @pytest.mark.parametrize("fmt", [SYM, CSC])
 def test_scatter_block_sizes(monkeypatch, fmt, entries):
     monkeypatch.setenv("CGMI_SCATTER_ENTRIES", entries)
@@ -152,3 +152,18 @@ def test_errors_without_fallback():
         assert st == cgmi.CG_ERR_STRUCTURE and h is None
     st, h = cgmi.cg_create(CSR, s.n, s.rowptr, s.col, np.full(s.nnz, np.inf))
     assert st == cgmi.CG_ERR_NONFINITE and h is None
+
+
+@pytest.mark.parametrize("case", ["fem32x32x30", "fem100", "ragged"])
+def test_csr_bit_identical_to_oracle(case):
+    # rows of <= 2048 entries with a mean of <= 32: the row-block kernel sums
+    # each row left to right from rounded products, exactly like the oracle
+    if case == "ragged":
+        ptr, col, val = W.random_sparse(5000, density=0.003, seed=21, empty_rows=40, long_rows=2, long_len=1500)
+    else:
+        s = fem_cached(case)
+        ptr, col, val = s.rowptr, s.col, s.val
+    st, stats = cgmi.cg_analyze(CSR, len(ptr) - 1, ptr, col, val)
+    assert st == 0
+    y, yo = check_spmv(CSR, ptr, col, val, W.uniform_vector(len(ptr) - 1, seed=22), label=f"bitwise {case}")
+    assert np.array_equal(y, yo)
