@@ -167,8 +167,9 @@ def main():
                                 spmv_colors=spmv[name]["colors"])
     # dominant product kernel: largest share of the step's time
     dom = max(solvers, key=lambda k: spmv[k]["us"] * per_format[k]["iters"])
-    kernel_name = {"csr": "k_spmv_csr<16,4>", "symcsr": "k_spmv_scatter<true,8> (all colour phases)",
-                   "csc": "k_spmv_scatter<false,16> (all colour phases)"}[dom]
+    kernel_name = {"csr": "k_spmv_csr_rows (CSR product)",
+                   "symcsr": "k_scatter_sums<true> + k_scatter_combine (symmetric-CSR product, all colours)",
+                   "csc": "k_scatter_sums<false> + k_scatter_combine (CSC product, all colours)"}[dom]
     traffic = load_traffic(dom)
     roofline = dict(bound="hbm", achieved=round(spmv[dom]["GBps"], 1), peak=HBM_PEAK_GBPS, unit="GB/s",
                     frac=round(spmv[dom]["GBps"] / HBM_PEAK_GBPS, 4), traffic=traffic, kernel=kernel_name,

@@ -69,6 +69,11 @@ typedef enum {
 
 /* cg_create flags */
 #define CG_CHECK_SYMMETRY 1u /* CSR / CSC: require A == A' exactly (pattern and bits) */
+#define CG_MIXED 2u          /* also keep an FP32 copy of D^-1/2 A D^-1/2 (D = diag A, which must be
+                                positive) for cg_solve_mixed */
+#define CG_LOWER 4u          /* CG_FMT_SYM_CSR given as the paper stores it: the LOWER triangle incl.
+                                diagonal by rows (j <= i, each row ends with its diagonal); converted
+                                exactly to the upper layout at creation (same arrays as CSC of D + U) */
 
 typedef struct {
     int32_t iters;      /* products Ap inside the loop (0 if the start already met tol) */
@@ -76,6 +81,8 @@ typedef struct {
     double relres;      /* ||r_k||_2 / ||b||_2 of the recursive residual */
     double relres_true; /* ||b - A x||_2 / ||b||_2 of the returned x (one extra product) */
     double ms;          /* host wall time of the call, milliseconds */
+    int32_t outer;      /* cg_solve_mixed: refinement steps (0 for cg_solve) */
+    int32_t reserved;
 } cg_info;
 
 /* Plan summary (host-side description of how the product is executed). */
@@ -87,6 +94,7 @@ typedef struct {
     int32_t spmv_blocks;     /* workgroups (= dot-product partials) of one product */
     int32_t vec_blocks;      /* workgroups of the vector kernels */
     int32_t colors;          /* scatter formats: colour phases per product; CSR: 0 */
+    int32_t scatter_blocks;  /* scatter formats: blocks of the plan (sizes of cg_analyze_export) */
     int32_t max_block_entries;
     int64_t slots;           /* scatter formats: total (block, target) write slots */
     int64_t plan_bytes;      /* device bytes of the plan beyond ptr / idx / vals */
@@ -103,8 +111,9 @@ typedef struct {
  *               strictly increasing within a line (sorted, no duplicates)
  *   vals        host, nnz float64, all finite
  *   index_base  0 or 1
- *   flags       0 or CG_CHECK_SYMMETRY
- * Errors: CG_ERR_ARG, CG_ERR_STRUCTURE (rules above; for CG_FMT_SYM_CSR every
+ *   flags       0 or CG_CHECK_SYMMETRY | CG_MIXED | CG_LOWER
+ * Errors: CG_ERR_ARG (also: CG_MIXED with a diagonal entry <= 0 or missing),
+ * CG_ERR_STRUCTURE (rules above; for CG_FMT_SYM_CSR every
  * row must start with its diagonal), CG_ERR_NONFINITE, CG_ERR_NOMEM,
  * CG_ERR_HIP, CG_ERR_UNSUPPORTED.  Blocks the host (planning and upload).
  */
@@ -132,6 +141,67 @@ int cg_set_batch(cg_handle *h, int32_t iters_per_launch);
  * device work runs on the handle's stream.
  */
 int cg_solve(cg_handle *h, const double *b, double *x, double tol, int32_t maxit, cg_info *info);
+
+/*
+ * cg_solve_mixed -- FP64 iterative refinement around FP32 inner CG solves.
+ * The paper runs the same CG in single precision (section IV, Tesla C870)
+ * and in double precision; here the product and the search directions of
+ * the inner CG use FP32 storage (the FP32 copy of D^-1/2 A D^-1/2 made at
+ * cg_create with CG_MIXED, FP32 p), while the residual b - A x (FP64
+ * product), all dot products and the alpha / beta recurrences stay FP64:
+ *   r = b - A x ; repeat { solve (D^-1/2 A D^-1/2) c = D^-1/2 r by CG to
+ *   ||r_c|| <= inner_tol ||D^-1/2 r|| ; x += D^-1/2 c ; r = b - A x }
+ *   until ||r|| <= tol ||b|| (the TRUE residual).
+ *   b, x, tol    as in cg_solve
+ *   maxit        >= 0: inner iterations allowed in total
+ *   inner_tol    in (0, 1)
+ *   max_outer    >= 1: refinement steps allowed
+ * Returns CG_OK, CG_NOT_CONVERGED (maxit or max_outer reached, x = last
+ * iterate), CG_ERR_BREAKDOWN (an inner solve broke down before any
+ * progress), CG_ERR_NONFINITE, CG_ERR_ARG (also: handle created without
+ * CG_MIXED) or CG_ERR_HIP.  info->iters counts inner iterations,
+ * info->outer refinement steps, info->relres = info->relres_true.
+ */
+int cg_solve_mixed(cg_handle *h, const double *b, double *x, double tol, int32_t maxit, double inner_tol,
+                   int32_t max_outer, cg_info *info);
+
+/*
+ * Batched solves: many independent SPD systems of uneven size, each with
+ * nrhs right-hand sides, advanced together by one sequence of kernels
+ * replayed from a HIP graph; every (system, right-hand side) pair has its own
+ * CG scalars and stopping test (the iteration of section III, per pair).
+ *   nsys      >= 1 systems
+ *   sys_off   host, nsys+1 int64: rows of system s are [sys_off[s], sys_off[s+1])
+ *             (sys_off[0] = 0, strictly increasing)
+ *   ptr, idx, vals  host CSR of the block-diagonal matrix (global indices;
+ *             every column of a row lies inside the row's system), rules of
+ *             cg_create for CG_FMT_CSR
+ *   nrhs      1, 2 or 4; vectors are interleaved: entry (i, r) at i*nrhs + r
+ * Errors as cg_create, plus CG_ERR_STRUCTURE for a row coupling two systems.
+ */
+typedef struct cg_batch cg_batch;
+int cg_batch_create(cg_batch **out, int32_t nsys, const int64_t *sys_off, const int32_t *ptr, const int32_t *idx,
+                    const double *vals, int32_t nrhs, int index_base);
+int cg_batch_set_stream(cg_batch *h, void *hip_stream);
+/* Y = A X for all systems and right-hand sides (device, N*nrhs float64 each). */
+int cg_batch_spmm(cg_batch *h, const double *X, double *Y);
+/* Project-written autotuner: times the product for every row-block size
+ * (256, 512, 1024 entries) x workgroup budget (1024, 2048, 4096), keeps the
+ * fastest plan and reports it (outputs may be NULL).  Uses the GPU. */
+int cg_batch_autotune(cg_batch *h, int32_t *entries_per_block, int32_t *workgroups, float *best_us);
+/* Solves all pairs from X (in: x0, out: solutions) to ||r|| <= tol ||b|| each.
+ *   B, X      device, N*nrhs float64, interleaved
+ *   iters, status  host, nsys*nrhs int32 each (pair s*nrhs + r), may be NULL:
+ *             per-pair iteration count and cg_status
+ *   info      aggregate: iters = max over pairs, status = worst pair status,
+ *             relres / relres_true = max over pairs
+ * Returns the worst status (CG_OK if every pair converged). */
+int cg_batch_solve(cg_batch *h, const double *B, double *X, double tol, int32_t maxit, int32_t *iters,
+                   int32_t *status, cg_info *info);
+void cg_batch_destroy(cg_batch *h);
+/* Detail of the last error on h; with h == NULL, of the calling thread's last
+ * failed cg_batch_create.  Never NULL. */
+const char *cg_batch_last_error(const cg_batch *h);
 
 /* y = A x (device pointers, n float64 each, x and y must not overlap).
  * Asynchronous on the handle's stream. */
@@ -163,9 +233,9 @@ int cg_analyze(int format, int64_t n, const int32_t *ptr, const int32_t *idx, co
  * Host-only export of the scatter plan of CG_FMT_SYM_CSR / CG_FMT_CSC
  * (colour of every block, its line and entry range, and its write slots),
  * so the plan can be checked independently.  Arrays sized from cg_analyze:
- *   blk_color, blk_line0, blk_line1      [spmv_blocks]  int32
- *   blk_entry0, blk_entry1               [spmv_blocks]  int32 (0-based)
- *   blk_slot0                            [spmv_blocks+1] int64: slots of block b
+ *   blk_color, blk_line0, blk_line1      [scatter_blocks]  int32
+ *   blk_entry0, blk_entry1               [scatter_blocks]  int32 (0-based)
+ *   blk_slot0                            [scatter_blocks+1] int64: slots of block b
  *                                        are [blk_slot0[b], blk_slot0[b+1])
  *   slot_target                          [slots] int32: row of y written
  *   slot_flags                           [slots] uint8: bit0 first writer of

@@ -30,7 +30,7 @@ def build(verbose=False):
     o = os.path.join(BUILD, "plan.o")
     _run(["g++", "-O2", "-std=c++17", "-fPIC", "-Wall", "-c", os.path.join(CSRC, "plan.cpp"), "-o", o])
     objs.append(o)
-    for src in ("kernels.hip", "capi.cpp"):
+    for src in ("kernels.hip", "batch.hip", "capi.cpp"):
         o = os.path.join(BUILD, src.split(".")[0] + ".o")
         _run([HIPCC, *HIP_FLAGS, "-x", "hip", "-c", os.path.join(CSRC, src), "-o", o])
         objs.append(o)

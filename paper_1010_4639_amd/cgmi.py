@@ -21,25 +21,30 @@ CG_OK, CG_NOT_CONVERGED = 0, 1
 CG_ERR_ARG, CG_ERR_STRUCTURE, CG_ERR_BREAKDOWN, CG_ERR_NONFINITE = -1, -2, -3, -4
 CG_ERR_NOMEM, CG_ERR_HIP, CG_ERR_UNSUPPORTED = -5, -6, -7
 CG_CHECK_SYMMETRY = 1
+CG_MIXED = 2
+CG_LOWER = 4
 
 # every symbol declared in include/cgmi.h
-EXPORTS = ("cg_create", "cg_set_stream", "cg_set_batch", "cg_solve", "cg_spmv", "cg_get_stats", "cg_destroy",
-           "cg_status_string", "cg_last_error", "cg_analyze", "cg_analyze_export")
+EXPORTS = ("cg_create", "cg_set_stream", "cg_set_batch", "cg_solve", "cg_solve_mixed", "cg_spmv", "cg_get_stats",
+           "cg_destroy", "cg_status_string", "cg_last_error", "cg_analyze", "cg_analyze_export",
+           "cg_batch_create", "cg_batch_set_stream", "cg_batch_spmm", "cg_batch_autotune", "cg_batch_solve",
+           "cg_batch_destroy", "cg_batch_last_error")
 
 
 class cg_info(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32), ("status", ctypes.c_int32), ("relres", ctypes.c_double),
-                ("relres_true", ctypes.c_double), ("ms", ctypes.c_double)]
+                ("relres_true", ctypes.c_double), ("ms", ctypes.c_double), ("outer", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
     def as_dict(self):
-        return {f: getattr(self, f) for f, _ in self._fields_}
+        return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
 
 
 class cg_plan_stats(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("nnz", ctypes.c_int64), ("format", ctypes.c_int32),
                 ("lanes_per_line", ctypes.c_int32), ("spmv_blocks", ctypes.c_int32),
                 ("vec_blocks", ctypes.c_int32), ("colors", ctypes.c_int32),
-                ("max_block_entries", ctypes.c_int32), ("slots", ctypes.c_int64),
+                ("scatter_blocks", ctypes.c_int32), ("max_block_entries", ctypes.c_int32), ("slots", ctypes.c_int64),
                 ("plan_bytes", ctypes.c_int64)]
 
     def as_dict(self):
@@ -76,6 +81,7 @@ def load():
     lib.cg_set_stream.argtypes = [_VP, _VP]
     lib.cg_set_batch.argtypes = [_VP, i32]
     lib.cg_solve.argtypes = [_VP, _VP, _VP, dbl, i32, ctypes.POINTER(cg_info)]
+    lib.cg_solve_mixed.argtypes = [_VP, _VP, _VP, dbl, i32, dbl, i32, ctypes.POINTER(cg_info)]
     lib.cg_spmv.argtypes = [_VP, _VP, _VP]
     lib.cg_get_stats.argtypes = [_VP, ctypes.POINTER(cg_plan_stats)]
     lib.cg_destroy.argtypes = [_VP]
@@ -86,7 +92,18 @@ def load():
     lib.cg_last_error.restype = ctypes.c_char_p
     lib.cg_analyze.argtypes = [ctypes.c_int, i64, _VP, _VP, _VP, ctypes.c_int, u32, ctypes.POINTER(cg_plan_stats)]
     lib.cg_analyze_export.argtypes = [ctypes.c_int, i64, _VP, _VP, ctypes.c_int] + [_VP] * 9
-    for nm in ("cg_create", "cg_set_stream", "cg_set_batch", "cg_solve", "cg_spmv", "cg_get_stats",
+    lib.cg_batch_create.argtypes = [ctypes.POINTER(_VP), i32, _VP, _VP, _VP, _VP, i32, ctypes.c_int]
+    lib.cg_batch_set_stream.argtypes = [_VP, _VP]
+    lib.cg_batch_spmm.argtypes = [_VP, _VP, _VP]
+    lib.cg_batch_autotune.argtypes = [_VP, _VP, _VP, _VP]
+    lib.cg_batch_solve.argtypes = [_VP, _VP, _VP, dbl, i32, _VP, _VP, ctypes.POINTER(cg_info)]
+    lib.cg_batch_destroy.argtypes = [_VP]
+    lib.cg_batch_destroy.restype = None
+    lib.cg_batch_last_error.argtypes = [_VP]
+    lib.cg_batch_last_error.restype = ctypes.c_char_p
+    for nm in ("cg_batch_create", "cg_batch_set_stream", "cg_batch_spmm", "cg_batch_autotune", "cg_batch_solve"):
+        getattr(lib, nm).restype = ctypes.c_int
+    for nm in ("cg_create", "cg_set_stream", "cg_set_batch", "cg_solve", "cg_solve_mixed", "cg_spmv", "cg_get_stats",
                "cg_analyze", "cg_analyze_export"):
         getattr(lib, nm).restype = ctypes.c_int
     _lib = lib
@@ -152,6 +169,14 @@ def cg_solve(handle, b_ptr, x_ptr, tol, maxit):
     return st, info.as_dict()
 
 
+def cg_solve_mixed(handle, b_ptr, x_ptr, tol, maxit, inner_tol, max_outer):
+    """Raw call on device addresses; returns (status, info dict)."""
+    info = cg_info()
+    st = load().cg_solve_mixed(handle, _VP(b_ptr), _VP(x_ptr), float(tol), int(maxit), float(inner_tol),
+                               int(max_outer), ctypes.byref(info))
+    return st, info.as_dict()
+
+
 def cg_spmv(handle, x_ptr, y_ptr):
     return load().cg_spmv(handle, _VP(x_ptr), _VP(y_ptr))
 
@@ -181,7 +206,7 @@ def cg_analyze_export(fmt, n, ptr, idx, index_base=0):
     st, stats = cg_analyze(fmt, n, ptr, idx, None, index_base)
     if st != CG_OK:
         return st, None
-    nb, ns = stats["spmv_blocks"], stats["slots"]
+    nb, ns = stats["scatter_blocks"], stats["slots"]
     out = dict(color=np.zeros(nb, np.int32), line0=np.zeros(nb, np.int32), line1=np.zeros(nb, np.int32),
                entry0=np.zeros(nb, np.int32), entry1=np.zeros(nb, np.int32), slot0=np.zeros(nb + 1, np.int64),
                target=np.zeros(ns, np.int32), flags=np.zeros(ns, np.uint8), count=np.zeros(ns, np.int32))
@@ -202,8 +227,10 @@ class Solver:
     and return float64 GPU tensors.
     """
 
-    def __init__(self, fmt, ptr, idx, vals, index_base=0, flags=0, batch=None):
+    def __init__(self, fmt, ptr, idx, vals, index_base=0, flags=0, batch=None, mixed=False):
         self.n = len(ptr) - 1
+        if mixed:
+            flags |= CG_MIXED
         st, h = cg_create(fmt, self.n, ptr, idx, vals, index_base, flags)
         if st != CG_OK:
             raise CgError(st, cg_last_error(None))
@@ -228,6 +255,20 @@ class Solver:
             raise CgError(st, cg_last_error(self.h))
         return x, d
 
+    def solve_mixed(self, b, x0=None, tol=1e-10, maxit=None, inner_tol=1e-4, max_outer=50, check=True):
+        """FP64 refinement around FP32 inner CG (handle created with mixed=True)."""
+        import torch
+        x = torch.zeros_like(b) if x0 is None else x0.clone()
+        bp, xp = _dev(b, self.n, "b"), _dev(x, self.n, "x")
+        self._stream()
+        info = cg_info()
+        st = load().cg_solve_mixed(self.h, bp, xp, float(tol), int(10 * self.n if maxit is None else maxit),
+                                   float(inner_tol), int(max_outer), ctypes.byref(info))
+        d = info.as_dict()
+        if check and st < 0 and st != CG_ERR_BREAKDOWN:
+            raise CgError(st, cg_last_error(self.h))
+        return x, d
+
     def spmv(self, x, y=None):
         import torch
         if y is None:
@@ -245,6 +286,96 @@ class Solver:
     def close(self):
         if self.h:
             cg_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+# ------------------------------------------------------------- batches
+def cg_batch_last_error(handle=None):
+    return load().cg_batch_last_error(handle).decode()
+
+
+def cg_batch_create(sys_off, ptr, idx, vals, nrhs=4, index_base=0):
+    """Returns (status, handle or None); host arrays of the block-diagonal CSR."""
+    lib = load()
+    so = np.ascontiguousarray(sys_off, dtype=np.int64)
+    ptr, idx, vals = _host_i32(ptr), _host_i32(idx), _host_f64(vals)
+    h = _VP()
+    st = lib.cg_batch_create(ctypes.byref(h), len(so) - 1, _np_ptr(so), _np_ptr(ptr), _np_ptr(idx), _np_ptr(vals),
+                             int(nrhs), int(index_base))
+    return st, (h if st == CG_OK else None)
+
+
+class Batch:
+    """Many independent systems (block-diagonal CSR) x nrhs right-hand sides.
+
+    Vectors are torch float64 GPU tensors of shape (N, nrhs) (row-major, so
+    entry (i, r) sits at i*nrhs + r)."""
+
+    def __init__(self, sys_off, ptr, idx, vals, nrhs=4, index_base=0):
+        st, h = cg_batch_create(sys_off, ptr, idx, vals, nrhs, index_base)
+        if st != CG_OK:
+            raise CgError(st, cg_batch_last_error(None))
+        self.h, self.nrhs = h, nrhs
+        self.N = int(sys_off[-1])
+        self.nsys = len(sys_off) - 1
+
+    def _stream(self):
+        import torch
+        load().cg_batch_set_stream(self.h, _VP(torch.cuda.current_stream().cuda_stream))
+
+    def _check(self, t, name):
+        import torch
+        if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float64 or not t.is_contiguous() \
+                or tuple(t.shape) != (self.N, self.nrhs):
+            raise TypeError(f"{name} must be a contiguous float64 GPU tensor of shape ({self.N}, {self.nrhs})")
+        return _VP(t.data_ptr())
+
+    def autotune(self):
+        e, w, us = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_float()
+        self._stream()
+        st = load().cg_batch_autotune(self.h, ctypes.byref(e), ctypes.byref(w), ctypes.byref(us))
+        if st != CG_OK:
+            raise CgError(st, cg_batch_last_error(self.h))
+        return dict(entries_per_block=e.value, workgroups=w.value, us=us.value)
+
+    def spmm(self, X, Y=None):
+        import torch
+        Y = torch.empty_like(X) if Y is None else Y
+        xp, yp = self._check(X, "X"), self._check(Y, "Y")
+        self._stream()
+        st = load().cg_batch_spmm(self.h, xp, yp)
+        if st != CG_OK:
+            raise CgError(st, cg_batch_last_error(self.h))
+        return Y
+
+    def solve(self, B, X0=None, tol=1e-10, maxit=None):
+        """Returns (X, info dict, iters[nsys, nrhs], status[nsys, nrhs])."""
+        import torch
+        X = torch.zeros_like(B) if X0 is None else X0.clone()
+        bp, xp = self._check(B, "B"), self._check(X, "X")
+        it = np.zeros((self.nsys, self.nrhs), np.int32)
+        stv = np.zeros((self.nsys, self.nrhs), np.int32)
+        info = cg_info()
+        self._stream()
+        load().cg_batch_solve(self.h, bp, xp, float(tol), int(10 * self.N if maxit is None else maxit),
+                              _np_ptr(it), _np_ptr(stv), ctypes.byref(info))
+        return X, info.as_dict(), it, stv
+
+    def close(self):
+        if self.h:
+            load().cg_batch_destroy(self.h)
             self.h = None
 
     def __del__(self):

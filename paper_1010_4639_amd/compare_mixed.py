@@ -1,0 +1,76 @@
+"""Time-to-tolerance of FP64 CG vs mixed-precision refinement on one system.
+
+    python -m paper_1010_4639_amd.compare_mixed [--workload fem160] [--formats csr]
+        [--tol 1e-10] [--inner-tol 1e-4] [--reps 2]
+
+For each format: the FP64 solve (cg_solve) and the mixed solve
+(cg_solve_mixed: FP32 product and search directions inside FP64 iterative
+refinement), both from x0 = 0 to ||b - A x|| <= tol ||b||, timed on the
+device with the host blocking on the result (median of `reps` after one
+warm-up).  Prints one JSON line with both times, iteration counts, the true
+residuals and the relative 2-norm difference between the two solutions.
+"""
+import argparse
+import json
+import sys
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--workload", default="fem160")
+    ap.add_argument("--formats", default="csr")
+    ap.add_argument("--tol", type=float, default=1e-10)
+    ap.add_argument("--inner-tol", type=float, default=1e-4)
+    ap.add_argument("--maxit", type=int, default=200000)
+    ap.add_argument("--reps", type=int, default=2)
+    a = ap.parse_args(argv)
+    import statistics
+    import time
+
+    import numpy as np
+    import torch
+
+    from paper_1010_4639_amd import cgmi
+    from paper_1010_4639_amd import workload as W
+
+    dev = torch.device("cuda:0")
+    t0 = time.time()
+    s = W.fem_config(a.workload, keep_geometry=False)
+    up, uc, uv = W.upper_triangle(s.rowptr, s.col, s.val)
+    arrs = {"csr": (s.rowptr, s.col, s.val), "symcsr": (up, uc, uv), "csc": (s.rowptr, s.col, s.val)}
+    print(f"[mixed] generated {a.workload} n={s.n} nnz={s.nnz} in {time.time() - t0:.1f}s", file=sys.stderr,
+          flush=True)
+    b = torch.from_numpy(s.b).to(dev)
+    out = {"workload": a.workload, "n": s.n, "nnz": s.nnz, "tol": a.tol, "inner_tol": a.inner_tol}
+    for name in a.formats.split(","):
+        with cgmi.Solver(name, *arrs[name], mixed=True) as S:
+            res = {}
+            for mode in ("fp64", "mixed"):
+                times, info, x = [], None, None
+                for r in range(a.reps + 1):
+                    torch.cuda.synchronize()
+                    t1 = time.perf_counter()
+                    if mode == "fp64":
+                        x, info = S.solve(b, tol=a.tol, maxit=a.maxit)
+                    else:
+                        x, info = S.solve_mixed(b, tol=a.tol, maxit=a.maxit, inner_tol=a.inner_tol,
+                                                max_outer=100)
+                    torch.cuda.synchronize()
+                    if r > 0:
+                        times.append((time.perf_counter() - t1) * 1e3)
+                    print(f"[mixed] {name} {mode} rep {r}: {info}", file=sys.stderr, flush=True)
+                res[mode] = dict(ms=round(statistics.median(times), 3), iters=info["iters"],
+                                 outer=info.get("outer", 0), status=info["status"],
+                                 relres_true=info["relres_true"], x=x)
+            xd, xm = res["fp64"].pop("x"), res["mixed"].pop("x")
+            res["rel_diff_2norm"] = float(torch.linalg.norm(xd - xm) / torch.linalg.norm(xd))
+            xt = torch.from_numpy(s.x_true).to(dev)
+            res["fp64"]["err_vs_x_true"] = float(torch.linalg.norm(xd - xt) / torch.linalg.norm(xt))
+            res["mixed"]["err_vs_x_true"] = float(torch.linalg.norm(xm - xt) / torch.linalg.norm(xt))
+            res["speedup"] = round(res["fp64"]["ms"] / res["mixed"]["ms"], 3)
+            out[name] = res
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -43,6 +43,14 @@ struct cg_handle {
     hipGraphExec_t gexec = nullptr;
     int batch = 32;
     int graph_batch = 0;
+    // mixed precision (CG_MIXED)
+    bool mixed = false;
+    DevState *st_in = nullptr; // state of the inner FP32 solves
+    float *p32 = nullptr;      // inner search direction, FP32
+    double *rout = nullptr;    // outer residual b - A x, FP64
+    hipGraph_t graph32 = nullptr;
+    hipGraphExec_t gexec32 = nullptr;
+    int graph32_batch = 0;
     std::string err;
 };
 
@@ -96,6 +104,10 @@ void release(cg_handle *h)
         (void)hipGraphExecDestroy(h->gexec);
     if (h->graph)
         (void)hipGraphDestroy(h->graph);
+    if (h->gexec32)
+        (void)hipGraphExecDestroy(h->gexec32);
+    if (h->graph32)
+        (void)hipGraphDestroy(h->graph32);
     for (auto &e : h->ev)
         if (e)
             (void)hipEventDestroy(e);
@@ -147,23 +159,53 @@ int upload_all(cg_handle *h, const std::vector<int32_t> &ptr0, const std::vector
         m.csr_nrb = (int)p.csr_rb.size() - 1;
     }
     if (p.format != kCsr && n > 0) {
+        // device arrays in colour order: the blocks of one colour, and their
+        // write slots, are contiguous
+        const int nb = p.nblocks;
+        std::vector<ScatterBlock> ob(nb);
+        std::vector<int32_t> otg, cso(p.ncolors + 1, 0);
+        std::vector<uint8_t> ofl;
+        std::vector<uint16_t> osg;
+        otg.reserve(p.slot_target.size());
+        ofl.reserve(p.slot_flag.size());
+        osg.reserve(p.seg.size());
+        for (int i = 0; i < nb; ++i) {
+            const ScatterBlock &src = p.blocks[p.phase_blocks[i]];
+            ScatterBlock d = src;
+            d.slot0 = (int32_t)otg.size();
+            d.id = i;
+            d.pad = p.block_color[src.id];
+            for (int s = 0; s < src.nslots; ++s) {
+                otg.push_back(p.slot_target[src.slot0 + s]);
+                ofl.push_back(p.slot_flag[src.slot0 + s]);
+            }
+            for (int s = 0; s <= src.nslots; ++s)
+                osg.push_back(p.seg[src.slot0 + src.id + s]);
+            cso[d.pad + 1] += src.nslots;
+            ob[i] = d;
+        }
+        for (int c = 0; c < p.ncolors; ++c)
+            cso[c + 1] += cso[c];
         ScatterBlock *b;
-        int32_t *pb, *tg;
+        int32_t *tg;
         uint8_t *fl;
         uint16_t *sg, *tl;
-        if ((st = upload(h, &b, p.blocks.data(), p.blocks.size())) != CG_OK ||
-            (st = upload(h, &pb, p.phase_blocks.data(), p.phase_blocks.size())) != CG_OK ||
-            (st = upload(h, &tg, p.slot_target.data(), p.slot_target.size())) != CG_OK ||
-            (st = upload(h, &fl, p.slot_flag.data(), p.slot_flag.size())) != CG_OK ||
-            (st = upload(h, &sg, p.seg.data(), p.seg.size())) != CG_OK ||
-            (st = upload(h, &tl, p.tl.data(), p.tl.size())) != CG_OK)
+        double *part;
+        if ((st = upload(h, &b, ob.data(), ob.size())) != CG_OK ||
+            (st = upload(h, &tg, otg.data(), otg.size())) != CG_OK ||
+            (st = upload(h, &fl, ofl.data(), ofl.size())) != CG_OK ||
+            (st = upload(h, &sg, osg.data(), osg.size())) != CG_OK ||
+            (st = upload(h, &tl, p.tl.data(), p.tl.size())) != CG_OK ||
+            (st = dalloc(h, &part, otg.size())) != CG_OK)
             return st;
         m.blocks = b;
-        m.phase_blocks = pb;
         m.slot_target = tg;
         m.slot_flag = fl;
         m.seg = sg;
         m.tl = tl;
+        m.part = part;
+        m.color_slot_off = cso;
+        m.scatter_wgs = p.scatter_wgs();
     }
     const size_t nv = (size_t)std::max<int64_t>(n, 1);
     if ((st = dalloc(h, &h->r, nv)) != CG_OK || (st = dalloc(h, &h->p, nv)) != CG_OK ||
@@ -174,6 +216,34 @@ int upload_all(cg_handle *h, const std::vector<int32_t> &ptr0, const std::vector
         (st = dalloc(h, &h->rho, ns)) != CG_OK || (st = dalloc(h, &h->bb, ns)) != CG_OK ||
         (st = dalloc(h, &h->st, 1)) != CG_OK)
         return st;
+    if (h->mixed && n > 0) {
+        // FP32 copy of D^-1/2 A D^-1/2: each value scaled in FP64, rounded once
+        std::vector<double> dg((size_t)n, 0.0);
+        for (int64_t l = 0; l < n; ++l)
+            for (int64_t k = ptr0[l]; k < ptr0[l + 1]; ++k)
+                if (idx0[k] == l)
+                    dg[l] = vals[k];
+        std::vector<double> sc((size_t)n);
+        for (int64_t i = 0; i < n; ++i) {
+            if (!(dg[i] > 0.0)) {
+                h->err = "CG_MIXED needs a positive diagonal (row " + std::to_string(i) + ")";
+                return CG_ERR_ARG;
+            }
+            sc[i] = 1.0 / std::sqrt(dg[i]);
+        }
+        std::vector<float> v32(idx0.size());
+        for (int64_t l = 0; l < n; ++l)
+            for (int64_t k = ptr0[l]; k < ptr0[l + 1]; ++k)
+                v32[k] = (float)(vals[k] * sc[l] * sc[idx0[k]]);
+        float *dv32;
+        double *dsc;
+        if ((st = upload(h, &dv32, v32.data(), v32.size())) != CG_OK ||
+            (st = upload(h, &dsc, sc.data(), sc.size())) != CG_OK || (st = dalloc(h, &h->p32, nv)) != CG_OK ||
+            (st = dalloc(h, &h->rout, nv)) != CG_OK || (st = dalloc(h, &h->st_in, 1)) != CG_OK)
+            return st;
+        m.val32 = dv32;
+        m.dscale = dsc;
+    }
     hipError_t e = hipHostMalloc((void **)&h->host_st, 2 * sizeof(DevState), hipHostMallocDefault);
     if (e != hipSuccess)
         return hip_fail(h->err, e, "hipHostMalloc");
@@ -192,6 +262,7 @@ void fill_stats(const Plan &p, cg_plan_stats *s)
     s->format = p.format;
     s->lanes_per_line = p.lanes;
     s->spmv_blocks = p.spmv_blocks();
+    s->scatter_blocks = p.nblocks;
     s->vec_blocks = p.vec_blocks;
     s->colors = p.ncolors;
     s->max_block_entries = p.max_entries;
@@ -217,27 +288,88 @@ void enqueue_iteration(cg_handle *h, hipStream_t s)
     launch_update_xp(h->dm, h->xw, h->p, h->r, h->st, h->rho, s);
 }
 
-int build_graph(cg_handle *h)
+// One inner (mixed-precision) iteration: FP32 product, FP64 r update, FP64 c
+// update with the FP32 search direction.
+void enqueue_iteration32(cg_handle *h, hipStream_t s)
 {
-    if (h->gexec && h->graph_batch == h->batch)
+    IterCtx c;
+    c.st = h->st_in;
+    launch_spmv32(h->dm, h->p32, h->q, h->sig, c, s);
+    launch_update_r(h->dm, h->r, h->q, h->st_in, h->sig, h->rho, s);
+    launch_update_xp32(h->dm, h->p, h->p32, h->r, h->st_in, h->rho, s);
+}
+
+int build_graph_generic(cg_handle *h, bool mixed)
+{
+    hipGraph_t &g = mixed ? h->graph32 : h->graph;
+    hipGraphExec_t &ge = mixed ? h->gexec32 : h->gexec;
+    int &gb = mixed ? h->graph32_batch : h->graph_batch;
+    if (ge && gb == h->batch)
         return CG_OK;
-    if (h->gexec) {
-        (void)hipGraphExecDestroy(h->gexec);
-        h->gexec = nullptr;
+    if (ge) {
+        (void)hipGraphExecDestroy(ge);
+        ge = nullptr;
     }
-    if (h->graph) {
-        (void)hipGraphDestroy(h->graph);
-        h->graph = nullptr;
+    if (g) {
+        (void)hipGraphDestroy(g);
+        g = nullptr;
     }
     HIP_TRY(h, hipStreamBeginCapture(h->capture, hipStreamCaptureModeThreadLocal));
-    for (int i = 0; i < h->batch; ++i)
-        enqueue_iteration(h, h->capture);
-    launch_check(h->dm, h->st, h->rho, h->capture);
-    hipError_t e = hipStreamEndCapture(h->capture, &h->graph);
+    for (int i = 0; i < h->batch; ++i) {
+        if (mixed)
+            enqueue_iteration32(h, h->capture);
+        else
+            enqueue_iteration(h, h->capture);
+    }
+    launch_check(h->dm, mixed ? h->st_in : h->st, h->rho, h->capture);
+    hipError_t e = hipStreamEndCapture(h->capture, &g);
     if (e != hipSuccess)
         return hip_fail(h->err, e, "hipStreamEndCapture");
-    HIP_TRY(h, hipGraphInstantiate(&h->gexec, h->graph, nullptr, nullptr, 0));
-    h->graph_batch = h->batch;
+    HIP_TRY(h, hipGraphInstantiate(&ge, g, nullptr, nullptr, 0));
+    gb = h->batch;
+    return CG_OK;
+}
+
+int build_graph(cg_handle *h)
+{
+    return build_graph_generic(h, false);
+}
+
+// Replays `ge` (two launches in flight) until the device status of `st`
+// leaves kRun; returns the final status through *status.
+int run_until_stop(cg_handle *h, hipGraphExec_t ge, DevState *st, int32_t *status)
+{
+    hipStream_t s = h->stream;
+    hipError_t e;
+    auto launch = [&](int slot) -> hipError_t {
+        hipError_t r = hipGraphLaunch(ge, s);
+        if (r == hipSuccess)
+            r = hipMemcpyAsync(&h->host_st[slot], st, sizeof(DevState), hipMemcpyDeviceToHost, s);
+        if (r == hipSuccess)
+            r = hipEventRecord(h->ev[slot], s);
+        return r;
+    };
+    if ((e = launch(0)) != hipSuccess)
+        return hip_fail(h->err, e, "hipGraphLaunch");
+    for (int i = 0;; ++i) {
+        if ((e = launch((i + 1) & 1)) != hipSuccess)
+            return hip_fail(h->err, e, "hipGraphLaunch");
+        if ((e = hipEventSynchronize(h->ev[i & 1])) != hipSuccess)
+            return hip_fail(h->err, e, "hipEventSynchronize");
+        *status = h->host_st[i & 1].status;
+        if (*status != kRun)
+            return CG_OK;
+    }
+}
+
+int read_state(cg_handle *h, DevState *st, DevState *out)
+{
+    hipError_t e;
+    if ((e = hipMemcpyAsync(&h->host_st[0], st, sizeof(DevState), hipMemcpyDeviceToHost, h->stream)) !=
+            hipSuccess ||
+        (e = hipStreamSynchronize(h->stream)) != hipSuccess)
+        return hip_fail(h->err, e, "state readback");
+    *out = h->host_st[0];
     return CG_OK;
 }
 
@@ -298,7 +430,7 @@ int cg_analyze_export(int format, int64_t n, const int32_t *ptr, const int32_t *
             st = build_plan(format, n, p0.data(), i0.data(), scatter_entries_override(), plan, err);
         if (st == CG_OK) {
             for (int b = 0; b < plan.nblocks; ++b) {
-                const ScatterBlock &bk = plan.blocks[b];
+                const ScatterBlock &bk = plan.blocks[b];   // block-id order
                 if (blk_color) blk_color[b] = plan.block_color[b];
                 if (blk_line0) blk_line0[b] = bk.line0;
                 if (blk_line1) blk_line1[b] = bk.line1;
@@ -331,14 +463,22 @@ int cg_create(cg_handle **out, int format, int64_t n, const int32_t *ptr, const 
     std::unique_ptr<cg_handle> h;
     try {
         h.reset(new cg_handle());
-        std::vector<int32_t> p0, i0;
-        int st = validate_and_normalise(format, n, ptr, idx, vals, index_base, flags, p0, i0, h->err);
+        std::vector<int32_t> p0, i0, perm;
+        int st = validate_and_normalise(format, n, ptr, idx, vals, index_base, flags, p0, i0, h->err, &perm);
         if (st == CG_OK && n > 0 && p0[n] > 0 && !vals) {
             h->err = "vals is NULL";
             st = CG_ERR_ARG;
         }
+        std::vector<double> pvals;
+        if (st == CG_OK && !perm.empty()) { // lower-triangle input: values follow the transposed layout
+            pvals.resize(perm.size());
+            for (size_t k = 0; k < perm.size(); ++k)
+                pvals[k] = vals[perm[k]];
+            vals = pvals.data();
+        }
         if (st == CG_OK)
             st = build_plan(format, n, p0.data(), i0.data(), scatter_entries_override(), h->plan, h->err);
+        h->mixed = (flags & CG_MIXED) != 0;
         if (st == CG_OK) {
             hipError_t e = hipGetDevice(&h->device);
             st = e == hipSuccess ? upload_all(h.get(), p0, i0, vals) : hip_fail(h->err, e, "hipGetDevice");
@@ -427,26 +567,9 @@ int cg_solve(cg_handle *h, const double *b, double *x, double tol, int32_t maxit
     if (e != hipSuccess)
         return done(hip_fail(h->err, e, "launch"));
     // iteration: two graph launches in flight, poll the older one's state
-    auto launch = [&](int slot) -> hipError_t {
-        hipError_t r = hipGraphLaunch(h->gexec, s);
-        if (r == hipSuccess)
-            r = hipMemcpyAsync(&h->host_st[slot], h->st, sizeof(DevState), hipMemcpyDeviceToHost, s);
-        if (r == hipSuccess)
-            r = hipEventRecord(h->ev[slot], s);
-        return r;
-    };
-    if ((e = launch(0)) != hipSuccess)
-        return done(hip_fail(h->err, e, "hipGraphLaunch"));
     int32_t status = kRun;
-    for (int i = 0;; ++i) {
-        if ((e = launch((i + 1) & 1)) != hipSuccess)
-            return done(hip_fail(h->err, e, "hipGraphLaunch"));
-        if ((e = hipEventSynchronize(h->ev[i & 1])) != hipSuccess)
-            return done(hip_fail(h->err, e, "hipEventSynchronize"));
-        status = h->host_st[i & 1].status;
-        if (status != kRun)
-            break;
-    }
+    if ((st = run_until_stop(h, h->gexec, h->st, &status)) != CG_OK)
+        return done(st);
     // finish: copy x out, true residual of the returned x
     if (status == kConverged || status == kMaxit || status == kBreakdown) {
         e = hipMemcpyAsync(x, h->xw, sizeof(double) * (size_t)n, hipMemcpyDeviceToDevice, s);
@@ -471,6 +594,108 @@ int cg_solve(cg_handle *h, const double *b, double *x, double tol, int32_t maxit
         h->err = "p'Ap <= 0 or non-finite: matrix not SPD";
     }
     return done(status_to_code(d.status));
+}
+
+int cg_solve_mixed(cg_handle *h, const double *b, double *x, double tol, int32_t maxit, double inner_tol,
+                   int32_t max_outer, cg_info *info)
+{
+    const auto t0 = std::chrono::steady_clock::now();
+    cg_info loc{};
+    if (!info)
+        info = &loc;
+    std::memset(info, 0, sizeof(*info));
+    auto done = [&](int code) {
+        info->status = code;
+        info->ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        return code;
+    };
+    if (!h)
+        return done(CG_ERR_ARG);
+    if (!h->mixed) {
+        h->err = "handle was created without CG_MIXED";
+        return done(CG_ERR_ARG);
+    }
+    if (!(tol >= 0.0) || maxit < 0 || !(inner_tol > 0.0 && inner_tol < 1.0) || max_outer < 1) {
+        h->err = "need tol >= 0, maxit >= 0, 0 < inner_tol < 1, max_outer >= 1";
+        return done(CG_ERR_ARG);
+    }
+    const int n = h->dm.n;
+    if (n == 0)
+        return done(CG_OK);
+    if (!b || !x) {
+        h->err = "b / x NULL";
+        return done(CG_ERR_ARG);
+    }
+    hipStream_t s = h->stream;
+    int st = build_graph_generic(h, true);
+    if (st != CG_OK)
+        return done(st);
+    // outer start: r = b - A x0, ||b||, ||r|| (FP64 product)
+    launch_spmv(h->dm, x, h->q, h->sig_spmv, IterCtx{}, s);
+    launch_init_vec(h->dm, b, x, h->q, h->rout, h->p, h->xw, h->rho, h->bb, s);
+    launch_init_state(h->dm, h->st, h->bb, h->rho, tol, maxit, s);
+    DevState out;
+    if ((st = read_state(h, h->st, &out)) != CG_OK)
+        return done(st);
+    if (out.status == kNonfinite) {
+        h->err = "b has a non-finite entry";
+        return done(CG_ERR_NONFINITE);
+    }
+    if (out.status == kZeroRhs) {
+        launch_fill(n, x, 0.0, s);
+        (void)hipStreamSynchronize(s);
+        return done(CG_OK);
+    }
+    const double nb = out.nb;
+    double relres = std::sqrt(out.rho) / nb;
+    int total = 0, outer = 0, code = CG_NOT_CONVERGED;
+    while (true) {
+        if (relres <= tol) {
+            code = CG_OK;
+            break;
+        }
+        if (outer >= max_outer || total >= maxit)
+            break;
+        // inner solve of (D^-1/2 A D^-1/2) c = D^-1/2 r in FP32 storage
+        launch_mx_init(h->dm, h->rout, h->r, h->p32, h->p, h->rho, h->bb, s);
+        launch_init_state(h->dm, h->st_in, h->bb, h->rho, inner_tol, maxit - total, s);
+        int32_t status = kRun;
+        if ((st = run_until_stop(h, h->gexec32, h->st_in, &status)) != CG_OK)
+            return done(st);
+        DevState in;
+        if ((st = read_state(h, h->st_in, &in)) != CG_OK)
+            return done(st);
+        total += in.iters;
+        ++outer;
+        if (in.status == kBreakdown && in.iters == 0) {
+            h->err = "inner FP32 solve broke down before any step";
+            code = CG_ERR_BREAKDOWN;
+            break;
+        }
+        // x += D^-1/2 c; r = b - A x (FP64 product), true residual norm
+        launch_mx_apply(h->dm, h->xw, h->p, s);
+        launch_spmv(h->dm, h->xw, h->q, h->sig_spmv, IterCtx{}, s);
+        launch_init_vec(h->dm, b, h->xw, h->q, h->rout, h->p, h->xw, h->rho, h->bb, s);
+        launch_outer_norm(h->dm, h->st, h->rho, s);
+        if ((st = read_state(h, h->st, &out)) != CG_OK)
+            return done(st);
+        relres = std::sqrt(out.rho) / nb;
+        if (!std::isfinite(relres)) {
+            h->err = "refinement produced a non-finite residual";
+            code = CG_ERR_BREAKDOWN;
+            break;
+        }
+    }
+    hipError_t e = hipMemcpyAsync(x, h->xw, sizeof(double) * (size_t)n, hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(s);
+    if (e != hipSuccess)
+        return done(hip_fail(h->err, e, "copy-out"));
+    info->iters = total;
+    info->outer = outer;
+    info->relres = relres;
+    info->relres_true = relres;
+    return done(code);
 }
 
 int cg_get_stats(const cg_handle *h, cg_plan_stats *stats)

@@ -1,0 +1,58 @@
+// Device helpers shared by the kernel files: XCD-aware workgroup order and
+// deterministic (fixed-tree) reductions.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "plan.h"
+
+namespace cgmi {
+namespace dev {
+
+constexpr int kWaves = kBlock / 64;
+constexpr int kXcds = 8; // MI355X: workgroups are dealt round-robin to 8 XCDs, each with its own L2
+
+// Workgroup id -> logical chunk, so that each XCD works on one contiguous
+// range of chunks (neighbouring rows share x and y lines in that XCD's L2).
+__device__ __forceinline__ int xcd_remap(int bid, int nblk)
+{
+    const int per = nblk / kXcds, rem = nblk % kXcds;
+    const int x = bid % kXcds, i = bid / kXcds;
+    return x * per + min(x, rem) + i;
+}
+
+template <int W>
+__device__ __forceinline__ double group_sum(double v)
+{
+#pragma unroll
+    for (int o = W / 2; o > 0; o >>= 1)
+        v += __shfl_xor(v, o, W);
+    return v; // butterfly: every lane of the group holds the same bits
+}
+
+// Sum over the workgroup; every thread returns the same bits.
+__device__ __forceinline__ double block_sum(double v, double *red)
+{
+    v = group_sum<64>(v);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0)
+        red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double t = red[0];
+#pragma unroll
+    for (int w = 1; w < kWaves; ++w)
+        t += red[w];
+    return t;
+}
+
+// Sum of m per-workgroup partials, identical in every workgroup.
+__device__ __forceinline__ double reduce_partials(const double *__restrict__ part, int m, double *red)
+{
+    double s = 0.0;
+    for (int i = threadIdx.x; i < m; i += kBlock)
+        s += part[i];
+    return block_sum(s, red);
+}
+
+} // namespace dev
+} // namespace cgmi

@@ -47,6 +47,8 @@ struct DevMatrix {
     const int32_t *ptr = nullptr;
     const int32_t *idx = nullptr;
     const double *val = nullptr;
+    const float *val32 = nullptr;  // mixed precision: values of D^-1/2 A D^-1/2 in FP32
+    const double *dscale = nullptr; // mixed precision: D^-1/2
     // CSR
     int csr_blocks = 0, csr_rows_per_block = 0;
     bool csr_stream = false;
@@ -54,16 +56,18 @@ struct DevMatrix {
     const int32_t *csr_rb = nullptr;
     // scatter
     int nblocks = 0, ncolors = 0, lds_entries = 0, lds_lines = 0, max_slots = 0;
-    std::vector<int32_t> color_off; // host copy
-    const ScatterBlock *blocks = nullptr;
-    const int32_t *phase_blocks = nullptr;
+    std::vector<int32_t> color_off;      // host copy: blocks per colour
+    std::vector<int32_t> color_slot_off; // host copy: slots per colour (device arrays in colour order)
+    int scatter_wgs = 0;                 // workgroups of k_scatter_sums (= dot partials)
+    const ScatterBlock *blocks = nullptr; // in colour order; slot0 / id refer to the colour-ordered arrays
+    double *part = nullptr;              // parked slot sums (colours >= 1)
     const int32_t *slot_target = nullptr;
     const uint8_t *slot_flag = nullptr;
     const uint16_t *seg = nullptr;
     const uint16_t *tl = nullptr;
     // vectors
     int vec_blocks = 0, vec_chunk = 0;
-    int spmv_blocks() const { return format == kCsr ? csr_blocks : nblocks; }
+    int spmv_blocks() const { return format == kCsr ? csr_blocks : scatter_wgs; }
 };
 
 // Iteration context: null st = plain product (no gating, p'q partials still
@@ -77,12 +81,25 @@ struct IterCtx {
 // y = A x; writes spmv_blocks() partials of x'y into sig_part.
 void launch_spmv(const DevMatrix &m, const double *x, double *y, double *sig_part, const IterCtx &ctx,
                  hipStream_t s);
+// y = A32 x with the FP32 copy of the scaled values (FP64 arithmetic).
+void launch_spmv32(const DevMatrix &m, const float *x, double *y, double *sig_part, const IterCtx &c,
+                   hipStream_t s);
 // r -= alpha q with alpha = rho / sum(sig_part); rho_part <- partials of r'r.
 void launch_update_r(const DevMatrix &m, double *r, const double *q, DevState *st, const double *sig_part,
                      double *rho_part, hipStream_t s);
 // x += alpha p; p = r + beta p (unless converged) with beta = sum(rho_part) / rho.
 void launch_update_xp(const DevMatrix &m, double *x, double *p, const double *r, DevState *st,
                       const double *rho_part, hipStream_t s);
+// mixed precision: the same update with p stored in FP32
+void launch_update_xp32(const DevMatrix &m, double *x, float *p, const double *r, DevState *st,
+                        const double *rho_part, hipStream_t s);
+// mixed precision: rh = D^-1/2 r_out, p = fl32(rh), c = 0, partials of rh'rh
+void launch_mx_init(const DevMatrix &m, const double *r_out, double *rh, float *p, double *c, double *rho_part,
+                    double *bb_part, hipStream_t s);
+// mixed precision: x += D^-1/2 c
+void launch_mx_apply(const DevMatrix &m, double *x, const double *c, hipStream_t s);
+// st->rho = sum(rho_part), st->res_true = sqrt(st->rho) / st->nb (one workgroup)
+void launch_outer_norm(const DevMatrix &m, DevState *st, const double *rho_part, hipStream_t s);
 // convergence / maxit test of the current residual (one workgroup).
 void launch_check(const DevMatrix &m, DevState *st, const double *rho_part, hipStream_t s);
 // r = b - q, p = r, xw = x0; partials of r'r and b'b.

@@ -7,6 +7,7 @@
 // floating-point atomics anywhere; the only cross-workgroup communication is
 // through per-workgroup partials read by a later kernel.
 #include "kernels.h"
+#include "devutil.h"
 
 #include <cmath>
 
@@ -14,50 +15,7 @@ namespace cgmi {
 
 namespace {
 
-constexpr int kWaves = kBlock / 64;
-constexpr int kXcds = 8; // MI355X: workgroups are dealt round-robin to 8 XCDs, each with its own L2
-
-// Workgroup id -> logical chunk, so that each XCD works on one contiguous
-// range of chunks (neighbouring rows share x and y lines in that XCD's L2).
-__device__ __forceinline__ int xcd_remap(int bid, int nblk)
-{
-    const int per = nblk / kXcds, rem = nblk % kXcds;
-    const int x = bid % kXcds, i = bid / kXcds;
-    return x * per + min(x, rem) + i;
-}
-
-template <int W>
-__device__ __forceinline__ double group_sum(double v)
-{
-#pragma unroll
-    for (int o = W / 2; o > 0; o >>= 1)
-        v += __shfl_xor(v, o, W);
-    return v; // butterfly: every lane of the group holds the same bits
-}
-
-// Sum over the workgroup; every thread returns the same bits.
-__device__ __forceinline__ double block_sum(double v, double *red)
-{
-    v = group_sum<64>(v);
-    __syncthreads();
-    if ((threadIdx.x & 63) == 0)
-        red[threadIdx.x >> 6] = v;
-    __syncthreads();
-    double t = red[0];
-#pragma unroll
-    for (int w = 1; w < kWaves; ++w)
-        t += red[w];
-    return t;
-}
-
-// Sum of m per-workgroup partials, identical in every workgroup.
-__device__ __forceinline__ double reduce_partials(const double *__restrict__ part, int m, double *red)
-{
-    double s = 0.0;
-    for (int i = threadIdx.x; i < m; i += kBlock)
-        s += part[i];
-    return block_sum(s, red);
-}
+using namespace dev;
 
 // Start of an iteration (before its product): stop when the current residual
 // meets the tolerance (decided and published by the previous x/p update, or by
@@ -96,13 +54,14 @@ __device__ bool iter_gate(DevState *st)
 // workgroup's contiguous range visited in passes of (256 / W) * U rows.
 // Index / value streams use non-temporal loads (read once); x is gathered
 // through the cache.  Fused epilogue: partial of x'y.
-template <int W, int U>
+// VT / PT: storage type of the values / of the input vector (double, or float
+// for the FP32 product of mixed-precision refinement); arithmetic is FP64.
+template <int W, int U, class VT, class PT>
 __global__ __launch_bounds__(kBlock) void k_spmv_csr(int n, int rows_per_block, const int32_t *__restrict__ ptr,
                                                      const int32_t *__restrict__ col,
-                                                     const double *__restrict__ val,
-                                                     const double *__restrict__ x, double *__restrict__ y,
-                                                     double *__restrict__ sig_part, DevState *st,
-                                                     const double *__restrict__ rho_part, int n_rho)
+                                                     const VT *__restrict__ val,
+                                                     const PT *__restrict__ x, double *__restrict__ y,
+                                                     double *__restrict__ sig_part, DevState *st)
 {
     __shared__ double red[kWaves];
     if (st != nullptr && !iter_gate(st))
@@ -136,13 +95,13 @@ __global__ __launch_bounds__(kBlock) void k_spmv_csr(int n, int rows_per_block, 
                 const bool ok = k < re[u];
                 any |= ok;
                 c[u] = ok ? __builtin_nontemporal_load(col + k) : -1;
-                v[u] = ok ? __builtin_nontemporal_load(val + k) : 0.0;
+                v[u] = ok ? (double)__builtin_nontemporal_load(val + k) : 0.0;
             }
             if (!any)
                 break;
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                const double xv = c[u] >= 0 ? x[c[u]] : 0.0;
+                const double xv = c[u] >= 0 ? (double)x[c[u]] : 0.0;
                 acc[u] = fma(v[u], xv, acc[u]);
             }
         }
@@ -158,7 +117,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv_csr(int n, int rows_per_block, 
         }
         if (lane < U && row < r1) {
             y[row] = yv;
-            sig = fma(x[row], yv, sig);
+            sig = fma((double)x[row], yv, sig);
         }
     }
     sig = block_sum(sig, red);
@@ -174,21 +133,21 @@ __global__ __launch_bounds__(kBlock) void k_spmv_csr(int n, int rows_per_block, 
 // each row is summed left to right by one thread -- the same order as the
 // textbook loop, so y is bit-identical to a serial row-by-row product.  A row
 // longer than a block is summed by the whole workgroup (fixed tree).
+template <class VT, class PT>
 __global__ __launch_bounds__(kBlock) void k_spmv_csr_rows(int nrb, const int32_t *__restrict__ rb_row,
                                                           const int32_t *__restrict__ ptr,
                                                           const int32_t *__restrict__ col,
-                                                          const double *__restrict__ val,
-                                                          const double *__restrict__ x, double *__restrict__ y,
-                                                          double *__restrict__ sig_part, DevState *st,
-                                                          const double *__restrict__ rho_part, int n_rho)
+                                                          const VT *__restrict__ val,
+                                                          const PT *__restrict__ x, double *__restrict__ y,
+                                                          double *__restrict__ sig_part, DevState *st)
 {
     constexpr int E = kStreamPerThread;
     __shared__ double prod[kStreamEntries];
     __shared__ int32_t lptr[kStreamRows + 1];
     __shared__ double red[kWaves];
+    const int wg = xcd_remap(blockIdx.x, gridDim.x);
     if (st != nullptr && !iter_gate(st))
         return;
-    const int wg = xcd_remap(blockIdx.x, gridDim.x);
     const int b0 = (int)((int64_t)wg * nrb / gridDim.x);
     const int b1 = (int)((int64_t)(wg + 1) * nrb / gridDim.x);
     const int t = threadIdx.x;
@@ -200,11 +159,12 @@ __global__ __launch_bounds__(kBlock) void k_spmv_csr_rows(int nrb, const int32_t
         if (e1 - e0 > kStreamEntries) { // one long row
             double a = 0.0;
             for (int e = e0 + t; e < e1; e += kBlock)
-                a = fma(__builtin_nontemporal_load(val + e), x[__builtin_nontemporal_load(col + e)], a);
+                a = fma((double)__builtin_nontemporal_load(val + e), (double)x[__builtin_nontemporal_load(col + e)],
+                        a);
             a = block_sum(a, red);
             if (t == 0) {
                 y[r0] = a;
-                sig = fma(x[r0], a, sig);
+                sig = fma((double)x[r0], a, sig);
             }
             continue;
         }
@@ -215,7 +175,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv_csr_rows(int nrb, const int32_t
             const int e = e0 + t + m * kBlock;
             const bool ok = e < e1;
             c[m] = ok ? __builtin_nontemporal_load(col + e) : -1;
-            v[m] = ok ? __builtin_nontemporal_load(val + e) : 0.0;
+            v[m] = ok ? (double)__builtin_nontemporal_load(val + e) : 0.0;
         }
         if (t < nr)
             lptr[t + 1] = __builtin_nontemporal_load(ptr + r0 + t + 1) - e0;
@@ -224,7 +184,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv_csr_rows(int nrb, const int32_t
 #pragma unroll
         for (int m = 0; m < E; ++m)
             if (c[m] >= 0)
-                prod[t + m * kBlock] = v[m] * x[c[m]];
+                prod[t + m * kBlock] = v[m] * (double)x[c[m]];
         __syncthreads();
         if (t < nr) {
             double a = 0.0;
@@ -232,7 +192,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv_csr_rows(int nrb, const int32_t
             for (int k = lptr[t]; k < k1; ++k)
                 a += prod[k];
             y[r0 + t] = a;
-            sig = fma(x[r0 + t], a, sig);
+            sig = fma((double)x[r0 + t], a, sig);
         }
         __syncthreads();
     }
@@ -241,36 +201,39 @@ __global__ __launch_bounds__(kBlock) void k_spmv_csr_rows(int nrb, const int32_t
         sig_part[wg] = sig;
 }
 
-// --------------------------------------------------- colour-phase scatter
-// One workgroup per scatter block (plan.h), one launch per colour.  Every
-// global load that does not depend on another is issued first: the block's
-// line pointers, x of its own lines, its contribution list (-> LDS), its
-// <= 2048 index / value pairs (8 per thread, coalesced, non-temporal) and its
-// write-slot descriptors (SU per thread).  Then the gathers (x at the column
-// indices for the symmetric row part; y and x at the slot targets), then all
-// arithmetic from LDS:
-//   sp[e] = a_e x_line(e)   product bound for another row (mirror / column)
-//   gp[e] = a_e x_idx(e)    symmetric CSR: product of the stored row itself
-// and one thread per slot sums its products in the plan's order and stores
-// (first writer of that row) or adds (later colour) y; the last writer adds
-// x_i y_i to the workgroup's dot partial.  No atomics.
-template <bool SYM, int SU>
-__global__ __launch_bounds__(kBlock) void k_spmv_scatter(
-    const int32_t *__restrict__ ptr, const int32_t *__restrict__ idx, const double *__restrict__ val,
-    const double *__restrict__ x, double *__restrict__ y, double *__restrict__ sig_part,
-    const ScatterBlock *__restrict__ blocks, const int32_t *__restrict__ phase_blocks,
-    const int32_t *__restrict__ slot_target, const uint8_t *__restrict__ slot_flag,
-    const uint16_t *__restrict__ seg, const uint16_t *__restrict__ tl, int lds_entries, int lds_lines,
-    DevState *st, int gate)
+// ------------------------------------------------- coloured scatter
+// Product for the formats whose entries write rows other than their own
+// (symmetric CSR: the mirrored triangle; CSC: every column).  Two kernels:
+//
+// k_scatter_sums -- all blocks of all colours at once (blocks stored in
+//   colour order, each workgroup walks a contiguous range).  Per block every
+//   independent global load is issued first (line pointers, x of the own
+//   lines, the contribution list -> LDS, <= 2048 index / value pairs, 8 per
+//   thread, and the write-slot descriptors, SU per thread); then the gathers;
+//   then from LDS
+//     sp[e] = a_e x_line(e)   product bound for another row (mirror / column)
+//     gp[e] = a_e x_idx(e)    symmetric CSR: product of the stored row itself
+//   and every slot's sum in the plan's fixed order.  Colour-0 blocks are the
+//   first writers of all their rows and store y directly; the others park
+//   their slot sums in `part`.  The dot x'y is linear in the slot sums, so
+//   each workgroup accumulates sum_slots x_target * sum here, before any y
+//   is final.
+// k_scatter_combine -- one launch per later colour: y_t (+)= part_s over the
+//   colour's slots (contiguous, coalesced).  Blocks of one colour write
+//   disjoint rows, so no atomics are needed; colours run in order.
+template <bool SYM, int SU, class VT, class PT>
+__global__ __launch_bounds__(kBlock) void k_scatter_sums(
+    const int32_t *__restrict__ ptr, const int32_t *__restrict__ idx, const VT *__restrict__ val,
+    const PT *__restrict__ x, double *__restrict__ y, double *__restrict__ part, double *__restrict__ sig_part,
+    const ScatterBlock *__restrict__ blocks, int nblocks, const int32_t *__restrict__ slot_target,
+    const uint16_t *__restrict__ seg, const uint16_t *__restrict__ tl, int lds_entries, int lds_lines, DevState *st)
 {
     constexpr int E = kMaxScatterEntries / kBlock; // entries per thread
     extern __shared__ double lds[];
     __shared__ double red[kWaves];
-    if (st != nullptr) {
-        if (gate ? !iter_gate(st) : st->status != kRun)
-            return;
-    }
-    const ScatterBlock bk = blocks[phase_blocks[xcd_remap(blockIdx.x, gridDim.x)]];
+    const int wg = xcd_remap(blockIdx.x, gridDim.x);
+    if (st != nullptr && !iter_gate(st))
+        return;
     double *sp = lds;
     double *gp = sp + lds_entries;
     double *xl = gp + (SYM ? lds_entries : 0);
@@ -278,92 +241,123 @@ __global__ __launch_bounds__(kBlock) void k_spmv_scatter(
     uint16_t *lm = reinterpret_cast<uint16_t *>(lp + lds_lines + 1);
     uint16_t *tv = lm + lds_entries;
     const int t = threadIdx.x;
-    const int nl = bk.line1 - bk.line0, ne = bk.k1 - bk.k0;
-
-    // ---- independent loads
-    for (int l = t; l <= nl; l += kBlock)
-        lp[l] = min(max(ptr[bk.line0 + l] - bk.k0, 0), ne);
-    for (int l = t; l < nl; l += kBlock)
-        xl[l] = x[bk.line0 + l];
-    for (int i = t; i < bk.ntl; i += kBlock)
-        tv[i] = tl[bk.tl0 + i];
-    int c[E];
-    double v[E];
+    const int b0 = (int)((int64_t)wg * nblocks / gridDim.x);
+    const int b1 = (int)((int64_t)(wg + 1) * nblocks / gridDim.x);
+    double sig = 0.0;
+    for (int b = b0; b < b1; ++b) {
+        const ScatterBlock bk = blocks[b];
+        const int nl = bk.line1 - bk.line0, ne = bk.k1 - bk.k0;
+        // ---- independent loads
+        for (int l = t; l <= nl; l += kBlock)
+            lp[l] = min(max(ptr[bk.line0 + l] - bk.k0, 0), ne);
+        for (int l = t; l < nl; l += kBlock)
+            xl[l] = (double)x[bk.line0 + l];
+        for (int i = t; i < bk.ntl; i += kBlock)
+            tv[i] = tl[bk.tl0 + i];
+        int c[E];
+        double v[E];
 #pragma unroll
-    for (int m = 0; m < E; ++m) {
-        const int e = t + m * kBlock;
-        const bool ok = e < ne;
-        c[m] = ok ? __builtin_nontemporal_load(idx + bk.k0 + e) : -1;
-        v[m] = ok ? __builtin_nontemporal_load(val + bk.k0 + e) : 0.0;
-    }
-    int tg[SU], lo[SU], hi[SU];
-    unsigned fl[SU];
-    const uint16_t *sg = seg + bk.slot0 + bk.id;
+        for (int m = 0; m < E; ++m) {
+            const int e = t + m * kBlock;
+            const bool ok = e < ne;
+            c[m] = ok ? __builtin_nontemporal_load(idx + bk.k0 + e) : -1;
+            v[m] = ok ? (double)__builtin_nontemporal_load(val + bk.k0 + e) : 0.0;
+        }
+        int tg[SU], lo[SU], hi[SU];
+        const uint16_t *sg = seg + bk.slot0 + bk.id;
 #pragma unroll
-    for (int u = 0; u < SU; ++u) {
-        const int s = t + u * kBlock;
-        const bool ok = s < bk.nslots;
-        tg[u] = ok ? slot_target[bk.slot0 + s] : -1;
-        fl[u] = ok ? slot_flag[bk.slot0 + s] : 0u;
-        lo[u] = ok ? sg[s] : 0;
-        hi[u] = ok ? sg[s + 1] : 0;
-    }
-    // ---- gathers
-    double xg[E];
-    if (SYM) {
+        for (int u = 0; u < SU; ++u) {
+            const int s = t + u * kBlock;
+            const bool ok = s < bk.nslots;
+            tg[u] = ok ? slot_target[bk.slot0 + s] : -1;
+            lo[u] = ok ? sg[s] : 0;
+            hi[u] = ok ? sg[s + 1] : 0;
+        }
+        // ---- gathers
+        double xg[E];
+        if (SYM) {
 #pragma unroll
-        for (int m = 0; m < E; ++m)
-            xg[m] = c[m] >= 0 ? x[c[m]] : 0.0;
-    }
-    double yo[SU], xt[SU];
+            for (int m = 0; m < E; ++m)
+                xg[m] = c[m] >= 0 ? (double)x[c[m]] : 0.0;
+        }
+        double xt[SU];
 #pragma unroll
-    for (int u = 0; u < SU; ++u) {
-        yo[u] = (tg[u] >= 0 && !(fl[u] & kSlotFirst)) ? y[tg[u]] : 0.0;
-        xt[u] = (tg[u] >= 0 && (fl[u] & kSlotLast)) ? x[tg[u]] : 0.0;
-    }
-    __syncthreads();
-    // ---- line of every entry
-    for (int l = t; l < nl; l += kBlock)
-        for (int k = lp[l]; k < lp[l + 1]; ++k)
-            lm[k] = (uint16_t)l;
-    __syncthreads();
-    // ---- products
+        for (int u = 0; u < SU; ++u)
+            xt[u] = tg[u] >= 0 ? (double)x[tg[u]] : 0.0;
+        __syncthreads();
+        // ---- line of every entry
+        for (int l = t; l < nl; l += kBlock)
+            for (int k = lp[l]; k < lp[l + 1]; ++k)
+                lm[k] = (uint16_t)l;
+        __syncthreads();
+        // ---- products
 #pragma unroll
-    for (int m = 0; m < E; ++m) {
-        const int e = t + m * kBlock;
-        if (c[m] >= 0) {
-            const int l = lm[e];
-            if (SYM) {
-                gp[e] = v[m] * xg[m];
-                if (c[m] != bk.line0 + l)
+        for (int m = 0; m < E; ++m) {
+            const int e = t + m * kBlock;
+            if (c[m] >= 0) {
+                const int l = lm[e];
+                if (SYM) {
+                    gp[e] = v[m] * xg[m];
+                    if (c[m] != bk.line0 + l)
+                        sp[e] = v[m] * xl[l];
+                } else {
                     sp[e] = v[m] * xl[l];
-            } else {
-                sp[e] = v[m] * xl[l];
+                }
             }
         }
-    }
-    __syncthreads();
-    // ---- write slots
-    double sig = 0.0;
+        __syncthreads();
+        // ---- slot sums
+        const bool first_colour = bk.pad == 0;
 #pragma unroll
-    for (int u = 0; u < SU; ++u) {
-        if (tg[u] < 0)
-            continue;
-        const int s = t + u * kBlock;
-        double a = 0.0;
-        if (SYM && s < nl) // own row: its stored entries, left to right
-            for (int k = lp[s]; k < lp[s + 1]; ++k)
-                a += gp[k];
-        for (int i = lo[u]; i < hi[u]; ++i)
-            a += sp[tv[i]];
-        const double yv = (fl[u] & kSlotFirst) ? a : yo[u] + a;
-        y[tg[u]] = yv;
-        if (fl[u] & kSlotLast)
-            sig = fma(xt[u], yv, sig);
+        for (int u = 0; u < SU; ++u) {
+            if (tg[u] < 0)
+                continue;
+            const int s = t + u * kBlock;
+            double a = 0.0;
+            if (SYM && s < nl) // own row: its stored entries, left to right
+                for (int k = lp[s]; k < lp[s + 1]; ++k)
+                    a += gp[k];
+            for (int i = lo[u]; i < hi[u]; ++i)
+                a += sp[tv[i]];
+            if (first_colour)
+                y[tg[u]] = a;
+            else
+                part[bk.slot0 + s] = a;
+            sig = fma(xt[u], a, sig);
+        }
+        __syncthreads(); // LDS is reused by the next block
     }
     sig = block_sum(sig, red);
     if (t == 0)
-        sig_part[bk.id] = sig;
+        sig_part[wg] = sig;
+}
+
+__global__ __launch_bounds__(kBlock) void k_scatter_combine(int nslots, const int32_t *__restrict__ slot_target,
+                                                            const uint8_t *__restrict__ slot_flag,
+                                                            const double *__restrict__ part, double *__restrict__ y,
+                                                            const DevState *st)
+{
+    if (st != nullptr && st->status != kRun)
+        return;
+    const int i0 = (blockIdx.x * kBlock) * 4 + threadIdx.x;
+    int tg[4];
+    unsigned fl[4];
+    double pv[4], yo[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int s = i0 + u * kBlock;
+        const bool ok = s < nslots;
+        tg[u] = ok ? __builtin_nontemporal_load(slot_target + s) : -1;
+        fl[u] = ok ? slot_flag[s] : 0u;
+        pv[u] = ok ? __builtin_nontemporal_load(part + s) : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+        yo[u] = (tg[u] >= 0 && !(fl[u] & kSlotFirst)) ? y[tg[u]] : 0.0;
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+        if (tg[u] >= 0)
+            y[tg[u]] = (fl[u] & kSlotFirst) ? pv[u] : yo[u] + pv[u];
 }
 
 // ------------------------------------------------------ vector kernels
@@ -429,8 +423,11 @@ __global__ __launch_bounds__(kBlock) void k_update_r(int n, int chunk, double *_
 // x += alpha p and p = r + beta p; workgroup 0 publishes r'r and the
 // convergence decision for the next iteration's gate (no workgroup of this
 // kernel reads those two fields).
+// PT: storage type of p (double; float for the inner solves of mixed
+// precision, where p is rounded to FP32 after the FP64 update).
+template <class PT>
 __global__ __launch_bounds__(kBlock) void k_update_xp(int n, int chunk, double *__restrict__ x,
-                                                      double *__restrict__ p, const double *__restrict__ r,
+                                                      PT *__restrict__ p, const double *__restrict__ r,
                                                       DevState *st, const double *__restrict__ rho_part,
                                                       int n_rho)
 {
@@ -445,7 +442,7 @@ __global__ __launch_bounds__(kBlock) void k_update_xp(int n, int chunk, double *
     for (int u = 0; u < kPre; ++u) {
         const int i = i0 + t + u * kBlock;
         const bool ok = i < i1;
-        pv[u] = ok ? p[i] : 0.0;
+        pv[u] = ok ? (double)p[i] : 0.0;
         xv[u] = ok ? x[i] : 0.0;
         rv[u] = ok ? r[i] : 0.0;
     }
@@ -463,14 +460,60 @@ __global__ __launch_bounds__(kBlock) void k_update_xp(int n, int chunk, double *
         if (i < i1) {
             x[i] = fma(alpha, pv[u], xv[u]);
             if (!conv)
-                p[i] = fma(beta, pv[u], rv[u]);
+                p[i] = (PT)fma(beta, pv[u], rv[u]);
         }
     }
     for (int i = i0 + t + kPre * kBlock; i < i1; i += kBlock) {
-        const double pi = p[i];
+        const double pi = (double)p[i];
         x[i] = fma(alpha, pi, x[i]);
         if (!conv)
-            p[i] = fma(beta, pi, r[i]);
+            p[i] = (PT)fma(beta, pi, r[i]);
+    }
+}
+
+// Mixed precision, start of an inner solve: rh = s .* r_out (scaled
+// residual, FP64), p = fl32(rh), c = 0; partials of rh'rh (into both arrays:
+// the inner solve's "b" is rh).
+__global__ __launch_bounds__(kBlock) void k_mx_init(int n, int chunk, const double *__restrict__ r_out,
+                                                    const double *__restrict__ s, double *__restrict__ rh,
+                                                    float *__restrict__ p, double *__restrict__ c,
+                                                    double *__restrict__ rho_part, double *__restrict__ bb_part)
+{
+    __shared__ double red[kWaves];
+    const int blk = xcd_remap(blockIdx.x, gridDim.x);
+    const int i0 = blk * chunk, i1 = min(n, i0 + chunk);
+    double a = 0.0;
+    for (int i = i0 + threadIdx.x; i < i1; i += kBlock) {
+        const double v = s[i] * r_out[i];
+        rh[i] = v;
+        p[i] = (float)v;
+        c[i] = 0.0;
+        a = fma(v, v, a);
+    }
+    a = block_sum(a, red);
+    if (threadIdx.x == 0) {
+        rho_part[blk] = a;
+        bb_part[blk] = a;
+    }
+}
+
+// Mixed precision, end of an inner solve: x += s .* c.
+__global__ __launch_bounds__(kBlock) void k_mx_apply(int n, double *__restrict__ x, const double *__restrict__ s,
+                                                     const double *__restrict__ c)
+{
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i < n)
+        x[i] = fma(s[i], c[i], x[i]);
+}
+
+// Outer residual norm: st->rho = sum of partials, st->res_true = sqrt / nb.
+__global__ __launch_bounds__(kBlock) void k_outer_norm(DevState *st, const double *__restrict__ part, int m)
+{
+    __shared__ double red[kWaves];
+    const double rho = reduce_partials(part, m, red);
+    if (threadIdx.x == 0) {
+        st->rho = rho;
+        st->res_true = st->nb > 0.0 ? sqrt(rho) / st->nb : 0.0;
     }
 }
 
@@ -560,62 +603,80 @@ __global__ __launch_bounds__(kBlock) void k_fill(int n, double *__restrict__ x, 
         x[i] = v;
 }
 
-template <int W>
-void csr_launch(const DevMatrix &m, const double *x, double *y, double *sig, const IterCtx &c, hipStream_t s)
+template <int W, class VT, class PT>
+void csr_launch(const DevMatrix &m, const VT *val, const PT *x, double *y, double *sig, const IterCtx &c,
+                hipStream_t s)
 {
-    hipLaunchKernelGGL((k_spmv_csr<W, 4>), dim3(m.csr_blocks), dim3(kBlock), 0, s, m.n, m.csr_rows_per_block,
-                       m.ptr, m.idx, m.val, x, y, sig, c.st, c.rho_part, c.n_rho);
+    hipLaunchKernelGGL((k_spmv_csr<W, 4, VT, PT>), dim3(m.csr_blocks), dim3(kBlock), 0, s, m.n,
+                       m.csr_rows_per_block, m.ptr, m.idx, val, x, y, sig, c.st);
 }
 
-template <bool SYM, int SU>
-void scatter_launch(const DevMatrix &m, const double *x, double *y, double *sig, const IterCtx &c, hipStream_t s)
+template <bool SYM, int SU, class VT, class PT>
+void scatter_launch(const DevMatrix &m, const VT *val, const PT *x, double *y, double *sig, const IterCtx &c,
+                    hipStream_t s)
 {
     const size_t E = (size_t)m.lds_entries, R = (size_t)m.lds_lines;
     const size_t lds = E * 8 * (SYM ? 2 : 1) + R * 8 + (R + 1) * 4 + 2 * E * 2;
-    for (int col = 0; col < m.ncolors; ++col) {
-        const int nb = m.color_off[col + 1] - m.color_off[col];
-        hipLaunchKernelGGL((k_spmv_scatter<SYM, SU>), dim3(nb), dim3(kBlock), lds, s, m.ptr, m.idx, m.val, x, y,
-                           sig, m.blocks, m.phase_blocks + m.color_off[col], m.slot_target, m.slot_flag, m.seg,
-                           m.tl, m.lds_entries, m.lds_lines, c.st, col == 0 ? 1 : 0);
+    hipLaunchKernelGGL((k_scatter_sums<SYM, SU, VT, PT>), dim3(m.scatter_wgs), dim3(kBlock), lds, s, m.ptr, m.idx,
+                       val, x, y, m.part, sig, m.blocks, m.nblocks, m.slot_target, m.seg, m.tl, m.lds_entries,
+                       m.lds_lines, c.st);
+    for (int col = 1; col < m.ncolors; ++col) {
+        const int s0 = m.color_slot_off[col], ns = m.color_slot_off[col + 1] - s0;
+        if (ns > 0)
+            hipLaunchKernelGGL(k_scatter_combine, dim3((ns + 4 * kBlock - 1) / (4 * kBlock)), dim3(kBlock), 0, s,
+                               ns, m.slot_target + s0, m.slot_flag + s0, m.part + s0, y, c.st);
     }
 }
 
-template <bool SYM>
-void scatter_dispatch(const DevMatrix &m, const double *x, double *y, double *sig, const IterCtx &c, hipStream_t s)
+template <bool SYM, class VT, class PT>
+void scatter_dispatch(const DevMatrix &m, const VT *val, const PT *x, double *y, double *sig, const IterCtx &c,
+                      hipStream_t s)
 {
     // write slots held in registers: SU per thread must cover the largest block
     if (m.max_slots <= 2 * kBlock)
-        scatter_launch<SYM, 2>(m, x, y, sig, c, s);
+        scatter_launch<SYM, 2>(m, val, x, y, sig, c, s);
     else if (m.max_slots <= 4 * kBlock)
-        scatter_launch<SYM, 4>(m, x, y, sig, c, s);
+        scatter_launch<SYM, 4>(m, val, x, y, sig, c, s);
     else if (m.max_slots <= 6 * kBlock)
-        scatter_launch<SYM, 6>(m, x, y, sig, c, s);
+        scatter_launch<SYM, 6>(m, val, x, y, sig, c, s);
     else
-        scatter_launch<SYM, 9>(m, x, y, sig, c, s);
+        scatter_launch<SYM, 9>(m, val, x, y, sig, c, s);
+}
+
+template <class VT, class PT>
+void spmv_any(const DevMatrix &m, const VT *val, const PT *x, double *y, double *sig_part, const IterCtx &c,
+              hipStream_t s)
+{
+    if (m.n == 0)
+        return;
+    if (m.format == kCsr && m.csr_stream) {
+        hipLaunchKernelGGL((k_spmv_csr_rows<VT, PT>), dim3(m.csr_blocks), dim3(kBlock), 0, s, m.csr_nrb, m.csr_rb,
+                           m.ptr, m.idx, val, x, y, sig_part, c.st);
+    } else if (m.format == kCsr) {
+        switch (m.lanes) {
+        case 4: csr_launch<4>(m, val, x, y, sig_part, c, s); break;
+        case 8: csr_launch<8>(m, val, x, y, sig_part, c, s); break;
+        case 16: csr_launch<16>(m, val, x, y, sig_part, c, s); break;
+        case 32: csr_launch<32>(m, val, x, y, sig_part, c, s); break;
+        default: csr_launch<64>(m, val, x, y, sig_part, c, s); break;
+        }
+    } else if (m.format == kSymCsr) {
+        scatter_dispatch<true>(m, val, x, y, sig_part, c, s);
+    } else {
+        scatter_dispatch<false>(m, val, x, y, sig_part, c, s);
+    }
 }
 
 } // namespace
 
 void launch_spmv(const DevMatrix &m, const double *x, double *y, double *sig_part, const IterCtx &c, hipStream_t s)
 {
-    if (m.n == 0)
-        return;
-    if (m.format == kCsr && m.csr_stream) {
-        hipLaunchKernelGGL(k_spmv_csr_rows, dim3(m.csr_blocks), dim3(kBlock), 0, s, m.csr_nrb, m.csr_rb, m.ptr,
-                           m.idx, m.val, x, y, sig_part, c.st, c.rho_part, c.n_rho);
-    } else if (m.format == kCsr) {
-        switch (m.lanes) {
-        case 4: csr_launch<4>(m, x, y, sig_part, c, s); break;
-        case 8: csr_launch<8>(m, x, y, sig_part, c, s); break;
-        case 16: csr_launch<16>(m, x, y, sig_part, c, s); break;
-        case 32: csr_launch<32>(m, x, y, sig_part, c, s); break;
-        default: csr_launch<64>(m, x, y, sig_part, c, s); break;
-        }
-    } else if (m.format == kSymCsr) {
-        scatter_dispatch<true>(m, x, y, sig_part, c, s);
-    } else {
-        scatter_dispatch<false>(m, x, y, sig_part, c, s);
-    }
+    spmv_any(m, m.val, x, y, sig_part, c, s);
+}
+
+void launch_spmv32(const DevMatrix &m, const float *x, double *y, double *sig_part, const IterCtx &c, hipStream_t s)
+{
+    spmv_any(m, m.val32, x, y, sig_part, c, s);
 }
 
 void launch_update_r(const DevMatrix &m, double *r, const double *q, DevState *st, const double *sig_part,
@@ -628,8 +689,33 @@ void launch_update_r(const DevMatrix &m, double *r, const double *q, DevState *s
 void launch_update_xp(const DevMatrix &m, double *x, double *p, const double *r, DevState *st,
                       const double *rho_part, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_update_xp, dim3(m.vec_blocks), dim3(kBlock), 0, s, m.n, m.vec_chunk, x, p, r, st,
+    hipLaunchKernelGGL(k_update_xp<double>, dim3(m.vec_blocks), dim3(kBlock), 0, s, m.n, m.vec_chunk, x, p, r, st,
                        rho_part, m.vec_blocks);
+}
+
+void launch_update_xp32(const DevMatrix &m, double *x, float *p, const double *r, DevState *st,
+                        const double *rho_part, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_update_xp<float>, dim3(m.vec_blocks), dim3(kBlock), 0, s, m.n, m.vec_chunk, x, p, r, st,
+                       rho_part, m.vec_blocks);
+}
+
+void launch_mx_init(const DevMatrix &m, const double *r_out, double *rh, float *p, double *c, double *rho_part,
+                    double *bb_part, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_mx_init, dim3(m.vec_blocks), dim3(kBlock), 0, s, m.n, m.vec_chunk, r_out, m.dscale, rh,
+                       p, c, rho_part, bb_part);
+}
+
+void launch_mx_apply(const DevMatrix &m, double *x, const double *c, hipStream_t s)
+{
+    if (m.n > 0)
+        hipLaunchKernelGGL(k_mx_apply, dim3((m.n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, m.n, x, m.dscale, c);
+}
+
+void launch_outer_norm(const DevMatrix &m, DevState *st, const double *rho_part, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_outer_norm, dim3(1), dim3(kBlock), 0, s, st, rho_part, m.vec_blocks);
 }
 
 void launch_check(const DevMatrix &m, DevState *st, const double *rho_part, hipStream_t s)

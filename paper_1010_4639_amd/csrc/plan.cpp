@@ -13,9 +13,9 @@ int64_t Plan::device_bytes() const
 {
     if (format == kCsr)
         return (int64_t)csr_rb.size() * 4;
-    return (int64_t)blocks.size() * sizeof(ScatterBlock) + (int64_t)phase_blocks.size() * 4 +
-           (int64_t)slot_target.size() * 4 + (int64_t)slot_flag.size() + (int64_t)seg.size() * 2 +
-           (int64_t)tl.size() * 2;
+    // descriptors, slot target / flag / segment offsets, contributions, parked sums
+    return (int64_t)blocks.size() * sizeof(ScatterBlock) + (int64_t)slot_target.size() * (4 + 1 + 8) +
+           (int64_t)seg.size() * 2 + (int64_t)tl.size() * 2;
 }
 
 int lanes_for_mean_length(double mean_len)
@@ -28,8 +28,10 @@ int lanes_for_mean_length(double mean_len)
 
 int validate_and_normalise(int fmt, int64_t n, const int32_t *ptr, const int32_t *idx, const double *vals,
                            int base, uint32_t flags, std::vector<int32_t> &ptr0, std::vector<int32_t> &idx0,
-                           std::string &err)
+                           std::string &err, std::vector<int32_t> *perm)
 {
+    if (perm)
+        perm->clear();
     if (fmt < 0 || fmt > 2) {
         err = "unknown format";
         return CG_ERR_ARG;
@@ -79,8 +81,12 @@ int validate_and_normalise(int fmt, int64_t n, const int32_t *ptr, const int32_t
                 err = "indices not strictly increasing in line " + std::to_string(l);
                 return CG_ERR_STRUCTURE;
             }
-            if (fmt == kSymCsr && k == b && j != l) {
+            if (fmt == kSymCsr && !(flags & CG_LOWER) && k == b && j != l) {
                 err = "symmetric CSR row " + std::to_string(l) + " does not start with its diagonal";
+                return CG_ERR_STRUCTURE;
+            }
+            if (fmt == kSymCsr && (flags & CG_LOWER) && k == e - 1 && j != l) {
+                err = "lower symmetric CSR row " + std::to_string(l) + " does not end with its diagonal";
                 return CG_ERR_STRUCTURE;
             }
             idx0[k] = (int32_t)j;
@@ -96,6 +102,27 @@ int validate_and_normalise(int fmt, int64_t n, const int32_t *ptr, const int32_t
                 err = "non-finite value at entry " + std::to_string(k);
                 return CG_ERR_NONFINITE;
             }
+    }
+    if (fmt == kSymCsr && (flags & CG_LOWER)) {
+        // lower triangle by rows == upper triangle by columns: transpose the
+        // structure (stable counting sort) into the upper-by-rows layout;
+        // the caller's values are permuted the same way by the creator
+        std::vector<int32_t> tp((size_t)n + 1, 0), ti((size_t)nnz), src((size_t)nnz);
+        for (int64_t k = 0; k < nnz; ++k)
+            tp[idx0[k] + 1]++;
+        for (int64_t i = 0; i < n; ++i)
+            tp[i + 1] += tp[i];
+        std::vector<int32_t> next(tp.begin(), tp.end() - 1);
+        for (int64_t l = 0; l < n; ++l)
+            for (int64_t k = ptr0[l]; k < ptr0[l + 1]; ++k) {
+                const int32_t d = next[idx0[k]]++;
+                ti[d] = (int32_t)l;
+                src[d] = (int32_t)k;
+            }
+        ptr0.swap(tp);
+        idx0.swap(ti);
+        if (perm)
+            perm->swap(src);
     }
     if ((flags & CG_CHECK_SYMMETRY) && fmt != kSymCsr) {
         // transpose by counting sort and compare entry by entry

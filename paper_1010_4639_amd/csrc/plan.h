@@ -42,7 +42,8 @@ struct ScatterBlock {
     int32_t k0, k1;        // entries [k0, k1) (a line longer than the block limit is split)
     int32_t slot0, nslots; // slots [slot0, slot0 + nslots); seg of this block starts at slot0 + id
     int32_t tl0, id;       // contributions start; block id (index of its dot partial)
-    int32_t ntl, pad;      // number of contributions
+    int32_t ntl;           // number of contributions
+    int32_t pad;           // device copy: colour of the block
 };
 
 struct Plan {
@@ -68,14 +69,17 @@ struct Plan {
     // vector kernels
     int vec_blocks = 0, vec_chunk = 0;
 
-    int spmv_blocks() const { return format == kCsr ? csr_blocks : nblocks; }
+    int scatter_wgs() const { return nblocks < kMaxSpmvBlocks ? nblocks : kMaxSpmvBlocks; }
+    int spmv_blocks() const { return format == kCsr ? csr_blocks : scatter_wgs(); }
     int64_t device_bytes() const;
 };
 
 // Validates (rules of cg_create) and returns 0-based copies.  vals may be null.
+// With CG_LOWER the structure is returned in the upper layout and *perm (if
+// given) maps each new entry position to the caller's entry index.
 int validate_and_normalise(int fmt, int64_t n, const int32_t *ptr, const int32_t *idx, const double *vals,
                            int base, uint32_t flags, std::vector<int32_t> &ptr0, std::vector<int32_t> &idx0,
-                           std::string &err);
+                           std::string &err, std::vector<int32_t> *perm = nullptr);
 
 // Builds the plan for 0-based arrays.  target_entries <= 0 selects the default.
 int build_plan(int fmt, int64_t n, const int32_t *ptr0, const int32_t *idx0, int target_entries, Plan &plan,

@@ -105,8 +105,10 @@ def direction_offsets(nx, ny):
 
 
 def fem_p1_system(nx, ny, nz, *, nu_iron=1e-3, iron_frac=0.4, jitter=0.2, seed=1,
-                  with_rhs=True, keep_geometry=True) -> FemSystem:
-    """Assemble the P1 / Kuhn-tet stiffness matrix on an nx*ny*nz interior grid."""
+                  with_rhs=True, keep_geometry=True, nrhs=1) -> FemSystem:
+    """Assemble the P1 / Kuhn-tet stiffness matrix on an nx*ny*nz interior grid.
+    nrhs > 1: x_true and b get shape (n, nrhs) (columns drawn in order from the
+    x_true stream; the first column equals the nrhs = 1 draw)."""
     rng_jit, rng_iron, rng_x, _ = _streams(seed)
     n = nx * ny * nz
     P = _lattice(nx, ny, nz, jitter, rng_jit)
@@ -120,15 +122,15 @@ def fem_p1_system(nx, ny, nz, *, nu_iron=1e-3, iron_frac=0.4, jitter=0.2, seed=1
     else:
         box = ((0, 0, 0), (0, 0, 0))
     iron_fraction = float(np.mean(nu_cell != 1.0))
-    x_true = rng_x.uniform(-1.0, 1.0, size=n) if with_rhs else None
-    xl = None
-    if with_rhs:
+    xcols = [rng_x.uniform(-1.0, 1.0, size=n) for _ in range(nrhs)] if with_rhs else []
+    xls = []
+    for xc in xcols:
         xl = np.zeros((nz + 2, ny + 2, nx + 2))
-        xl[1:-1, 1:-1, 1:-1] = x_true.reshape(nz, ny, nx)
-        xl = xl.ravel()
+        xl[1:-1, 1:-1, 1:-1] = xc.reshape(nz, ny, nx)
+        xls.append(xl.ravel())
 
     U8 = np.zeros(n * 8)                 # upper key (node, direction code)
-    b = np.zeros(n) if with_rhs else None
+    bcols = [np.zeros(n) for _ in xcols]
     cz, cy, cx = cells[2], cells[1], cells[0]
     nu_flat = nu_cell.ravel()
     min_orient = np.inf
@@ -172,16 +174,22 @@ def fem_p1_system(nx, ny, nz, *, nu_iron=1e-3, iron_frac=0.4, jitter=0.2, seed=1
                 keys_l.append(node[a][m] * 8 + code)
                 vals_l.append(kab[m])
         U8 += np.bincount(np.concatenate(keys_l), weights=np.concatenate(vals_l), minlength=n * 8)
-        if with_rhs:
+        for xl, bc in zip(xls, bcols):
             for a in range(4):
                 acc = np.zeros(base.size)
                 for bb in range(4):
                     kab = w * np.einsum("ij,ij->i", g[:, a, :], g[:, bb, :])
                     acc += kab * xl[lin[bb]]
                 m = node[a] >= 0
-                b += np.bincount(node[a][m], weights=acc[m], minlength=n)
+                bc += np.bincount(node[a][m], weights=acc[m], minlength=n)
         del J, Jinv, g, V
     rowptr, col, val = _upper_keys_to_csr(U8, nx, ny, nz)
+    if not with_rhs:
+        x_true = b = None
+    elif nrhs == 1:
+        x_true, b = xcols[0], bcols[0]
+    else:
+        x_true, b = np.stack(xcols, axis=1), np.stack(bcols, axis=1)
     return FemSystem(nx=nx, ny=ny, nz=nz, n=n, rowptr=rowptr, col=col, val=val,
                      x_true=x_true, b=b, coords=P if keep_geometry else None,
                      nu_cell=nu_cell, iron_box=box, iron_fraction=iron_fraction,
@@ -349,3 +357,55 @@ def random_spd_sparse(n, *, density=0.05, seed=0):
 
 def uniform_vector(n, *, seed=0, lo=-1.0, hi=1.0):
     return np.random.default_rng(seed).uniform(lo, hi, size=n)
+
+
+def block_diagonal(systems):
+    """Concatenate CSR systems [(rowptr, col, val), ...] into one block-diagonal
+    CSR with global indices; returns (sys_off int64[nsys+1], rowptr, col, val).
+    (Index bookkeeping only.)"""
+    offs = [0]
+    ptrs, cols, vals = [np.zeros(1, np.int64)], [], []
+    nnz = 0
+    for (rp, c, v) in systems:
+        n = len(rp) - 1
+        ptrs.append(np.asarray(rp[1:], dtype=np.int64) + nnz)
+        cols.append(np.asarray(c, dtype=np.int64) + offs[-1])
+        vals.append(np.asarray(v, dtype=np.float64))
+        nnz += int(rp[-1])
+        offs.append(offs[-1] + n)
+    rowptr = np.concatenate(ptrs)
+    if rowptr[-1] >= 2 ** 31:
+        raise ValueError("nnz exceeds int32 indexing")
+    return (np.array(offs, dtype=np.int64), rowptr.astype(np.int32), np.concatenate(cols).astype(np.int32),
+            np.concatenate(vals))
+
+
+def fem_batch(nsys, *, lo=20, hi=60, nu_iron=1e-3, seed=4, nrhs=4, workers=1):
+    """The batch workload: nsys systems of the FEM generator with interior grid
+    edges drawn independently per axis, integer U{lo..hi}; system s uses the
+    s-th child of SeedSequence(seed) for its own streams.  Right-hand sides
+    b = A x_true for nrhs seeded x_true ~ U(-1, 1) per system (formed element
+    by element).  Returns (list of FemSystem, B (N, nrhs), Xtrue (N, nrhs))."""
+    ss = np.random.SeedSequence(seed)
+    kids = ss.spawn(nsys + 1)
+    dims = np.random.Generator(np.random.PCG64(kids[0])).integers(lo, hi + 1, size=(nsys, 3))
+    args = [(int(d[0]), int(d[1]), int(d[2]), nu_iron, int(kids[s + 1].generate_state(1)[0]), nrhs)
+            for s, d in enumerate(dims)]
+    if workers > 1:
+        import multiprocessing as mp
+        with mp.get_context("fork").Pool(workers) as pool:
+            out = pool.map(_batch_member, args)
+    else:
+        out = [_batch_member(a) for a in args]
+    systems = [o[0] for o in out]
+    B = np.concatenate([o[1] for o in out])
+    X = np.concatenate([o[2] for o in out])
+    return systems, B, X
+
+
+def _batch_member(a):
+    nx, ny, nz, nu, sd, nrhs = a
+    s = fem_p1_system(nx, ny, nz, nu_iron=nu, seed=sd, with_rhs=True, keep_geometry=False, nrhs=nrhs)
+    b = s.b.reshape(s.n, nrhs)
+    x = s.x_true.reshape(s.n, nrhs)
+    return (s.rowptr, s.col, s.val), b, x

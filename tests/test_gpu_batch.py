@@ -1,0 +1,106 @@
+"""Batched solves (many uneven systems x several right-hand sides, one kernel
+sequence) vs the oracle run on every (system, right-hand side) pair alone.
+
+Per pair: same status; true residual (oracle product) <= 2 tol; energy-norm
+difference to the oracle's solution <= 1e-8; iteration count within 3 %.
+The products of every system are checked row by row against the oracle's.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1010_4639_amd import cgmi
+from paper_1010_4639_amd import workload as W
+from tests.gpu_util import say, spmv_bound, to_dev
+from tests.test_gpu_cg import a_norm
+
+pytestmark = pytest.mark.gpu
+
+
+def small_batch(nrhs, seed=1):
+    rng = np.random.default_rng(seed)
+    systems, Bs = [], []
+    for k, dims in enumerate([(6, 5, 4), (9, 8, 7), (3, 3, 3), (12, 10, 9), (7, 7, 7)]):
+        s = W.fem_p1_system(*dims, seed=10 + k, nrhs=nrhs)
+        systems.append((s.rowptr, s.col, s.val))
+        Bs.append(s.b.reshape(s.n, nrhs))
+    ptr, col, val = W.random_spd_sparse(150, density=0.05, seed=seed)
+    systems.append((ptr, col, val))
+    Bs.append(rng.uniform(-1, 1, size=(150, nrhs)))
+    return systems, np.concatenate(Bs)
+
+
+@pytest.mark.parametrize("nrhs", [1, 2, 4])
+def test_batch_matches_single_oracle_solves(nrhs):
+    systems, B = small_batch(nrhs)
+    so, ptr, col, val = W.block_diagonal(systems)
+    with cgmi.Batch(so, ptr, col, val, nrhs=nrhs) as bt:
+        X, info, iters, stat = bt.solve(to_dev(B), tol=1e-10, maxit=20000)
+        X = X.cpu().numpy()
+    say(f"batch nrhs={nrhs}: {info}")
+    for s, arrs in enumerate(systems):
+        r0, r1 = so[s], so[s + 1]
+        for r in range(nrhs):
+            b = B[r0:r1, r]
+            xo, oi, _ = oracle.cg(0, *arrs, b, tol=1e-10, maxit=20000)
+            xg = X[r0:r1, r]
+            assert stat[s, r] == oi["status"] == 0, (s, r, stat[s, r])
+            rt = np.linalg.norm(b - oracle.spmv(0, *arrs, xg)) / np.linalg.norm(b)
+            assert rt <= 2e-10, (s, r, rt)
+            ea = a_norm(0, arrs, xg - xo) / a_norm(0, arrs, xo)
+            assert ea <= 1e-8, (s, r, ea)
+            assert abs(int(iters[s, r]) - oi["iters"]) <= max(2, 0.03 * oi["iters"]), (s, r, iters[s, r], oi)
+
+
+def test_batch_spmm_rowwise():
+    systems, B = small_batch(4, seed=2)
+    so, ptr, col, val = W.block_diagonal(systems)
+    X = np.random.default_rng(3).uniform(-1, 1, size=(so[-1], 4))
+    with cgmi.Batch(so, ptr, col, val, nrhs=4) as bt:
+        Y = bt.spmm(to_dev(X)).cpu().numpy()
+    for r in range(4):
+        yo = oracle.spmv(0, ptr, col, val, X[:, r])
+        # one thread sums each row left to right from rounded products: bit-identical
+        assert np.array_equal(Y[:, r], yo)
+
+
+def test_batch_statuses_per_pair():
+    import torch
+    sysA = W.fem_p1_system(6, 6, 5, seed=3)
+    n = 40
+    d = np.where(np.arange(n) % 2 == 0, 1.0, -1.0)               # indefinite: breakdown
+    sysB = (np.arange(n + 1, dtype=np.int32), np.arange(n, dtype=np.int32), d)
+    so, ptr, col, val = W.block_diagonal([(sysA.rowptr, sysA.col, sysA.val), sysB])
+    N = so[-1]
+    rng = np.random.default_rng(4)
+    B = rng.uniform(-1, 1, size=(N, 4))
+    B[: so[1], 1] = 0.0                      # pair (0, 1): b = 0
+    B[5, 2] = np.nan                         # pair (0, 2): non-finite b
+    X0 = rng.uniform(-1, 1, size=(N, 4))
+    with cgmi.Batch(so, ptr, col, val, nrhs=4) as bt:
+        X, info, iters, st = bt.solve(to_dev(B), to_dev(X0), tol=1e-10, maxit=5000)
+        X = X.cpu().numpy()
+        assert st[0, 0] == st[0, 3] == cgmi.CG_OK
+        assert st[0, 1] == cgmi.CG_OK and iters[0, 1] == 0 and np.all(X[: so[1], 1] == 0)
+        assert st[0, 2] == cgmi.CG_ERR_NONFINITE and np.array_equal(X[: so[1], 2], X0[: so[1], 2])
+        assert np.all(st[1] == cgmi.CG_ERR_BREAKDOWN)
+        assert info["status"] == cgmi.CG_ERR_BREAKDOWN or info["status"] == cgmi.CG_ERR_NONFINITE
+        X, info, iters, st = bt.solve(to_dev(np.nan_to_num(B)), tol=1e-14, maxit=3)
+        assert np.all(st[0][[0, 2, 3]] == cgmi.CG_NOT_CONVERGED) and np.all(iters[0][[0, 2, 3]] == 3)
+
+
+def test_batch_autotune_and_determinism():
+    systems, B = small_batch(4, seed=5)
+    so, ptr, col, val = W.block_diagonal(systems)
+    with cgmi.Batch(so, ptr, col, val, nrhs=4) as bt:
+        X1, i1, it1, _ = bt.solve(to_dev(B))
+        X2, i2, it2, _ = bt.solve(to_dev(B))
+        import torch
+        assert torch.equal(X1, X2) and np.array_equal(it1, it2)
+        tuned = bt.autotune()
+        say(f"autotune: {tuned}")
+        assert tuned["entries_per_block"] in (256, 512, 1024) and tuned["workgroups"] >= len(systems)
+        X3, i3, it3, st3 = bt.solve(to_dev(B))
+        assert np.all(st3 == 0)
+        d = (X3 - X1).cpu().numpy()
+        assert np.linalg.norm(d) <= 1e-6 * np.linalg.norm(X1.cpu().numpy())

@@ -167,3 +167,18 @@ def test_csr_bit_identical_to_oracle(case):
     assert st == 0
     y, yo = check_spmv(CSR, ptr, col, val, W.uniform_vector(len(ptr) - 1, seed=22), label=f"bitwise {case}")
     assert np.array_equal(y, yo)
+
+
+def test_lower_triangle_input_matches_full_product():
+    import scipy.sparse as sp
+    s = W.fem_p1_system(9, 8, 7, seed=23)
+    A = sp.csr_matrix((s.val, s.col, s.rowptr), shape=(s.n, s.n))
+    L = sp.tril(A, format="csr")
+    L.sort_indices()
+    x = W.uniform_vector(s.n, seed=24)
+    with cgmi.Solver(SYM, L.indptr.astype(np.int32) + 1, L.indices.astype(np.int32) + 1, L.data, index_base=1,
+                     flags=cgmi.CG_LOWER) as S:
+        y = S.spmv(to_dev(x)).cpu().numpy()
+    import oracle
+    yo = oracle.spmv(CSR, s.rowptr, s.col, s.val, x)
+    assert np.all(np.abs(y - yo) <= 1e-13 * oracle.spmv(CSR, s.rowptr, s.col, np.abs(s.val), np.abs(x)))

@@ -82,7 +82,7 @@ def check_scatter_plan(fmt, ptr, idx):
     n = len(ptr) - 1
     st, P = cgmi.cg_analyze_export(fmt, n, ptr, idx)
     assert st == 0, cgmi.cg_last_error(None)
-    nb = P["stats"]["spmv_blocks"]
+    nb = P["stats"]["scatter_blocks"]
     assert P["stats"]["colors"] == P["color"].max() + 1
     # blocks tile the lines and the entries contiguously (a long line may be split)
     assert P["line0"][0] == 0 and P["line1"][-1] == n
@@ -140,7 +140,7 @@ def test_scatter_plan_small_blocks_many_colours(monkeypatch):
     s = W.fem_p1_system(8, 7, 6, seed=4)
     up, uc, _ = W.upper_triangle(s.rowptr, s.col, s.val)
     P = check_scatter_plan(cgmi.CG_FMT_SYM_CSR, up, uc)
-    assert P["stats"]["spmv_blocks"] > 20 and P["stats"]["colors"] >= 2
+    assert P["stats"]["scatter_blocks"] > 20 and P["stats"]["colors"] >= 2
     check_scatter_plan(cgmi.CG_FMT_CSC, s.rowptr, s.col)
 
 
@@ -166,7 +166,7 @@ def test_scatter_plan_long_rows_symcsr(monkeypatch):
     monkeypatch.setenv("CGMI_SCATTER_ENTRIES", "32")
     up, uc = _arrow_upper(200)
     P = check_scatter_plan(cgmi.CG_FMT_SYM_CSR, up, uc)
-    split = [b for b in range(P["stats"]["spmv_blocks"]) if P["line0"][b] == 0 and P["line1"][b] == 1]
+    split = [b for b in range(P["stats"]["scatter_blocks"]) if P["line0"][b] == 0 and P["line1"][b] == 1]
     assert len(split) == 7                         # 200 entries of row 0 in blocks of 32
 
 
@@ -185,3 +185,48 @@ def test_one_based_input_same_plan():
     assert st0 == st1 == 0
     for k in ("color", "target", "flags", "count", "slot0"):
         assert np.array_equal(P0[k], P1[k])
+
+
+def _lower_arrays(s):
+    import scipy.sparse as sp
+    A = sp.csr_matrix((s.val, s.col, s.rowptr), shape=(s.n, s.n))
+    L = sp.tril(A, format="csr")
+    L.sort_indices()
+    return L.indptr.astype(np.int32), L.indices.astype(np.int32), L.data.copy()
+
+
+def test_lower_triangle_input_paper_storage():
+    # the paper stores L + D by rows, 1-based; CG_LOWER accepts exactly that
+    s = W.fem_p1_system(6, 5, 4, seed=8)
+    lp, lc, lv = _lower_arrays(s)
+    st, stats = cgmi.cg_analyze(cgmi.CG_FMT_SYM_CSR, s.n, lp + 1, lc + 1, lv, 1, cgmi.CG_LOWER)
+    assert st == 0 and stats["nnz"] == len(lc)
+    up, uc, uv = W.upper_triangle(s.rowptr, s.col, s.val)
+    st_up, stats_up = cgmi.cg_analyze(cgmi.CG_FMT_SYM_CSR, s.n, up, uc, uv)
+    assert stats["colors"] == stats_up["colors"] and stats["slots"] == stats_up["slots"]
+    # without the flag the lower layout is malformed, and upper arrays are malformed with it
+    assert cgmi.cg_analyze(cgmi.CG_FMT_SYM_CSR, s.n, lp, lc, lv)[0] == cgmi.CG_ERR_STRUCTURE
+    assert cgmi.cg_analyze(cgmi.CG_FMT_SYM_CSR, s.n, up, uc, uv, 0, cgmi.CG_LOWER)[0] == cgmi.CG_ERR_STRUCTURE
+
+
+def test_batch_create_validation_on_host():
+    # structure errors are reported before any device work
+    s1 = W.fem_p1_system(3, 3, 2, seed=1)
+    s2 = W.fem_p1_system(2, 2, 2, seed=2)
+    so, ptr, col, val = W.block_diagonal([(s1.rowptr, s1.col, s1.val), (s2.rowptr, s2.col, s2.val)])
+    bad = col.copy()
+    bad[0] = so[1]                       # row 0 of system 0 couples into system 1 (unsorted too)
+    st, h = cgmi.cg_batch_create(so, ptr, np.sort(bad[:ptr[1]]).tolist() + bad[ptr[1]:].tolist(), val)
+    assert st == cgmi.CG_ERR_STRUCTURE and h is None and "another system" in cgmi.cg_batch_last_error(None)
+    st, h = cgmi.cg_batch_create(np.array([0, 5, 5, so[-1]]), ptr, col, val)
+    assert st == cgmi.CG_ERR_STRUCTURE
+    st, h = cgmi.cg_batch_create(so, ptr, col, val, nrhs=3)
+    assert st == cgmi.CG_ERR_ARG
+
+
+def test_block_diagonal_helper():
+    s1 = W.fem_p1_system(3, 3, 2, seed=1)
+    s2 = W.fem_p1_system(2, 2, 2, seed=2)
+    so, ptr, col, val = W.block_diagonal([(s1.rowptr, s1.col, s1.val), (s2.rowptr, s2.col, s2.val)])
+    assert list(so) == [0, s1.n, s1.n + s2.n]
+    assert ptr[-1] == s1.nnz + s2.nnz and col[ptr[s1.n]] >= s1.n
