@@ -186,9 +186,28 @@ int upload_all(cg_handle *h, const std::vector<int32_t> &ptr0, const std::vector
         }
         for (int c = 0; c < p.ncolors; ++c)
             cso[c + 1] += cso[c];
+        // per row: its parked slots (colours >= 1) in ascending colour order,
+        // and whether a colour-0 block writes it
+        std::vector<int32_t> rsp((size_t)n + 1, 0), rsi;
+        std::vector<uint8_t> c0((size_t)n, 0);
+        const int32_t first_parked = cso.size() > 1 ? cso[1] : 0;
+        for (size_t q = 0; q < otg.size(); ++q) {
+            if ((int32_t)q < first_parked)
+                c0[otg[q]] = 1;
+            else
+                rsp[otg[q] + 1]++;
+        }
+        for (int64_t i = 0; i < n; ++i)
+            rsp[i + 1] += rsp[i];
+        rsi.resize(rsp[n]);
+        {
+            std::vector<int32_t> next(rsp.begin(), rsp.end() - 1);
+            for (size_t q = first_parked; q < otg.size(); ++q)
+                rsi[next[otg[q]]++] = (int32_t)q;
+        }
         ScatterBlock *b;
-        int32_t *tg;
-        uint8_t *fl;
+        int32_t *tg, *drsp, *drsi;
+        uint8_t *fl, *dc0;
         uint16_t *sg, *tl;
         double *part;
         if ((st = upload(h, &b, ob.data(), ob.size())) != CG_OK ||
@@ -196,8 +215,13 @@ int upload_all(cg_handle *h, const std::vector<int32_t> &ptr0, const std::vector
             (st = upload(h, &fl, ofl.data(), ofl.size())) != CG_OK ||
             (st = upload(h, &sg, osg.data(), osg.size())) != CG_OK ||
             (st = upload(h, &tl, p.tl.data(), p.tl.size())) != CG_OK ||
-            (st = dalloc(h, &part, otg.size())) != CG_OK)
+            (st = dalloc(h, &part, otg.size())) != CG_OK || (st = upload(h, &drsp, rsp.data(), rsp.size())) != CG_OK ||
+            (st = upload(h, &drsi, rsi.data(), rsi.size())) != CG_OK ||
+            (st = upload(h, &dc0, c0.data(), c0.size())) != CG_OK)
             return st;
+        m.rs_ptr = drsp;
+        m.rs_idx = drsi;
+        m.has_c0 = dc0;
         m.blocks = b;
         m.slot_target = tg;
         m.slot_flag = fl;

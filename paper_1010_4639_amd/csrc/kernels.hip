@@ -210,17 +210,19 @@ __global__ __launch_bounds__(kBlock) void k_spmv_csr_rows(int nrb, const int32_t
 //   independent global load is issued first (line pointers, x of the own
 //   lines, the contribution list -> LDS, <= 2048 index / value pairs, 8 per
 //   thread, and the write-slot descriptors, SU per thread); then the gathers;
-//   then from LDS
-//     sp[e] = a_e x_line(e)   product bound for another row (mirror / column)
-//     gp[e] = a_e x_idx(e)    symmetric CSR: product of the stored row itself
-//   and every slot's sum in the plan's fixed order.  Colour-0 blocks are the
+//   then, through one LDS product buffer: (symmetric CSR) the products of
+//   the stored rows themselves, a_e x_idx(e), each own row summed left to
+//   right by the thread that owns that row's slot; then the products bound
+//   for other rows, a_e x_line(e) (mirror / column), and every slot's sum in
+//   the plan's fixed order.  Colour-0 blocks are the
 //   first writers of all their rows and store y directly; the others park
 //   their slot sums in `part`.  The dot x'y is linear in the slot sums, so
 //   each workgroup accumulates sum_slots x_target * sum here, before any y
 //   is final.
-// k_scatter_combine -- one launch per later colour: y_t (+)= part_s over the
-//   colour's slots (contiguous, coalesced).  Blocks of one colour write
-//   disjoint rows, so no atomics are needed; colours run in order.
+// k_scatter_gather -- one launch: every row adds its parked slot sums, in
+//   ascending colour order, to what its colour-0 writer stored (if any).
+//   Blocks of one colour write disjoint rows, so colour 0 can store without
+//   conflicts; the colour order fixes the accumulation order of the rest.
 template <bool SYM, int SU, class VT, class PT>
 __global__ __launch_bounds__(kBlock) void k_scatter_sums(
     const int32_t *__restrict__ ptr, const int32_t *__restrict__ idx, const VT *__restrict__ val,
@@ -234,9 +236,8 @@ __global__ __launch_bounds__(kBlock) void k_scatter_sums(
     const int wg = xcd_remap(blockIdx.x, gridDim.x);
     if (st != nullptr && !iter_gate(st))
         return;
-    double *sp = lds;
-    double *gp = sp + lds_entries;
-    double *xl = gp + (SYM ? lds_entries : 0);
+    double *sp = lds; // own-row products first (symmetric CSR), then the products bound elsewhere
+    double *xl = sp + lds_entries;
     int32_t *lp = reinterpret_cast<int32_t *>(xl + lds_lines);
     uint16_t *lm = reinterpret_cast<uint16_t *>(lp + lds_lines + 1);
     uint16_t *tv = lm + lds_entries;
@@ -290,19 +291,28 @@ __global__ __launch_bounds__(kBlock) void k_scatter_sums(
             for (int k = lp[l]; k < lp[l + 1]; ++k)
                 lm[k] = (uint16_t)l;
         __syncthreads();
-        // ---- products
+        // ---- symmetric CSR: own rows, stored entries left to right; the sum
+        //      of row l stays in thread l, which owns that row's slot (l < 256)
+        double own = 0.0;
+        if (SYM) {
+#pragma unroll
+            for (int m = 0; m < E; ++m)
+                if (c[m] >= 0)
+                    sp[t + m * kBlock] = v[m] * xg[m];
+            __syncthreads();
+            if (t < nl)
+                for (int k = lp[t]; k < lp[t + 1]; ++k)
+                    own += sp[k];
+            __syncthreads();
+        }
+        // ---- products bound for other rows (mirror / column)
 #pragma unroll
         for (int m = 0; m < E; ++m) {
             const int e = t + m * kBlock;
             if (c[m] >= 0) {
                 const int l = lm[e];
-                if (SYM) {
-                    gp[e] = v[m] * xg[m];
-                    if (c[m] != bk.line0 + l)
-                        sp[e] = v[m] * xl[l];
-                } else {
+                if (!SYM || c[m] != bk.line0 + l)
                     sp[e] = v[m] * xl[l];
-                }
             }
         }
         __syncthreads();
@@ -313,10 +323,7 @@ __global__ __launch_bounds__(kBlock) void k_scatter_sums(
             if (tg[u] < 0)
                 continue;
             const int s = t + u * kBlock;
-            double a = 0.0;
-            if (SYM && s < nl) // own row: its stored entries, left to right
-                for (int k = lp[s]; k < lp[s + 1]; ++k)
-                    a += gp[k];
+            double a = (SYM && s < nl) ? own : 0.0; // s < nl <= 256 implies u == 0 and s == t
             for (int i = lo[u]; i < hi[u]; ++i)
                 a += sp[tv[i]];
             if (first_colour)
@@ -332,32 +339,27 @@ __global__ __launch_bounds__(kBlock) void k_scatter_sums(
         sig_part[wg] = sig;
 }
 
-__global__ __launch_bounds__(kBlock) void k_scatter_combine(int nslots, const int32_t *__restrict__ slot_target,
-                                                            const uint8_t *__restrict__ slot_flag,
-                                                            const double *__restrict__ part, double *__restrict__ y,
-                                                            const DevState *st)
+// One thread per row: y_i = (y_i if a colour-0 block wrote it, else 0)
+// + the row's parked slot sums in ascending colour order.  Every row is
+// owned by one thread, so no atomics; the order is fixed by the plan.
+__global__ __launch_bounds__(kBlock) void k_scatter_gather(int n, const int32_t *__restrict__ rs_ptr,
+                                                           const int32_t *__restrict__ rs_idx,
+                                                           const uint8_t *__restrict__ has_c0,
+                                                           const double *__restrict__ part, double *__restrict__ y,
+                                                           const DevState *st)
 {
     if (st != nullptr && st->status != kRun)
         return;
-    const int i0 = (blockIdx.x * kBlock) * 4 + threadIdx.x;
-    int tg[4];
-    unsigned fl[4];
-    double pv[4], yo[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-        const int s = i0 + u * kBlock;
-        const bool ok = s < nslots;
-        tg[u] = ok ? __builtin_nontemporal_load(slot_target + s) : -1;
-        fl[u] = ok ? slot_flag[s] : 0u;
-        pv[u] = ok ? __builtin_nontemporal_load(part + s) : 0.0;
-    }
-#pragma unroll
-    for (int u = 0; u < 4; ++u)
-        yo[u] = (tg[u] >= 0 && !(fl[u] & kSlotFirst)) ? y[tg[u]] : 0.0;
-#pragma unroll
-    for (int u = 0; u < 4; ++u)
-        if (tg[u] >= 0)
-            y[tg[u]] = (fl[u] & kSlotFirst) ? pv[u] : yo[u] + pv[u];
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n)
+        return;
+    const int k0 = rs_ptr[i], k1 = rs_ptr[i + 1];
+    if (k0 == k1)
+        return; // written once, by its colour-0 block
+    double a = has_c0[i] ? y[i] : 0.0;
+    for (int k = k0; k < k1; ++k)
+        a += part[rs_idx[k]];
+    y[i] = a;
 }
 
 // ------------------------------------------------------ vector kernels
@@ -616,16 +618,13 @@ void scatter_launch(const DevMatrix &m, const VT *val, const PT *x, double *y, d
                     hipStream_t s)
 {
     const size_t E = (size_t)m.lds_entries, R = (size_t)m.lds_lines;
-    const size_t lds = E * 8 * (SYM ? 2 : 1) + R * 8 + (R + 1) * 4 + 2 * E * 2;
+    const size_t lds = E * 8 + R * 8 + (R + 1) * 4 + 2 * E * 2;
     hipLaunchKernelGGL((k_scatter_sums<SYM, SU, VT, PT>), dim3(m.scatter_wgs), dim3(kBlock), lds, s, m.ptr, m.idx,
                        val, x, y, m.part, sig, m.blocks, m.nblocks, m.slot_target, m.seg, m.tl, m.lds_entries,
                        m.lds_lines, c.st);
-    for (int col = 1; col < m.ncolors; ++col) {
-        const int s0 = m.color_slot_off[col], ns = m.color_slot_off[col + 1] - s0;
-        if (ns > 0)
-            hipLaunchKernelGGL(k_scatter_combine, dim3((ns + 4 * kBlock - 1) / (4 * kBlock)), dim3(kBlock), 0, s,
-                               ns, m.slot_target + s0, m.slot_flag + s0, m.part + s0, y, c.st);
-    }
+    if (m.ncolors > 1)
+        hipLaunchKernelGGL(k_scatter_gather, dim3((m.n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, m.n, m.rs_ptr,
+                           m.rs_idx, m.has_c0, m.part, y, c.st);
 }
 
 template <bool SYM, class VT, class PT>

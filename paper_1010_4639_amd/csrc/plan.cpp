@@ -13,9 +13,10 @@ int64_t Plan::device_bytes() const
 {
     if (format == kCsr)
         return (int64_t)csr_rb.size() * 4;
-    // descriptors, slot target / flag / segment offsets, contributions, parked sums
-    return (int64_t)blocks.size() * sizeof(ScatterBlock) + (int64_t)slot_target.size() * (4 + 1 + 8) +
-           (int64_t)seg.size() * 2 + (int64_t)tl.size() * 2;
+    // descriptors, slot target / flag / segment offsets, contributions, parked
+    // sums and their per-row index (upper bounds: every slot counted)
+    return (int64_t)blocks.size() * sizeof(ScatterBlock) + (int64_t)slot_target.size() * (4 + 1 + 8 + 4) +
+           (int64_t)seg.size() * 2 + (int64_t)tl.size() * 2 + n * 5;
 }
 
 int lanes_for_mean_length(double mean_len)
