@@ -9,6 +9,9 @@ imports nothing from the GPU library.
   validation and the CG iteration of section III of the paper.
 * ``exact.py``: the same SpMV and CG in exact rational arithmetic for tiny
   inputs.
+* ``fem.py``: the finite-element operator A(nu) = sum_e nu_e K_e, the
+  adjoint solve and the gradients dL/db, dL/dA (on the pattern) and dL/dnu
+  (numpy FP64; pinned in ``tests/test_oracle_fem.py``).
 
 Parity status: every function is pinned by the CPU tests (closed forms,
 exact arithmetic, library routines, invariants); see the test module

@@ -66,6 +66,7 @@ class FemSystem:
     iron_box: tuple           # ((ox, oy, oz), (Lx, Ly, Lz)) in cell indices
     iron_fraction: float
     min_orient_det: float     # min over tets of sign(perm)*det(J)
+    seed: int = 0
 
     @property
     def nnz(self) -> int:
@@ -193,7 +194,42 @@ def fem_p1_system(nx, ny, nz, *, nu_iron=1e-3, iron_frac=0.4, jitter=0.2, seed=1
     return FemSystem(nx=nx, ny=ny, nz=nz, n=n, rowptr=rowptr, col=col, val=val,
                      x_true=x_true, b=b, coords=P if keep_geometry else None,
                      nu_cell=nu_cell, iron_box=box, iron_fraction=iron_fraction,
-                     min_orient_det=min_orient)
+                     min_orient_det=min_orient, seed=seed)
+
+
+def fem_mesh(s: FemSystem):
+    """The tetrahedral mesh behind a generated system (needs keep_geometry).
+
+    Returns (coords f64[npts, 3], tets int32[nelem, 4], dof int32[npts],
+    nu_elem f64[nelem]): lattice points numbered x-fastest over the full
+    (nx+2) x (ny+2) x (nz+2) lattice, boundary points included; dof = the
+    unknown's id or -1 on the Dirichlet boundary; elements ordered as the
+    generator visits them (axis permutation outer, then cells x-fastest),
+    vertices (c, c + e_s0, c + e_s0 + e_s1, c + (1,1,1)); nu_elem = the
+    reluctivity of each element's cell.  nelem = 6 (nx+1)(ny+1)(nz+1)."""
+    if s.coords is None:
+        raise ValueError("system was generated without keep_geometry")
+    nx, ny, nz = s.nx, s.ny, s.nz
+    coords = s.coords.reshape(-1, 3).copy()
+    dof = _node_ids(nx, ny, nz).ravel().astype(np.int32)
+    cz, cy, cx = nz + 1, ny + 1, nx + 1
+    base = ((np.arange(cz)[:, None, None] * (ny + 2) + np.arange(cy)[None, :, None]) * (nx + 2)
+            + np.arange(cx)[None, None, :]).ravel()
+    stride = np.array([1, nx + 2, (nx + 2) * (ny + 2)], dtype=np.int64)
+    tets = np.empty((6, base.size, 4), dtype=np.int64)
+    for s_idx, perm in enumerate(PERMS):
+        cur = np.zeros(3, dtype=np.int64)
+        tets[s_idx, :, 0] = base
+        for v, ax in enumerate(perm):
+            cur[ax] += 1
+            tets[s_idx, :, v + 1] = base + int(cur @ stride)
+    nu_elem = np.tile(s.nu_cell.ravel(), 6)
+    return coords, tets.reshape(-1, 4).astype(np.int32), dof, nu_elem
+
+
+def observation(s: FemSystem):
+    """x_obs ~ U(-1, 1), n values, from the fourth stream of the system's seed."""
+    return _streams(s.seed)[3].uniform(-1.0, 1.0, size=s.n)
 
 
 def _key_valid(nx, ny, nz):
