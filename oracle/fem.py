@@ -21,8 +21,9 @@ x = A^-1 b and a loss L(x):
 Functions:
 * ``element_matrices``: K_e of every element.  The barycentric functions are
   found from their defining property phi_a(P_b) = delta_ab: with the 4x4
-  matrix M whose rows are [1, P_b], the coefficients of phi_a are column a of
-  M^-1, so its gradient is rows 1..3 of that column; |T_e| = |det M| / 6.
+  matrix M whose rows are [1, P_b - P_0] (coordinates measured from the
+  first vertex), the coefficients of phi_a are column a of M^-1, so its
+  gradient is rows 1..3 of that column; |T_e| = |det M| / 6.
 * ``assemble``: A(nu) on a given CSR pattern (sum of element contributions).
 * ``nu_grad``, ``pattern_grad``: the formulas above, element by element and
   entry by entry.
@@ -43,11 +44,22 @@ PAIRS = [(a, b) for a in range(4) for b in range(a, 4)]
 def element_matrices(coords, tets):
     """K_e (nelem, 4, 4) without the coefficient, from vertex coordinates."""
     P = np.asarray(coords, dtype=np.float64)[np.asarray(tets)]          # (e, 4, 3)
-    M = np.concatenate([np.ones(P.shape[:2] + (1,)), P], axis=2)       # rows [1, P_b]
+    # the basis functions of an element do not depend on where the origin is:
+    # measuring from the first vertex keeps M as well conditioned as the element
+    P = P - P[:, :1, :]
+    M = np.concatenate([np.ones(P.shape[:2] + (1,)), P], axis=2)       # rows [1, P_b - P_0]
     C = np.linalg.inv(M)                                               # column a: coefficients of phi_a
     grads = C[:, 1:, :]                                                # (e, 3, 4): column a = grad phi_a
     vol = np.abs(np.linalg.det(M)) / 6.0
     return vol[:, None, None] * np.einsum("eka,ekb->eab", grads, grads)
+
+
+def cauchy_schwarz_scale(K):
+    """|T_e| |grad phi_a| |grad phi_b| = sqrt(K_aa K_bb): the size against
+    which the rounding error of K_e[a, b] is measured (an off-diagonal entry
+    can be much smaller than this by cancellation)."""
+    d = np.sqrt(np.maximum(np.einsum("eaa->ea", K), 0.0))
+    return d[:, :, None] * d[:, None, :]
 
 
 def _pattern_positions(rowptr, col, rows, cols):
