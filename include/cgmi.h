@@ -207,6 +207,76 @@ const char *cg_batch_last_error(const cg_batch *h);
  * Asynchronous on the handle's stream. */
 int cg_spmv(cg_handle *h, const double *x, double *y);
 
+/*
+ * Differentiating the solve.  For x = A^-1 b and a loss L(x), the adjoint
+ * lam = A^-1 dL/dx (A symmetric, so a second cg_solve on the same handle)
+ * gives dL/db = lam and dL/dA_ij = -lam_i x_j; nothing from the forward
+ * iterations is kept.  (The paper's solver is section III's CG; these two
+ * calls make it usable inside a gradient-based outer loop.)
+ *
+ * cg_set_values -- replace the values of the handle's matrix, structure
+ * unchanged (no re-planning).
+ *   vals  device, nnz float64, in the entry order of the arrays given to
+ *         cg_create (also for CG_LOWER input); read before the call's work
+ *         on the handle's stream ends
+ * Enqueued on the handle's stream.  With CG_MIXED the FP32 scaled copy is
+ * rebuilt too, and the call blocks until it is done: CG_ERR_ARG if a line
+ * then lacks a positive, finite diagonal (the FP32 copy is then unusable until
+ * the next successful call).  Values are not checked for finiteness.
+ */
+int cg_set_values(cg_handle *h, const double *vals);
+
+/*
+ * cg_pattern_grad -- dL/d(stored value) for every stored entry, given the
+ * adjoint lam and the solution x (device, n float64 each):
+ *   CSR, CSC:       grad[k] = -lam_i x_j for the entry (i, j)
+ *   symmetric CSR:  the stored u_ij (i < j) stands for A_ij and A_ji, so
+ *                   grad[k] = -(lam_i x_j + lam_j x_i); diagonal -lam_i x_i
+ *   grad  device, nnz float64, written in the caller's entry order
+ * Asynchronous on the handle's stream.
+ */
+int cg_pattern_grad(cg_handle *h, const double *lam, const double *x, double *grad);
+
+/*
+ * Finite-element operator with one coefficient per element: linear
+ * tetrahedra, A(nu) = sum_e nu_e K_e with K_e[a][b] = |T_e| grad(phi_a) .
+ * grad(phi_b) (the stiffness matrix of a magnetostatic / electrostatic model,
+ * nu = reluctivity), rows and columns of Dirichlet vertices removed.  The
+ * paper's systems are of this kind (abstract and section I: finite-element
+ * models of Maxwell's equations; section III: the SPD matrix solved).
+ *
+ * cg_fem_create -- plan the operator.
+ *   npts    points (>= 0); coords host, 3*npts float64 (x, y, z), finite
+ *   nelem   elements (0 <= nelem < 2^27); tets host, 4*nelem int32 point ids
+ *   dof     host, npts int32: the unknown of each point in [0, n), or -1 for
+ *           a Dirichlet point (value 0, no row)
+ *   n       unknowns (rows of A)
+ * Builds on the host the full-CSR pattern of A (entry (i, j) iff an element
+ * has unknowns i and j; columns sorted) and, per entry, the list of element
+ * contributions in ascending element order; on the device the element
+ * matrices K_e (10 distinct values each).  Errors: CG_ERR_ARG (sizes, ids,
+ * an element of zero or non-finite volume, > 2^31 entries), CG_ERR_NONFINITE
+ * (coordinates), CG_ERR_NOMEM, CG_ERR_HIP.  Blocks the host.
+ */
+typedef struct cg_fem cg_fem;
+int cg_fem_create(cg_fem **out, int64_t npts, const double *coords, int64_t nelem, const int32_t *tets,
+                  const int32_t *dof, int64_t n);
+int cg_fem_set_stream(cg_fem *f, void *hip_stream);
+/* The pattern: *nnz; rowptr host n+1 int32 and col host nnz int32 (each may
+ * be NULL, e.g. to ask for nnz first).  0-based. */
+int cg_fem_pattern(const cg_fem *f, int64_t *nnz, int32_t *rowptr, int32_t *col);
+/* vals = A(nu) on the pattern (device: nu nelem float64, vals nnz float64);
+ * each value summed over its contributions in the fixed list order.
+ * Asynchronous on the operator's stream. */
+int cg_fem_assemble(cg_fem *f, const double *nu, double *vals);
+/* grad_e = dL/dnu_e = -lam_e' K_e x_e (device: lam, x n float64; grad nelem
+ * float64); Dirichlet vertices contribute 0.  Asynchronous. */
+int cg_fem_nu_grad(cg_fem *f, const double *lam, const double *x, double *grad);
+void cg_fem_destroy(cg_fem *f);
+/* Detail of the last error on f; with f == NULL, of the calling thread's last
+ * failed cg_fem_create.  Never NULL. */
+const char *cg_fem_last_error(const cg_fem *f);
+
 /* Plan summary of a handle. */
 int cg_get_stats(const cg_handle *h, cg_plan_stats *stats);
 

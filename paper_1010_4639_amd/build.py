@@ -1,6 +1,6 @@
 """Build the HIP library libcgmi.so in-tree for gfx950.
 
-plan.cpp is plain host C++ (g++); kernels.hip and capi.cpp go through hipcc
+plan.cpp is plain host C++ (g++); kernels.hip, batch.hip, fem.hip and capi.cpp go through hipcc
 with packed-FP32 instructions disabled (-packed-fp32-ops), then everything is
 linked into one shared library next to this file.
 """
@@ -30,7 +30,7 @@ def build(verbose=False):
     o = os.path.join(BUILD, "plan.o")
     _run(["g++", "-O2", "-std=c++17", "-fPIC", "-Wall", "-c", os.path.join(CSRC, "plan.cpp"), "-o", o])
     objs.append(o)
-    for src in ("kernels.hip", "batch.hip", "capi.cpp"):
+    for src in ("kernels.hip", "batch.hip", "fem.hip", "capi.cpp"):
         o = os.path.join(BUILD, src.split(".")[0] + ".o")
         _run([HIPCC, *HIP_FLAGS, "-x", "hip", "-c", os.path.join(CSRC, src), "-o", o])
         objs.append(o)

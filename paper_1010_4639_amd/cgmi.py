@@ -28,7 +28,9 @@ CG_LOWER = 4
 EXPORTS = ("cg_create", "cg_set_stream", "cg_set_batch", "cg_solve", "cg_solve_mixed", "cg_spmv", "cg_get_stats",
            "cg_destroy", "cg_status_string", "cg_last_error", "cg_analyze", "cg_analyze_export",
            "cg_batch_create", "cg_batch_set_stream", "cg_batch_spmm", "cg_batch_autotune", "cg_batch_solve",
-           "cg_batch_destroy", "cg_batch_last_error")
+           "cg_batch_destroy", "cg_batch_last_error", "cg_set_values", "cg_pattern_grad", "cg_fem_create",
+           "cg_fem_set_stream", "cg_fem_pattern", "cg_fem_assemble", "cg_fem_nu_grad", "cg_fem_destroy",
+           "cg_fem_last_error")
 
 
 class cg_info(ctypes.Structure):
@@ -101,7 +103,20 @@ def load():
     lib.cg_batch_destroy.restype = None
     lib.cg_batch_last_error.argtypes = [_VP]
     lib.cg_batch_last_error.restype = ctypes.c_char_p
-    for nm in ("cg_batch_create", "cg_batch_set_stream", "cg_batch_spmm", "cg_batch_autotune", "cg_batch_solve"):
+    lib.cg_set_values.argtypes = [_VP, _VP]
+    lib.cg_pattern_grad.argtypes = [_VP, _VP, _VP, _VP]
+    lib.cg_fem_create.argtypes = [ctypes.POINTER(_VP), i64, _VP, i64, _VP, _VP, i64]
+    lib.cg_fem_set_stream.argtypes = [_VP, _VP]
+    lib.cg_fem_pattern.argtypes = [_VP, ctypes.POINTER(i64), _VP, _VP]
+    lib.cg_fem_assemble.argtypes = [_VP, _VP, _VP]
+    lib.cg_fem_nu_grad.argtypes = [_VP, _VP, _VP, _VP]
+    lib.cg_fem_destroy.argtypes = [_VP]
+    lib.cg_fem_destroy.restype = None
+    lib.cg_fem_last_error.argtypes = [_VP]
+    lib.cg_fem_last_error.restype = ctypes.c_char_p
+    for nm in ("cg_batch_create", "cg_batch_set_stream", "cg_batch_spmm", "cg_batch_autotune", "cg_batch_solve",
+               "cg_set_values", "cg_pattern_grad", "cg_fem_create", "cg_fem_set_stream", "cg_fem_pattern",
+               "cg_fem_assemble", "cg_fem_nu_grad"):
         getattr(lib, nm).restype = ctypes.c_int
     for nm in ("cg_create", "cg_set_stream", "cg_set_batch", "cg_solve", "cg_solve_mixed", "cg_spmv", "cg_get_stats",
                "cg_analyze", "cg_analyze_export"):
@@ -229,6 +244,8 @@ class Solver:
 
     def __init__(self, fmt, ptr, idx, vals, index_base=0, flags=0, batch=None, mixed=False):
         self.n = len(ptr) - 1
+        self.nnz = len(idx)
+        self.fmt = _fmt(fmt)
         if mixed:
             flags |= CG_MIXED
         st, h = cg_create(fmt, self.n, ptr, idx, vals, index_base, flags)
@@ -280,12 +297,150 @@ class Solver:
             raise CgError(st, cg_last_error(self.h))
         return y
 
+    def set_values(self, vals):
+        """New values (GPU float64 tensor, nnz, the entry order given at creation)."""
+        vp = _dev(vals, self.nnz, "vals")
+        self._stream()
+        st = load().cg_set_values(self.h, vp)
+        if st != CG_OK:
+            raise CgError(st, cg_last_error(self.h))
+
+    def pattern_grad(self, lam, x, out=None):
+        """dL/d(stored values) from the adjoint lam and the solution x."""
+        import torch
+        if out is None:
+            out = torch.empty(self.nnz, dtype=torch.float64, device=x.device)
+        lp, xp, gp = _dev(lam, self.n, "lam"), _dev(x, self.n, "x"), _dev(out, self.nnz, "grad")
+        self._stream()
+        st = load().cg_pattern_grad(self.h, lp, xp, gp)
+        if st != CG_OK:
+            raise CgError(st, cg_last_error(self.h))
+        return out
+
     def stats(self):
         return cg_get_stats(self.h)[1]
 
     def close(self):
         if self.h:
             cg_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+# ------------------------------------------------- C-named thin wrappers
+def cg_set_values(handle, vals_ptr):
+    return load().cg_set_values(handle, _VP(vals_ptr))
+
+
+def cg_pattern_grad(handle, lam_ptr, x_ptr, grad_ptr):
+    return load().cg_pattern_grad(handle, _VP(lam_ptr), _VP(x_ptr), _VP(grad_ptr))
+
+
+def cg_fem_last_error(handle=None):
+    return (load().cg_fem_last_error(handle) or b"").decode()
+
+
+def cg_fem_create(coords, tets, dof, n):
+    """Host arrays coords (npts, 3) f64, tets (nelem, 4) int32, dof (npts,) int32."""
+    lib = load()
+    c = _host_f64(np.asarray(coords).reshape(-1))
+    t = _host_i32(np.asarray(tets).reshape(-1))
+    d = _host_i32(dof)
+    h = _VP()
+    st = lib.cg_fem_create(ctypes.byref(h), d.size, _np_ptr(c), t.size // 4, _np_ptr(t), _np_ptr(d), int(n))
+    return st, h
+
+
+def cg_fem_set_stream(handle, stream_ptr):
+    return load().cg_fem_set_stream(handle, _VP(stream_ptr))
+
+
+def cg_fem_pattern(handle, n):
+    lib = load()
+    nnz = ctypes.c_int64()
+    st = lib.cg_fem_pattern(handle, ctypes.byref(nnz), None, None)
+    if st != CG_OK:
+        return st, None, None
+    rp, col = np.empty(n + 1, np.int32), np.empty(max(nnz.value, 1), np.int32)
+    st = lib.cg_fem_pattern(handle, ctypes.byref(nnz), _np_ptr(rp), _np_ptr(col))
+    return st, rp, col[:nnz.value].copy()
+
+
+def cg_fem_assemble(handle, nu_ptr, vals_ptr):
+    return load().cg_fem_assemble(handle, _VP(nu_ptr), _VP(vals_ptr))
+
+
+def cg_fem_nu_grad(handle, lam_ptr, x_ptr, grad_ptr):
+    return load().cg_fem_nu_grad(handle, _VP(lam_ptr), _VP(x_ptr), _VP(grad_ptr))
+
+
+def cg_fem_destroy(handle):
+    load().cg_fem_destroy(handle)
+
+
+class FemOperator:
+    """Linear-tetrahedron operator A(nu) = sum_e nu_e K_e on the device.
+
+    FemOperator(coords, tets, dof, n): host mesh arrays.  pattern() gives the
+    full-CSR structure (host numpy), assemble(nu) the values, nu_grad(lam, x)
+    the gradient -lam_e' K_e x_e, all on float64 GPU tensors.
+    """
+
+    def __init__(self, coords, tets, dof, n):
+        self.n = int(n)
+        self.nelem = int(np.asarray(tets).size // 4)
+        st, h = cg_fem_create(coords, tets, dof, n)
+        if st != CG_OK:
+            raise CgError(st, cg_fem_last_error(None))
+        self.h = h
+        st, self.rowptr, self.col = cg_fem_pattern(h, self.n)
+        if st != CG_OK:
+            raise CgError(st, cg_fem_last_error(h))
+        self.nnz = int(self.col.size)
+
+    def _stream(self):
+        import torch
+        cg_fem_set_stream(self.h, torch.cuda.current_stream().cuda_stream)
+
+    def pattern(self):
+        return self.rowptr, self.col
+
+    def assemble(self, nu, out=None):
+        import torch
+        if out is None:
+            out = torch.empty(self.nnz, dtype=torch.float64, device=nu.device)
+        np_, vp = _dev(nu, self.nelem, "nu"), _dev(out, self.nnz, "vals")
+        self._stream()
+        st = load().cg_fem_assemble(self.h, np_, vp)
+        if st != CG_OK:
+            raise CgError(st, cg_fem_last_error(self.h))
+        return out
+
+    def nu_grad(self, lam, x, out=None):
+        import torch
+        if out is None:
+            out = torch.empty(self.nelem, dtype=torch.float64, device=x.device)
+        lp, xp, gp = _dev(lam, self.n, "lam"), _dev(x, self.n, "x"), _dev(out, self.nelem, "grad")
+        self._stream()
+        st = load().cg_fem_nu_grad(self.h, lp, xp, gp)
+        if st != CG_OK:
+            raise CgError(st, cg_fem_last_error(self.h))
+        return out
+
+    def close(self):
+        if self.h:
+            cg_fem_destroy(self.h)
             self.h = None
 
     def __del__(self):

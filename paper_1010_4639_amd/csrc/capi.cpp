@@ -51,6 +51,9 @@ struct cg_handle {
     hipGraph_t graph32 = nullptr;
     hipGraphExec_t gexec32 = nullptr;
     int graph32_batch = 0;
+    // caller entry order -> normalised order (lower-triangle input), device copy
+    int32_t *perm = nullptr;
+    int32_t *flag = nullptr; // device word for checks made by kernels
     std::string err;
 };
 
@@ -241,29 +244,12 @@ int upload_all(cg_handle *h, const std::vector<int32_t> &ptr0, const std::vector
         (st = dalloc(h, &h->st, 1)) != CG_OK)
         return st;
     if (h->mixed && n > 0) {
-        // FP32 copy of D^-1/2 A D^-1/2: each value scaled in FP64, rounded once
-        std::vector<double> dg((size_t)n, 0.0);
-        for (int64_t l = 0; l < n; ++l)
-            for (int64_t k = ptr0[l]; k < ptr0[l + 1]; ++k)
-                if (idx0[k] == l)
-                    dg[l] = vals[k];
-        std::vector<double> sc((size_t)n);
-        for (int64_t i = 0; i < n; ++i) {
-            if (!(dg[i] > 0.0)) {
-                h->err = "CG_MIXED needs a positive diagonal (row " + std::to_string(i) + ")";
-                return CG_ERR_ARG;
-            }
-            sc[i] = 1.0 / std::sqrt(dg[i]);
-        }
-        std::vector<float> v32(idx0.size());
-        for (int64_t l = 0; l < n; ++l)
-            for (int64_t k = ptr0[l]; k < ptr0[l + 1]; ++k)
-                v32[k] = (float)(vals[k] * sc[l] * sc[idx0[k]]);
+        // FP32 copy of D^-1/2 A D^-1/2 and D^-1/2 itself: filled by mixed_rescale
         float *dv32;
         double *dsc;
-        if ((st = upload(h, &dv32, v32.data(), v32.size())) != CG_OK ||
-            (st = upload(h, &dsc, sc.data(), sc.size())) != CG_OK || (st = dalloc(h, &h->p32, nv)) != CG_OK ||
-            (st = dalloc(h, &h->rout, nv)) != CG_OK || (st = dalloc(h, &h->st_in, 1)) != CG_OK)
+        if ((st = dalloc(h, &dv32, idx0.size())) != CG_OK || (st = dalloc(h, &dsc, (size_t)n)) != CG_OK ||
+            (st = dalloc(h, &h->p32, nv)) != CG_OK || (st = dalloc(h, &h->rout, nv)) != CG_OK ||
+            (st = dalloc(h, &h->st_in, 1)) != CG_OK)
             return st;
         m.val32 = dv32;
         m.dscale = dsc;
@@ -397,6 +383,24 @@ int read_state(cg_handle *h, DevState *st, DevState *out)
     return CG_OK;
 }
 
+// Mixed precision: D^-1/2 and the FP32 copy of D^-1/2 A D^-1/2 from the
+// current FP64 values (each scaled value formed in FP64, rounded once), on
+// the handle's stream; blocks to read the diagonal check.
+int mixed_rescale(cg_handle *h)
+{
+    hipStream_t s = h->stream;
+    HIP_TRY(h, hipMemsetAsync(h->flag, 0, sizeof(int32_t), s));
+    launch_mx_rescale(h->dm, const_cast<double *>(h->dm.dscale), const_cast<float *>(h->dm.val32), h->flag, s);
+    HIP_TRY(h, hipGetLastError());
+    HIP_TRY(h, hipMemcpyAsync(&h->host_st[0].pad, h->flag, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIP_TRY(h, hipStreamSynchronize(s));
+    if (h->host_st[0].pad) {
+        h->err = "CG_MIXED needs a positive, finite diagonal entry in every line";
+        return CG_ERR_ARG;
+    }
+    return CG_OK;
+}
+
 int status_to_code(int32_t s)
 {
     switch (s) {
@@ -507,6 +511,12 @@ int cg_create(cg_handle **out, int format, int64_t n, const int32_t *ptr, const 
             hipError_t e = hipGetDevice(&h->device);
             st = e == hipSuccess ? upload_all(h.get(), p0, i0, vals) : hip_fail(h->err, e, "hipGetDevice");
         }
+        if (st == CG_OK && !perm.empty())
+            st = upload(h.get(), &h->perm, perm.data(), perm.size());
+        if (st == CG_OK)
+            st = dalloc(h.get(), &h->flag, 1);
+        if (st == CG_OK && h->mixed && n > 0)
+            st = mixed_rescale(h.get());
         if (st != CG_OK) {
             g_err = h->err;
             release(h.get());
@@ -720,6 +730,40 @@ int cg_solve_mixed(cg_handle *h, const double *b, double *x, double tol, int32_t
     info->relres = relres;
     info->relres_true = relres;
     return done(code);
+}
+
+int cg_set_values(cg_handle *h, const double *vals)
+{
+    if (!h)
+        return CG_ERR_ARG;
+    const int64_t nnz = h->plan.nnz;
+    if (nnz == 0)
+        return CG_OK;
+    if (!vals) {
+        h->err = "vals is NULL";
+        return CG_ERR_ARG;
+    }
+    hipStream_t s = h->stream;
+    launch_set_values(nnz, vals, h->perm, const_cast<double *>(h->dm.val), s);
+    HIP_TRY(h, hipGetLastError());
+    if (h->mixed && h->dm.n > 0)
+        return mixed_rescale(h);
+    return CG_OK;
+}
+
+int cg_pattern_grad(cg_handle *h, const double *lam, const double *x, double *grad)
+{
+    if (!h)
+        return CG_ERR_ARG;
+    if (h->plan.nnz == 0)
+        return CG_OK;
+    if (!lam || !x || !grad) {
+        h->err = "lam / x / grad NULL";
+        return CG_ERR_ARG;
+    }
+    launch_pattern_grad(h->dm, lam, x, h->perm, grad, h->stream);
+    HIP_TRY(h, hipGetLastError());
+    return CG_OK;
 }
 
 int cg_get_stats(const cg_handle *h, cg_plan_stats *stats)

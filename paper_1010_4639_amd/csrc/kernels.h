@@ -114,5 +114,12 @@ void launch_init_state(const DevMatrix &m, DevState *st, const double *bb_part, 
 void launch_true_residual(const DevMatrix &m, const double *b, const double *q, double *part, DevState *st,
                           hipStream_t s);
 void launch_fill(int n, double *x, double v, hipStream_t s);
+// val[k] = src[perm ? perm[k] : k] for k < nnz
+void launch_set_values(int64_t nnz, const double *src, const int32_t *perm, double *val, hipStream_t s);
+// mixed precision: recompute D^-1/2 and the FP32 scaled values from m.val; *bad <- 1 on a bad diagonal
+void launch_mx_rescale(const DevMatrix &m, double *sc, float *v32, int32_t *bad, hipStream_t s);
+// out[perm ? perm[k] : k] = dL/d(stored value k) from the adjoint lam and the solution x
+void launch_pattern_grad(const DevMatrix &m, const double *lam, const double *x, const int32_t *perm, double *out,
+                         hipStream_t s);
 
 } // namespace cgmi

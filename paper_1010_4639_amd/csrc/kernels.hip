@@ -605,6 +605,84 @@ __global__ __launch_bounds__(kBlock) void k_fill(int n, double *__restrict__ x, 
         x[i] = v;
 }
 
+// New values for a planned matrix: val[k] = src[perm[k]] (perm = the
+// normalisation's entry order, e.g. a lower triangle read as its transpose),
+// or src[k] when there is none.
+__global__ __launch_bounds__(kBlock) void k_gather_values(int64_t nnz, const double *__restrict__ src,
+                                                          const int32_t *__restrict__ perm, double *__restrict__ val)
+{
+    const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (k < nnz)
+        val[k] = src[perm ? perm[k] : k];
+}
+
+// Mixed precision after new values: s_l = 1 / sqrt(a_ll) per line; a line
+// whose diagonal is absent, non-positive or not finite raises *bad.
+__global__ __launch_bounds__(kBlock) void k_mx_diag(int n, const int32_t *__restrict__ ptr,
+                                                    const int32_t *__restrict__ idx, const double *__restrict__ val,
+                                                    double *__restrict__ sc, int32_t *__restrict__ bad)
+{
+    const int l = blockIdx.x * kBlock + threadIdx.x;
+    if (l >= n)
+        return;
+    double d = 0.0;
+    for (int k = ptr[l]; k < ptr[l + 1]; ++k)
+        if (idx[k] == l)
+            d = val[k];
+    if (!(d > 0.0) || !isfinite(d)) {
+        *bad = 1;
+        d = 1.0;
+    }
+    sc[l] = 1.0 / sqrt(d);
+}
+
+// Mixed precision: v32 = fl32(s_line * a * s_index), each product in FP64.
+__global__ __launch_bounds__(kBlock) void k_mx_scale(int n, const int32_t *__restrict__ ptr,
+                                                     const int32_t *__restrict__ idx, const double *__restrict__ val,
+                                                     const double *__restrict__ sc, float *__restrict__ v32)
+{
+    const int l = blockIdx.x * kBlock + threadIdx.x;
+    if (l >= n)
+        return;
+    const double sl = sc[l];
+    for (int k = ptr[l]; k < ptr[l + 1]; ++k)
+        v32[k] = (float)(val[k] * sl * sc[idx[k]]);
+}
+
+// Gradient of a loss with respect to the stored values, given the adjoint
+// solution lam (A lam = dL/dx) and the solution x: dL/dA_ij = -lam_i x_j.
+// CSR (line = row i): -lam_l x_idx; CSC (line = column j): -lam_idx x_l;
+// symmetric CSR (upper, one stored value stands for A_ij and A_ji):
+// -(lam_l x_idx + lam_idx x_l), and -lam_l x_l on the diagonal.  Written in
+// the caller's entry order (out[perm[k]]).  One thread per line.
+__global__ __launch_bounds__(kBlock) void k_pattern_grad(int fmt, int n, const int32_t *__restrict__ ptr,
+                                                         const int32_t *__restrict__ idx,
+                                                         const double *__restrict__ lam,
+                                                         const double *__restrict__ x,
+                                                         const int32_t *__restrict__ perm, double *__restrict__ out)
+{
+#pragma clang fp contract(off)
+    const int l = blockIdx.x * kBlock + threadIdx.x;
+    if (l >= n)
+        return;
+    const double ll = lam[l], xl = x[l];
+    for (int k = ptr[l]; k < ptr[l + 1]; ++k) {
+        const int j = idx[k];
+        double g;
+        if (fmt == kCsr) {
+            g = -(ll * x[j]);
+        } else if (fmt == kCsc) {
+            g = -(lam[j] * xl);
+        } else if (j == l) {
+            g = -(ll * xl);
+        } else {
+            const double t1 = ll * x[j], t2 = lam[j] * xl; // two rounded products, then one rounded sum
+            g = -(t1 + t2);
+        }
+        out[perm ? perm[k] : k] = g;
+    }
+}
+
 template <int W, class VT, class PT>
 void csr_launch(const DevMatrix &m, const VT *val, const PT *x, double *y, double *sig, const IterCtx &c,
                 hipStream_t s)
@@ -746,6 +824,30 @@ void launch_fill(int n, double *x, double v, hipStream_t s)
 {
     if (n > 0)
         hipLaunchKernelGGL(k_fill, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, n, x, v);
+}
+
+void launch_set_values(int64_t nnz, const double *src, const int32_t *perm, double *val, hipStream_t s)
+{
+    if (nnz > 0)
+        hipLaunchKernelGGL(k_gather_values, dim3((unsigned)((nnz + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, nnz,
+                           src, perm, val);
+}
+
+void launch_mx_rescale(const DevMatrix &m, double *sc, float *v32, int32_t *bad, hipStream_t s)
+{
+    if (m.n <= 0)
+        return;
+    const dim3 g((m.n + kBlock - 1) / kBlock);
+    hipLaunchKernelGGL(k_mx_diag, g, dim3(kBlock), 0, s, m.n, m.ptr, m.idx, m.val, sc, bad);
+    hipLaunchKernelGGL(k_mx_scale, g, dim3(kBlock), 0, s, m.n, m.ptr, m.idx, m.val, sc, v32);
+}
+
+void launch_pattern_grad(const DevMatrix &m, const double *lam, const double *x, const int32_t *perm, double *out,
+                         hipStream_t s)
+{
+    if (m.n > 0)
+        hipLaunchKernelGGL(k_pattern_grad, dim3((m.n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, m.format, m.n,
+                           m.ptr, m.idx, lam, x, perm, out);
 }
 
 } // namespace cgmi
