@@ -311,12 +311,34 @@ int cg_analyze(int format, int64_t n, const int32_t *ptr, const int32_t *idx, co
  *   slot_flags                           [slots] uint8: bit0 first writer of
  *                                        that row, bit1 last writer
  *   slot_count                           [slots] int32: products summed into it
- * Returns CG_ERR_ARG for CG_FMT_CSR.
+ * Returns CG_ERR_ARG for CG_FMT_CSR and CG_FMT_CSC (see cg_analyze_panels).
  */
 int cg_analyze_export(int format, int64_t n, const int32_t *ptr, const int32_t *idx, int index_base,
                       int32_t *blk_color, int32_t *blk_line0, int32_t *blk_line1, int32_t *blk_entry0,
                       int32_t *blk_entry1, int64_t *blk_slot0, int32_t *slot_target, uint8_t *slot_flags,
                       int32_t *slot_count);
+
+/*
+ * Host-only export of the CSC plan ("column panels"), so it can be checked
+ * independently.  The columns are cut into panels of `width` >= 2 bw + 1
+ * columns (bw = the largest |i - j| of an entry), so panels k and k + 2 never
+ * write the same row; even panels are colour 0, odd panels colour 1.  Inside
+ * a panel the entries are ordered by row, then column; a slot is one (panel,
+ * row) pair and its entries are contiguous.  Sizes from cg_analyze on
+ * CG_FMT_CSC: nnz, slots, scatter_blocks (= chunks).
+ *   width         *int64 panel width in columns
+ *   entry_src     [nnz] int32: 0-based position in idx of each entry, panel order
+ *   slot_target   [slots] int32: row written by the slot
+ *   slot_ptr      [slots+1] int32: the slot's entries, panel order
+ *   slot_panel    [slots] int32: panel of the slot
+ *   chunk_slot    [chunks+1] int32: slots of each workgroup chunk
+ *   first_parked  *int32: slots from here on are colour 1 (their sums are
+ *                 parked, then added to y row by row)
+ * Any output may be NULL.  Same errors as cg_analyze.
+ */
+int cg_analyze_panels(int64_t n, const int32_t *ptr, const int32_t *idx, int index_base, int64_t *width,
+                      int32_t *entry_src, int32_t *slot_target, int32_t *slot_ptr, int32_t *slot_panel,
+                      int32_t *chunk_slot, int32_t *first_parked);
 
 #ifdef __cplusplus
 }

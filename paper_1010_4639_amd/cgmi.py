@@ -30,7 +30,7 @@ EXPORTS = ("cg_create", "cg_set_stream", "cg_set_batch", "cg_solve", "cg_solve_m
            "cg_batch_create", "cg_batch_set_stream", "cg_batch_spmm", "cg_batch_autotune", "cg_batch_solve",
            "cg_batch_destroy", "cg_batch_last_error", "cg_set_values", "cg_pattern_grad", "cg_fem_create",
            "cg_fem_set_stream", "cg_fem_pattern", "cg_fem_assemble", "cg_fem_nu_grad", "cg_fem_destroy",
-           "cg_fem_last_error")
+           "cg_fem_last_error", "cg_analyze_panels")
 
 
 class cg_info(ctypes.Structure):
@@ -103,6 +103,7 @@ def load():
     lib.cg_batch_destroy.restype = None
     lib.cg_batch_last_error.argtypes = [_VP]
     lib.cg_batch_last_error.restype = ctypes.c_char_p
+    lib.cg_analyze_panels.argtypes = [i64, _VP, _VP, ctypes.c_int] + [_VP] * 7
     lib.cg_set_values.argtypes = [_VP, _VP]
     lib.cg_pattern_grad.argtypes = [_VP, _VP, _VP, _VP]
     lib.cg_fem_create.argtypes = [ctypes.POINTER(_VP), i64, _VP, i64, _VP, _VP, i64]
@@ -116,7 +117,7 @@ def load():
     lib.cg_fem_last_error.restype = ctypes.c_char_p
     for nm in ("cg_batch_create", "cg_batch_set_stream", "cg_batch_spmm", "cg_batch_autotune", "cg_batch_solve",
                "cg_set_values", "cg_pattern_grad", "cg_fem_create", "cg_fem_set_stream", "cg_fem_pattern",
-               "cg_fem_assemble", "cg_fem_nu_grad"):
+               "cg_fem_assemble", "cg_fem_nu_grad", "cg_analyze_panels"):
         getattr(lib, nm).restype = ctypes.c_int
     for nm in ("cg_create", "cg_set_stream", "cg_set_batch", "cg_solve", "cg_solve_mixed", "cg_spmv", "cg_get_stats",
                "cg_analyze", "cg_analyze_export"):
@@ -230,6 +231,26 @@ def cg_analyze_export(fmt, n, ptr, idx, index_base=0):
                                   *[_np_ptr(out[k]) for k in ("color", "line0", "line1", "entry0", "entry1",
                                                               "slot0", "target", "flags", "count")])
     out["stats"] = stats
+    return st, out
+
+
+def cg_analyze_panels(n, ptr, idx, index_base=0):
+    """Host-only CSC panel plan; returns (status, dict of numpy arrays)."""
+    lib = load()
+    st, stats = cg_analyze(CG_FMT_CSC, n, ptr, idx, None, index_base)
+    if st != CG_OK:
+        return st, None
+    p, i = _host_i32(ptr), _host_i32(idx)
+    nnz, ns, nch = int(stats["nnz"]), int(stats["slots"]), int(stats["scatter_blocks"])
+    out = dict(stats=stats, entry_src=np.empty(max(nnz, 1), np.int32), target=np.empty(max(ns, 1), np.int32),
+               slot_ptr=np.empty(ns + 1, np.int32), panel=np.empty(max(ns, 1), np.int32),
+               chunk_slot=np.empty(nch + 1, np.int32))
+    w, fp = ctypes.c_int64(), ctypes.c_int32()
+    st = lib.cg_analyze_panels(n, _np_ptr(p), _np_ptr(i), index_base, ctypes.byref(w), _np_ptr(out["entry_src"]),
+                               _np_ptr(out["target"]), _np_ptr(out["slot_ptr"]), _np_ptr(out["panel"]),
+                               _np_ptr(out["chunk_slot"]), ctypes.byref(fp))
+    out["entry_src"], out["target"], out["panel"] = out["entry_src"][:nnz], out["target"][:ns], out["panel"][:ns]
+    out["width"], out["first_parked"] = w.value, fp.value
     return st, out
 
 

@@ -155,13 +155,71 @@ int upload_all(cg_handle *h, const std::vector<int32_t> &ptr0, const std::vector
     m.val = dval;
     if (p.format == kCsr && p.csr_stream) {
         int32_t *rb;
-        if ((st = upload(h, &rb, p.csr_rb.data(), p.csr_rb.size())) != CG_OK)
+        int2 *rbe;
+        std::vector<int2> bnd(p.csr_rb.size());
+        for (size_t i = 0; i < bnd.size(); ++i)
+            bnd[i] = make_int2(p.csr_rb[i], ptr0[p.csr_rb[i]]);
+        if ((st = upload(h, &rb, p.csr_rb.data(), p.csr_rb.size())) != CG_OK ||
+            (st = upload(h, &rbe, bnd.data(), bnd.size())) != CG_OK)
             return st;
         m.csr_stream = true;
         m.csr_rb = rb;
+        m.csr_rbe = rbe;
         m.csr_nrb = (int)p.csr_rb.size() - 1;
     }
-    if (p.format != kCsr && n > 0) {
+    if (p.panel && n > 0) {
+        // CSC column panels: slots of colour 0 first (see plan.h)
+        const int64_t ns = (int64_t)p.pn_slot_target.size();
+        const int32_t fp = p.pn_first_parked;
+        std::vector<int32_t> rsp((size_t)n + 1, 0), rsi;
+        std::vector<uint8_t> c0((size_t)n, 0);
+        for (int64_t q = 0; q < ns; ++q) {
+            if (q < fp)
+                c0[p.pn_slot_target[q]] = 1;
+            else
+                rsp[p.pn_slot_target[q] + 1]++;
+        }
+        bool gather = ns > fp;
+        for (int64_t i = 0; i < n; ++i) {
+            gather = gather || (!c0[i] && rsp[i + 1] == 0);
+            rsp[i + 1] += rsp[i];
+        }
+        rsi.resize(rsp[n]);
+        {
+            std::vector<int32_t> next(rsp.begin(), rsp.end() - 1);
+            for (int64_t q = fp; q < ns; ++q)
+                rsi[next[p.pn_slot_target[q]]++] = (int32_t)(q - fp);
+        }
+        int32_t *cs, *sp, *stg, *pc, *src, *drsp, *drsi;
+        uint8_t *dc0;
+        double *pv, *part;
+        if ((st = upload(h, &cs, p.pn_chunk_slot.data(), p.pn_chunk_slot.size())) != CG_OK ||
+            (st = upload(h, &sp, p.pn_slot_ptr.data(), p.pn_slot_ptr.size())) != CG_OK ||
+            (st = upload(h, &stg, p.pn_slot_target.data(), p.pn_slot_target.size())) != CG_OK ||
+            (st = upload(h, &pc, p.pn_col.data(), p.pn_col.size())) != CG_OK ||
+            (st = upload(h, &src, p.pn_src.data(), p.pn_src.size())) != CG_OK ||
+            (st = dalloc(h, &pv, p.pn_src.size())) != CG_OK || (st = dalloc(h, &part, (size_t)(ns - fp))) != CG_OK ||
+            (st = upload(h, &drsp, rsp.data(), rsp.size())) != CG_OK ||
+            (st = upload(h, &drsi, rsi.data(), rsi.size())) != CG_OK ||
+            (st = upload(h, &dc0, c0.data(), c0.size())) != CG_OK)
+            return st;
+        m.panel = true;
+        m.pn_gather = gather;
+        m.pn_chunk_slot = cs;
+        m.pn_slot_ptr = sp;
+        m.pn_slot_target = stg;
+        m.pn_col = pc;
+        m.pn_src = src;
+        m.pn_val = pv;
+        m.pn_first_parked = fp;
+        m.part = part;
+        m.rs_ptr = drsp;
+        m.rs_idx = drsi;
+        m.has_c0 = dc0;
+        m.scatter_wgs = p.scatter_wgs();
+        if (h->mixed && (st = dalloc(h, &m.pn_val32, p.pn_src.size())) != CG_OK)
+            return st;
+    } else if (p.format != kCsr && n > 0) {
         // device arrays in colour order: the blocks of one colour, and their
         // write slots, are contiguous
         const int nb = p.nblocks;
@@ -276,7 +334,7 @@ void fill_stats(const Plan &p, cg_plan_stats *s)
     s->vec_blocks = p.vec_blocks;
     s->colors = p.ncolors;
     s->max_block_entries = p.max_entries;
-    s->slots = (int64_t)p.slot_target.size();
+    s->slots = p.panel ? (int64_t)p.pn_slot_target.size() : (int64_t)p.slot_target.size();
     s->plan_bytes = p.device_bytes();
 }
 
@@ -401,6 +459,26 @@ int mixed_rescale(cg_handle *h)
     return CG_OK;
 }
 
+// Every array derived from the FP64 values (CSC panel order, the mixed
+// FP32 scaled copy) rebuilt from dm.val, on the handle's stream.
+int refresh_values(cg_handle *h)
+{
+    DevMatrix &m = h->dm;
+    const int64_t nnz = h->plan.nnz;
+    if (m.panel)
+        launch_permute(nnz, m.val, m.pn_src, m.pn_val, h->stream);
+    HIP_TRY(h, hipGetLastError());
+    if (h->mixed && m.n > 0) {
+        const int st = mixed_rescale(h);
+        if (st != CG_OK)
+            return st;
+        if (m.panel)
+            launch_permute(nnz, m.val32, m.pn_src, m.pn_val32, h->stream);
+        HIP_TRY(h, hipGetLastError());
+    }
+    return CG_OK;
+}
+
 int status_to_code(int32_t s)
 {
     switch (s) {
@@ -448,6 +526,10 @@ int cg_analyze_export(int format, int64_t n, const int32_t *ptr, const int32_t *
         g_err = "CSR has no scatter plan";
         return CG_ERR_ARG;
     }
+    if (format == kCsc) {
+        g_err = "CSC uses the column-panel plan (cg_analyze_panels)";
+        return CG_ERR_ARG;
+    }
     std::vector<int32_t> p0, i0;
     std::string err;
     int st;
@@ -471,6 +553,36 @@ int cg_analyze_export(int format, int64_t n, const int32_t *ptr, const int32_t *
             if (slot_target) std::memcpy(slot_target, plan.slot_target.data(), ns * 4);
             if (slot_flags) std::memcpy(slot_flags, plan.slot_flag.data(), ns);
             if (slot_count) std::memcpy(slot_count, plan.slot_count.data(), ns * 4);
+        }
+    } catch (const std::bad_alloc &) {
+        err = "host allocation failed";
+        st = CG_ERR_NOMEM;
+    }
+    g_err = st == CG_OK ? std::string() : err;
+    return st;
+}
+
+int cg_analyze_panels(int64_t n, const int32_t *ptr, const int32_t *idx, int index_base, int64_t *width,
+                      int32_t *entry_src, int32_t *slot_target, int32_t *slot_ptr, int32_t *slot_panel,
+                      int32_t *chunk_slot, int32_t *first_parked)
+{
+    std::vector<int32_t> p0, i0;
+    std::string err;
+    int st;
+    try {
+        st = validate_and_normalise(kCsc, n, ptr, idx, nullptr, index_base, 0, p0, i0, err);
+        Plan plan;
+        if (st == CG_OK)
+            st = build_plan(kCsc, n, p0.data(), i0.data(), 0, plan, err);
+        if (st == CG_OK) {
+            const size_t ns = plan.pn_slot_target.size();
+            if (width) *width = plan.pn_width;
+            if (first_parked) *first_parked = plan.pn_first_parked;
+            if (entry_src) std::memcpy(entry_src, plan.pn_src.data(), plan.pn_src.size() * 4);
+            if (slot_target) std::memcpy(slot_target, plan.pn_slot_target.data(), ns * 4);
+            if (slot_ptr) std::memcpy(slot_ptr, plan.pn_slot_ptr.data(), plan.pn_slot_ptr.size() * 4);
+            if (slot_panel) std::memcpy(slot_panel, plan.pn_slot_panel.data(), ns * 4);
+            if (chunk_slot) std::memcpy(chunk_slot, plan.pn_chunk_slot.data(), plan.pn_chunk_slot.size() * 4);
         }
     } catch (const std::bad_alloc &) {
         err = "host allocation failed";
@@ -515,8 +627,8 @@ int cg_create(cg_handle **out, int format, int64_t n, const int32_t *ptr, const 
             st = upload(h.get(), &h->perm, perm.data(), perm.size());
         if (st == CG_OK)
             st = dalloc(h.get(), &h->flag, 1);
-        if (st == CG_OK && h->mixed && n > 0)
-            st = mixed_rescale(h.get());
+        if (st == CG_OK)
+            st = refresh_values(h.get());
         if (st != CG_OK) {
             g_err = h->err;
             release(h.get());
@@ -746,9 +858,7 @@ int cg_set_values(cg_handle *h, const double *vals)
     hipStream_t s = h->stream;
     launch_set_values(nnz, vals, h->perm, const_cast<double *>(h->dm.val), s);
     HIP_TRY(h, hipGetLastError());
-    if (h->mixed && h->dm.n > 0)
-        return mixed_rescale(h);
-    return CG_OK;
+    return refresh_values(h);
 }
 
 int cg_pattern_grad(cg_handle *h, const double *lam, const double *x, double *grad)

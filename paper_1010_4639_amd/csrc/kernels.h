@@ -54,6 +54,7 @@ struct DevMatrix {
     bool csr_stream = false;
     int csr_nrb = 0;
     const int32_t *csr_rb = nullptr;
+    const int2 *csr_rbe = nullptr;       // per row-block boundary: {first row, first entry}
     // scatter
     int nblocks = 0, ncolors = 0, lds_entries = 0, lds_lines = 0, max_slots = 0;
     std::vector<int32_t> color_off;      // host copy: blocks per colour
@@ -68,6 +69,14 @@ struct DevMatrix {
     const uint8_t *slot_flag = nullptr;
     const uint16_t *seg = nullptr;
     const uint16_t *tl = nullptr;
+    // CSC column panels (nblocks = chunks, scatter_wgs = their workgroups)
+    bool panel = false;
+    bool pn_gather = false;               // some row has parked sums or no writer
+    const int32_t *pn_chunk_slot = nullptr, *pn_slot_ptr = nullptr, *pn_slot_target = nullptr;
+    const int32_t *pn_col = nullptr, *pn_src = nullptr;
+    double *pn_val = nullptr;             // values in panel order (from val through pn_src)
+    float *pn_val32 = nullptr;            // mixed precision: val32 in panel order
+    int pn_first_parked = 0;
     // vectors
     int vec_blocks = 0, vec_chunk = 0;
     int spmv_blocks() const { return format == kCsr ? csr_blocks : scatter_wgs; }
@@ -114,6 +123,9 @@ void launch_init_state(const DevMatrix &m, DevState *st, const double *bb_part, 
 void launch_true_residual(const DevMatrix &m, const double *b, const double *q, double *part, DevState *st,
                           hipStream_t s);
 void launch_fill(int n, double *x, double v, hipStream_t s);
+// dst[k] = src[perm[k]] for k < nnz (values into the CSC panel order)
+void launch_permute(int64_t nnz, const double *src, const int32_t *perm, double *dst, hipStream_t s);
+void launch_permute(int64_t nnz, const float *src, const int32_t *perm, float *dst, hipStream_t s);
 // val[k] = src[perm ? perm[k] : k] for k < nnz
 void launch_set_values(int64_t nnz, const double *src, const int32_t *perm, double *val, hipStream_t s);
 // mixed precision: recompute D^-1/2 and the FP32 scaled values from m.val; *bad <- 1 on a bad diagonal

@@ -127,14 +127,19 @@ __global__ __launch_bounds__(kBlock) void k_spmv_csr(int n, int rows_per_block, 
 
 // ------------------------------------------------- CSR row blocks
 // Short rows (the FEM case): a workgroup takes a contiguous range of row
-// blocks (<= 256 rows, <= 2048 entries each).  For each block every thread
-// first issues its 8 index / value loads (fully coalesced, non-temporal) and
-// then the 8 gathers of x, parks the products in LDS, and after one barrier
-// each row is summed left to right by one thread -- the same order as the
-// textbook loop, so y is bit-identical to a serial row-by-row product.  A row
-// longer than a block is summed by the whole workgroup (fixed tree).
+// blocks (<= 256 rows, <= 2048 entries each).  The boundaries {first row,
+// first entry} of every block are precomputed (uniform: scalar loads, no
+// dependent read of the row pointers).  For each block every thread first
+// issues its 8 index / value loads (fully coalesced, non-temporal) and its
+// row's local pointer, then the 8 gathers of x, parks the products in LDS,
+// and after one barrier each row is summed left to right by one thread -- the
+// same order as the textbook loop, so y is bit-identical to a serial
+// row-by-row product.  A row longer than a block is summed by the whole
+// workgroup (fixed tree).  (Prefetching the next block into registers was
+// measured slower: the extra registers cut the resident workgroups by more
+// than the latency it hides.)
 template <class VT, class PT>
-__global__ __launch_bounds__(kBlock) void k_spmv_csr_rows(int nrb, const int32_t *__restrict__ rb_row,
+__global__ __launch_bounds__(kBlock) void k_spmv_csr_rows(int nrb, const int2 *__restrict__ rbe,
                                                           const int32_t *__restrict__ ptr,
                                                           const int32_t *__restrict__ col,
                                                           const VT *__restrict__ val,
@@ -153,9 +158,9 @@ __global__ __launch_bounds__(kBlock) void k_spmv_csr_rows(int nrb, const int32_t
     const int t = threadIdx.x;
     double sig = 0.0;
     for (int b = b0; b < b1; ++b) {
-        const int r0 = rb_row[b], r1 = rb_row[b + 1];
-        const int nr = r1 - r0;
-        const int e0 = ptr[r0], e1 = ptr[r1];
+        const int2 lo = rbe[b], hi = rbe[b + 1];
+        const int r0 = lo.x, nr = hi.x - lo.x;
+        const int e0 = lo.y, e1 = hi.y;
         if (e1 - e0 > kStreamEntries) { // one long row
             double a = 0.0;
             for (int e = e0 + t; e < e1; e += kBlock)
@@ -199,6 +204,106 @@ __global__ __launch_bounds__(kBlock) void k_spmv_csr_rows(int nrb, const int32_t
     sig = block_sum(sig, red);
     if (t == 0)
         sig_part[wg] = sig;
+}
+
+// ------------------------------------------------- CSC column panels
+// One launch over every chunk of every panel (chunks of colour 0 first; a
+// workgroup walks a contiguous range of chunks).  A chunk is a run of write
+// slots -- (panel, row) pairs, each a contiguous segment of entries in column
+// order -- so it is processed like a CSR row block: coalesced index / value
+// loads, the gathers of x, products parked in LDS, one thread per slot sums
+// its segment left to right.  Colour-0 slots store y; colour-1 slots park the
+// sum for k_scatter_gather.  x'y is linear in the slot sums, so each
+// workgroup accumulates sum_slots x_row * sum.  A slot longer than a chunk
+// is summed by the whole workgroup (fixed tree).
+template <class VT, class PT>
+__global__ __launch_bounds__(kBlock) void k_panel_rows(int nch, const int32_t *__restrict__ chunk_slot,
+                                                       const int32_t *__restrict__ slot_ptr,
+                                                       const int32_t *__restrict__ slot_target,
+                                                       const int32_t *__restrict__ col, const VT *__restrict__ val,
+                                                       const PT *__restrict__ x, double *__restrict__ y,
+                                                       double *__restrict__ part, int first_parked,
+                                                       double *__restrict__ sig_part, DevState *st)
+{
+    constexpr int E = kStreamPerThread;
+    __shared__ double prod[kStreamEntries];
+    __shared__ int32_t lptr[kStreamRows + 1];
+    __shared__ double red[kWaves];
+    const int wg = xcd_remap(blockIdx.x, gridDim.x);
+    if (st != nullptr && !iter_gate(st))
+        return;
+    const int c0 = (int)((int64_t)wg * nch / gridDim.x);
+    const int c1 = (int)((int64_t)(wg + 1) * nch / gridDim.x);
+    const int t = threadIdx.x;
+    double sig = 0.0;
+    for (int c = c0; c < c1; ++c) {
+        const int s0 = chunk_slot[c], ns = chunk_slot[c + 1] - s0;
+        const int e0 = slot_ptr[s0], e1 = slot_ptr[s0 + ns];
+        if (e1 - e0 > kStreamEntries) { // one long slot
+            double a = 0.0;
+            for (int e = e0 + t; e < e1; e += kBlock)
+                a = fma((double)__builtin_nontemporal_load(val + e), (double)x[__builtin_nontemporal_load(col + e)],
+                        a);
+            a = block_sum(a, red);
+            if (t == 0) {
+                const int tg = slot_target[s0];
+                if (s0 < first_parked)
+                    y[tg] = a;
+                else
+                    part[s0 - first_parked] = a;
+                sig = fma((double)x[tg], a, sig);
+            }
+            continue;
+        }
+        int cc[E];
+        double v[E];
+#pragma unroll
+        for (int m = 0; m < E; ++m) {
+            const int e = e0 + t + m * kBlock;
+            const bool ok = e < e1;
+            cc[m] = ok ? __builtin_nontemporal_load(col + e) : -1;
+            v[m] = ok ? (double)__builtin_nontemporal_load(val + e) : 0.0;
+        }
+        int tg = -1;
+        if (t < ns) {
+            lptr[t + 1] = __builtin_nontemporal_load(slot_ptr + s0 + t + 1) - e0;
+            tg = __builtin_nontemporal_load(slot_target + s0 + t);
+        }
+        if (t == 0)
+            lptr[0] = 0;
+#pragma unroll
+        for (int m = 0; m < E; ++m)
+            if (cc[m] >= 0)
+                prod[t + m * kBlock] = v[m] * (double)x[cc[m]];
+        const double xt = tg >= 0 ? (double)x[tg] : 0.0;
+        __syncthreads();
+        if (t < ns) {
+            double a = 0.0;
+            const int k1 = lptr[t + 1];
+            for (int k = lptr[t]; k < k1; ++k)
+                a += prod[k];
+            const int sl = s0 + t;
+            if (sl < first_parked)
+                y[tg] = a;
+            else
+                part[sl - first_parked] = a;
+            sig = fma(xt, a, sig);
+        }
+        __syncthreads();
+    }
+    sig = block_sum(sig, red);
+    if (t == 0)
+        sig_part[wg] = sig;
+}
+
+// dst[k] = src[perm[k]]: values into the panel order
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_permute(int64_t nnz, const T *__restrict__ src,
+                                                    const int32_t *__restrict__ perm, T *__restrict__ dst)
+{
+    const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (k < nnz)
+        dst[k] = src[perm[k]];
 }
 
 // ------------------------------------------------- coloured scatter
@@ -354,9 +459,13 @@ __global__ __launch_bounds__(kBlock) void k_scatter_gather(int n, const int32_t 
     if (i >= n)
         return;
     const int k0 = rs_ptr[i], k1 = rs_ptr[i + 1];
-    if (k0 == k1)
-        return; // written once, by its colour-0 block
-    double a = has_c0[i] ? y[i] : 0.0;
+    const bool c0 = has_c0[i] != 0;
+    if (k0 == k1) {
+        if (!c0)
+            y[i] = 0.0; // no entry writes this row
+        return;         // else written once, by its colour-0 block
+    }
+    double a = c0 ? y[i] : 0.0;
     for (int k = k0; k < k1; ++k)
         a += part[rs_idx[k]];
     y[i] = a;
@@ -720,14 +829,27 @@ void scatter_dispatch(const DevMatrix &m, const VT *val, const PT *x, double *y,
         scatter_launch<SYM, 9>(m, val, x, y, sig, c, s);
 }
 
+inline const double *panel_vals(const DevMatrix &m, const double *) { return m.pn_val; }
+inline const float *panel_vals(const DevMatrix &m, const float *) { return m.pn_val32; }
+
 template <class VT, class PT>
 void spmv_any(const DevMatrix &m, const VT *val, const PT *x, double *y, double *sig_part, const IterCtx &c,
               hipStream_t s)
 {
     if (m.n == 0)
         return;
+    if (m.panel) {
+        if (m.nblocks > 0)
+            hipLaunchKernelGGL((k_panel_rows<VT, PT>), dim3(m.scatter_wgs), dim3(kBlock), 0, s, m.nblocks,
+                               m.pn_chunk_slot, m.pn_slot_ptr, m.pn_slot_target, m.pn_col, panel_vals(m, val), x, y,
+                               m.part, m.pn_first_parked, sig_part, c.st);
+        if (m.pn_gather)
+            hipLaunchKernelGGL(k_scatter_gather, dim3((m.n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, m.n,
+                               m.rs_ptr, m.rs_idx, m.has_c0, m.part, y, c.st);
+        return;
+    }
     if (m.format == kCsr && m.csr_stream) {
-        hipLaunchKernelGGL((k_spmv_csr_rows<VT, PT>), dim3(m.csr_blocks), dim3(kBlock), 0, s, m.csr_nrb, m.csr_rb,
+        hipLaunchKernelGGL((k_spmv_csr_rows<VT, PT>), dim3(m.csr_blocks), dim3(kBlock), 0, s, m.csr_nrb, m.csr_rbe,
                            m.ptr, m.idx, val, x, y, sig_part, c.st);
     } else if (m.format == kCsr) {
         switch (m.lanes) {
@@ -824,6 +946,20 @@ void launch_fill(int n, double *x, double v, hipStream_t s)
 {
     if (n > 0)
         hipLaunchKernelGGL(k_fill, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, n, x, v);
+}
+
+void launch_permute(int64_t nnz, const double *src, const int32_t *perm, double *dst, hipStream_t s)
+{
+    if (nnz > 0)
+        hipLaunchKernelGGL(k_permute<double>, dim3((unsigned)((nnz + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, nnz,
+                           src, perm, dst);
+}
+
+void launch_permute(int64_t nnz, const float *src, const int32_t *perm, float *dst, hipStream_t s)
+{
+    if (nnz > 0)
+        hipLaunchKernelGGL(k_permute<float>, dim3((unsigned)((nnz + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, nnz,
+                           src, perm, dst);
 }
 
 void launch_set_values(int64_t nnz, const double *src, const int32_t *perm, double *val, hipStream_t s)

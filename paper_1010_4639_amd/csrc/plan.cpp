@@ -13,6 +13,9 @@ int64_t Plan::device_bytes() const
 {
     if (format == kCsr)
         return (int64_t)csr_rb.size() * 4;
+    if (panel) // entry source + column + reordered value; slot target / pointer / parked sum; row lists
+        return nnz * (4 + 4 + 8) + (int64_t)pn_slot_target.size() * (4 + 4 + 8 + 4) +
+               (int64_t)pn_chunk_slot.size() * 8 + n * 5;
     // descriptors, slot target / flag / segment offsets, contributions, parked
     // sums and their per-row index (upper bounds: every slot counted)
     return (int64_t)blocks.size() * sizeof(ScatterBlock) + (int64_t)slot_target.size() * (4 + 1 + 8 + 4) +
@@ -202,6 +205,91 @@ static void plan_csr(Plan &p, const int32_t *ptr)
     g = std::max<int64_t>(1, std::min<int64_t>(g, kMaxSpmvBlocks));
     p.csr_blocks = (int)g;
     p.csr_rows_per_block = (int)((n + g - 1) / g);
+}
+
+// CSC column panels (see plan.h).
+static int plan_panels(Plan &p, const int32_t *ptr, const int32_t *idx, std::string &err)
+{
+    const int64_t n = p.n, nnz = p.nnz;
+    int64_t bw = 0;
+    for (int64_t j = 0; j < n; ++j)
+        for (int64_t k = ptr[j]; k < ptr[j + 1]; ++k)
+            bw = std::max<int64_t>(bw, std::llabs((int64_t)idx[k] - j));
+    const int64_t W = std::min<int64_t>(n, std::max<int64_t>(2 * bw + 1, kPanelMinWidth));
+    const int64_t np = (n + W - 1) / W;
+    p.panel = true;
+    p.pn_width = W;
+    p.pn_npanels = (int)np;
+    p.pn_src.resize((size_t)nnz);
+    p.pn_col.resize((size_t)nnz);
+    p.pn_slot_target.clear();
+    p.pn_slot_panel.clear();
+    p.pn_slot_ptr.assign(1, 0);
+    std::vector<int64_t> cnt;
+    int64_t pos = 0;
+    for (int parity = 0; parity < 2; ++parity) {
+        if (parity == 1)
+            p.pn_first_parked = (int32_t)p.pn_slot_target.size();
+        for (int64_t k = parity; k < np; k += 2) {
+            const int64_t c0 = k * W, c1 = std::min(n, c0 + W);
+            const int64_t rlo = std::max<int64_t>(0, c0 - bw), rhi = std::min(n, c1 + bw);
+            cnt.assign((size_t)(rhi - rlo + 1), 0);
+            for (int64_t j = c0; j < c1; ++j)
+                for (int64_t e = ptr[j]; e < ptr[j + 1]; ++e)
+                    cnt[idx[e] - rlo + 1]++;
+            for (int64_t r = 0; r < rhi - rlo; ++r) {
+                if (cnt[r + 1] > 0) {
+                    p.pn_slot_target.push_back((int32_t)(rlo + r));
+                    p.pn_slot_panel.push_back((int32_t)k);
+                    p.pn_slot_ptr.push_back((int32_t)(pos + cnt[r] + cnt[r + 1]));
+                }
+                cnt[r + 1] += cnt[r];
+            }
+            // stable placement: columns ascending, so each row's segment is in column order
+            for (int64_t j = c0; j < c1; ++j)
+                for (int64_t e = ptr[j]; e < ptr[j + 1]; ++e) {
+                    const int64_t q = pos + cnt[idx[e] - rlo]++;
+                    p.pn_src[q] = (int32_t)e;
+                    p.pn_col[q] = (int32_t)j;
+                }
+            pos += cnt[rhi - rlo];
+        }
+    }
+    if (np < 2)
+        p.pn_first_parked = (int32_t)p.pn_slot_target.size();
+    if (pos != nnz) {
+        err = "internal: panel placement lost entries";
+        return CG_ERR_HIP;
+    }
+    // chunks: consecutive slots, <= kPanelChunkEntries entries and
+    // <= kPanelChunkSlots slots; a longer slot is a chunk of its own
+    const int64_t ns = (int64_t)p.pn_slot_target.size();
+    p.pn_chunk_slot.assign(1, 0);
+    int64_t s0 = 0;
+    for (int64_t s = 0; s < ns; ++s) {
+        const int64_t len = (int64_t)p.pn_slot_ptr[s + 1] - p.pn_slot_ptr[s];
+        if (s > s0 && ((int64_t)p.pn_slot_ptr[s + 1] - p.pn_slot_ptr[s0] > kPanelChunkEntries ||
+                       s - s0 >= kPanelChunkSlots || len > kPanelChunkEntries)) {
+            p.pn_chunk_slot.push_back((int32_t)s);
+            s0 = s;
+        }
+        if (len > kPanelChunkEntries) {
+            p.pn_chunk_slot.push_back((int32_t)(s + 1));
+            s0 = s + 1;
+        }
+    }
+    if (p.pn_chunk_slot.back() != ns)
+        p.pn_chunk_slot.push_back((int32_t)ns);
+    const int64_t nch = (int64_t)p.pn_chunk_slot.size() - 1;
+    p.nblocks = (int)nch;
+    p.ncolors = np >= 2 && p.pn_first_parked < ns ? 2 : (ns > 0 ? 1 : 0);
+    p.max_entries = 0;
+    for (int64_t c = 0; c < nch; ++c)
+        p.max_entries = std::max<int>(p.max_entries, p.pn_slot_ptr[p.pn_chunk_slot[c + 1]] -
+                                                         p.pn_slot_ptr[p.pn_chunk_slot[c]]);
+    p.max_slots = kPanelChunkSlots;
+    p.max_lines = 0;
+    return CG_OK;
 }
 
 static int plan_scatter(Plan &p, const int32_t *ptr, const int32_t *idx, int target_entries, std::string &err)
@@ -418,6 +506,8 @@ int build_plan(int fmt, int64_t n, const int32_t *ptr0, const int32_t *idx0, int
         plan_csr(p, ptr0);
         return CG_OK;
     }
+    if (fmt == kCsc)
+        return plan_panels(p, ptr0, idx0, err);
     if (target_entries <= 0)
         target_entries = kDefaultScatterEntries;
     target_entries = std::min(target_entries, kMaxScatterEntries);

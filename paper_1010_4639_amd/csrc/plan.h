@@ -13,6 +13,18 @@
 // two flags: FIRST (no earlier colour writes that row, so the block stores
 // instead of read-modify-write) and LAST (no later colour writes it, so the
 // block holds the final y_i and adds p_i y_i to the fused dot product).
+//
+// CSC plan ("column panels").  The columns are cut into panels of W >= 2 bw + 1
+// consecutive columns (bw = the largest |i - j| of a stored entry), so panel
+// k only writes rows within bw of its columns and panels k and k + 2 never
+// share a row: even panels form colour 0, odd panels colour 1.  Inside a
+// panel the entries are ordered by row, then column, so every (panel, row)
+// pair -- a write slot -- is one contiguous segment summed in ascending column
+// order, and consecutive slots are grouped into chunks (<= 2048 entries,
+// <= 256 slots) for the workgroups.  Slots of colour 0 come first and write
+// y; colour-1 slots are parked and added row by row afterwards.  This is the
+// two-dimensional blocking of compressed-sparse-blocks storage applied to
+// the transpose product: column blocks for the scatter, row order inside.
 #pragma once
 
 #include <cstdint>
@@ -32,6 +44,9 @@ constexpr int kStreamPerThread = 8;                    // CSR row-block kernel: 
 constexpr int kStreamEntries = kBlock * kStreamPerThread; // entries per CSR row block
 constexpr int kStreamRows = kBlock;                    // rows per CSR row block (one thread each)
 constexpr double kStreamMaxMeanRow = 32.0;             // longer mean rows use lanes-per-row
+constexpr int kPanelMinWidth = 4096;    // CSC panels span at least this many columns
+constexpr int kPanelChunkEntries = kStreamEntries; // entries per CSC panel chunk
+constexpr int kPanelChunkSlots = kBlock;           // slots per CSC panel chunk (one thread each)
 constexpr uint8_t kSlotFirst = 1;
 constexpr uint8_t kSlotLast = 2;
 
@@ -66,6 +81,17 @@ struct Plan {
     std::vector<int32_t> slot_count;      // contributions per slot (export / checks only)
     std::vector<uint16_t> seg;            // per block nslots + 1 local offsets into its contributions
     std::vector<uint16_t> tl;             // local entry index (k - k0) of every contribution
+    // CSC column panels (format kCsc): entries in panel order
+    bool panel = false;
+    int64_t pn_width = 0;
+    int pn_npanels = 0;
+    std::vector<int32_t> pn_src;          // [nnz] caller entry (0-based) of each panel-order entry
+    std::vector<int32_t> pn_col;          // [nnz] column of each panel-order entry
+    std::vector<int32_t> pn_slot_target;  // [slots] row written
+    std::vector<int32_t> pn_slot_ptr;     // [slots + 1] entries of each slot (panel order)
+    std::vector<int32_t> pn_slot_panel;   // [slots] panel of each slot (export / checks)
+    std::vector<int32_t> pn_chunk_slot;   // [chunks + 1] slots of each chunk
+    int32_t pn_first_parked = 0;          // slots >= this belong to colour 1
     // vector kernels
     int vec_blocks = 0, vec_chunk = 0;
 

@@ -355,6 +355,23 @@ def random_sparse(n, *, density=0.05, seed=0, empty_rows=0, long_rows=0, long_le
     return rowptr.astype(np.int32), col, val
 
 
+def banded_sparse(n, bw, *, density=0.01, seed=0, empty=0):
+    """Random non-symmetric sparse matrix with every entry within bw of the
+    diagonal (|i - j| <= bw), sorted CSR arrays (read them as CSC just as
+    well); `empty` lines carry no entry.  Values ~ U(-1, 1)."""
+    rng = np.random.default_rng(seed)
+    dead = set(rng.choice(n, size=empty, replace=False).tolist()) if empty else set()
+    lines = []
+    for j in range(n):
+        lo, hi = max(0, j - bw), min(n, j + bw + 1)
+        k = 0 if j in dead else rng.binomial(hi - lo, density)
+        lines.append(np.sort(rng.choice(np.arange(lo, hi), size=k, replace=False)))
+    ptr = np.zeros(n + 1, np.int64)
+    ptr[1:] = np.cumsum([c.size for c in lines])
+    idx = np.concatenate(lines).astype(np.int32)
+    return ptr.astype(np.int32), idx, rng.uniform(-1.0, 1.0, size=idx.size)
+
+
 def random_spd_dense(n, *, seed=0):
     """Dense SPD matrix M = B^T B + n I with B ~ U(-1,1), as full CSR."""
     rng = np.random.default_rng(seed)

@@ -129,28 +129,103 @@ def test_scatter_plan_fem_symcsr():
     assert P["stats"]["colors"] <= 8
 
 
-def test_scatter_plan_fem_csc():
+def check_panel_plan(ptr, idx, base=0):
+    """Re-derives the CSC column-panel plan from the arrays and compares."""
+    n = len(ptr) - 1
+    st, P = cgmi.cg_analyze_panels(n, ptr, idx, base)
+    assert st == 0, cgmi.cg_last_error(None)
+    p0 = np.asarray(ptr, np.int64) - base
+    i0 = np.asarray(idx, np.int64) - base
+    nnz = int(p0[-1])
+    col_of = np.repeat(np.arange(n), np.diff(p0))             # column of each stored entry
+    bw = int(np.max(np.abs(i0 - col_of))) if nnz else 0
+    W = P["width"]
+    assert W >= min(n, 2 * bw + 1) and W >= min(n, 4096)
+    src = P["entry_src"]
+    assert np.array_equal(np.sort(src), np.arange(nnz)), "entries lost or duplicated"
+    rows, cols = i0[src], col_of[src]
+    ns = P["target"].size
+    sp = P["slot_ptr"]
+    assert sp[0] == 0 and sp[-1] == nnz and np.all(np.diff(sp) > 0)
+    seen = set()
+    for s_ in range(ns):
+        seg = slice(sp[s_], sp[s_ + 1])
+        pk = int(P["panel"][s_])
+        assert np.all(rows[seg] == P["target"][s_])
+        assert np.all(cols[seg] // W == pk)
+        assert np.all(np.diff(cols[seg]) > 0), "segment not in ascending column order"
+        key = (pk, int(P["target"][s_]))
+        assert key not in seen
+        seen.add(key)
+    # every (panel, row) pair with entries is exactly one slot
+    assert seen == set(zip((col_of // W).tolist(), i0.tolist()))
+    # colour 0 = even panels first, then odd; same-colour panels never share a row
+    fp = P["first_parked"]
+    assert np.all(P["panel"][:fp] % 2 == 0) and np.all(P["panel"][fp:] % 2 == 1)
+    for colour in (0, 1):
+        tg = P["target"][:fp] if colour == 0 else P["target"][fp:]
+        assert len(set(tg.tolist())) == tg.size, f"row written twice in colour {colour}"
+    # chunks tile the slots: <= 2048 entries and <= 256 slots, or one long slot
+    cs = P["chunk_slot"]
+    assert cs[0] == 0 and cs[-1] == ns and np.all(np.diff(cs) > 0)
+    for c in range(cs.size - 1):
+        ne = sp[cs[c + 1]] - sp[cs[c]]
+        assert (ne <= 2048 and cs[c + 1] - cs[c] <= 256) or cs[c + 1] - cs[c] == 1
+    assert P["stats"]["scatter_blocks"] == cs.size - 1 and P["stats"]["slots"] == ns
+    return P
+
+
+def test_panel_plan_fem_csc():
     s = W.fem_p1_system(12, 10, 9, seed=3)
-    P = check_scatter_plan(cgmi.CG_FMT_CSC, s.rowptr, s.col)   # symmetric: CSC arrays == CSR arrays
-    assert P["stats"]["colors"] <= 8
+    P = check_panel_plan(s.rowptr, s.col)                     # symmetric: CSC arrays == CSR arrays
+    assert P["stats"]["colors"] == 1                          # n = 1080 < 4096 columns: one panel
 
 
-def test_scatter_plan_small_blocks_many_colours(monkeypatch):
-    monkeypatch.setenv("CGMI_SCATTER_ENTRIES", "64")
-    s = W.fem_p1_system(8, 7, 6, seed=4)
-    up, uc, _ = W.upper_triangle(s.rowptr, s.col, s.val)
-    P = check_scatter_plan(cgmi.CG_FMT_SYM_CSR, up, uc)
-    assert P["stats"]["scatter_blocks"] > 20 and P["stats"]["colors"] >= 2
-    check_scatter_plan(cgmi.CG_FMT_CSC, s.rowptr, s.col)
+def test_panel_plan_fem_two_colours():
+    s = W.fem_p1_system(30, 28, 26, seed=9)                   # n = 21 840, bw = 871
+    P = check_panel_plan(s.rowptr, s.col)
+    assert P["width"] == 4096 and P["stats"]["colors"] == 2 and P["first_parked"] < P["target"].size
 
 
-def test_scatter_plan_ragged_nonsymmetric_csc(monkeypatch):
-    monkeypatch.setenv("CGMI_SCATTER_ENTRIES", "96")
+def test_panel_plan_wide_band():
+    s = W.fem_p1_system(70, 70, 8, seed=10)                   # bw = 4971 > 4096/2: width = 2 bw + 1
+    P = check_panel_plan(s.rowptr, s.col)
+    assert P["width"] == 2 * (70 * 70 + 70 + 1) + 1
+
+
+def test_panel_plan_ragged_nonsymmetric_csc():
     ptr, col, val = W.random_sparse(300, density=0.03, seed=5, empty_rows=20, long_rows=2, long_len=250)
-    # read as CSC arrays: 2 columns of 250 entries (longer than a block), 20 empty columns
-    P = check_scatter_plan(cgmi.CG_FMT_CSC, ptr, col)
-    # the long columns are split over several blocks
-    assert np.any(P["line1"] - P["line0"] == 1)
+    # read as CSC arrays: 2 columns of 250 entries, 20 empty columns; rows without entries exist too
+    check_panel_plan(ptr, col)
+    one = check_panel_plan(ptr + 1, col + 1, base=1)
+    assert one["target"].size > 0
+
+
+def test_panel_plan_banded_multi_panel():
+    ptr, idx, _ = W.banded_sparse(10000, 1500, density=0.004, seed=11, empty=300)
+    P = check_panel_plan(ptr, idx)
+    assert P["width"] == 4096 and P["stats"]["colors"] == 2
+
+
+def test_panel_plan_long_slot_and_banded():
+    # a column panel holding one row with 3000 entries (a dense row): its slot is a chunk of its own
+    n = 5000
+    cols = [[j] for j in range(n)]
+    for j in range(n):
+        if j != 7:
+            cols[j] = sorted(set(cols[j] + [7]))
+    ptr = np.zeros(n + 1, np.int32)
+    ptr[1:] = np.cumsum([len(c) for c in cols])
+    idx = np.concatenate([np.array(c) for c in cols]).astype(np.int32)
+    P = check_panel_plan(ptr, idx)
+    lens = np.diff(P["slot_ptr"])
+    assert lens.max() == n and P["stats"]["max_block_entries"] == n
+
+
+def test_analyze_export_refuses_csc():
+    s = W.fem_p1_system(4, 4, 4, seed=1)
+    st, _ = cgmi.cg_analyze_export(cgmi.CG_FMT_CSC, s.n, s.rowptr, s.col)
+    assert st == cgmi.CG_ERR_ARG and "panel" in cgmi.cg_last_error(None)
 
 
 def _arrow_upper(n):
