@@ -351,8 +351,9 @@ void enqueue_iteration(cg_handle *h, hipStream_t s)
     c.st = h->st;
     c.rho_part = h->rho;
     c.n_rho = h->dm.vec_blocks;
+    c.defer_rows = true;
     launch_spmv(h->dm, h->p, h->q, h->sig, c, s);
-    launch_update_r(h->dm, h->r, h->q, h->st, h->sig, h->rho, s);
+    launch_update_r(h->dm, h->r, h->q, h->st, h->sig, h->rho, s, true);
     launch_update_xp(h->dm, h->xw, h->p, h->r, h->st, h->rho, s);
 }
 
@@ -362,8 +363,9 @@ void enqueue_iteration32(cg_handle *h, hipStream_t s)
 {
     IterCtx c;
     c.st = h->st_in;
+    c.defer_rows = true;
     launch_spmv32(h->dm, h->p32, h->q, h->sig, c, s);
-    launch_update_r(h->dm, h->r, h->q, h->st_in, h->sig, h->rho, s);
+    launch_update_r(h->dm, h->r, h->q, h->st_in, h->sig, h->rho, s, true);
     launch_update_xp32(h->dm, h->p, h->p32, h->r, h->st_in, h->rho, s);
 }
 

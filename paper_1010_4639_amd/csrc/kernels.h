@@ -80,6 +80,8 @@ struct DevMatrix {
     // vectors
     int vec_blocks = 0, vec_chunk = 0;
     int spmv_blocks() const { return format == kCsr ? csr_blocks : scatter_wgs; }
+    // the product ends with a row pass (parked slot sums, rows with no writer)
+    bool row_pass() const { return panel ? pn_gather : (format == kSymCsr && ncolors > 1); }
 };
 
 // Iteration context: null st = plain product (no gating, p'q partials still
@@ -88,6 +90,9 @@ struct IterCtx {
     DevState *st = nullptr;
     const double *rho_part = nullptr;
     int n_rho = 0;
+    // leave the row pass of a scatter product to the r update (y then holds
+    // only the colour-0 rows; the iteration's q is never read elsewhere)
+    bool defer_rows = false;
 };
 
 // y = A x; writes spmv_blocks() partials of x'y into sig_part.
@@ -97,8 +102,10 @@ void launch_spmv(const DevMatrix &m, const double *x, double *y, double *sig_par
 void launch_spmv32(const DevMatrix &m, const float *x, double *y, double *sig_part, const IterCtx &c,
                    hipStream_t s);
 // r -= alpha q with alpha = rho / sum(sig_part); rho_part <- partials of r'r.
+// rows_deferred: q came from a product launched with defer_rows, so each
+// q_i is finished here from the parked slot sums first.
 void launch_update_r(const DevMatrix &m, double *r, const double *q, DevState *st, const double *sig_part,
-                     double *rho_part, hipStream_t s);
+                     double *rho_part, hipStream_t s, bool rows_deferred = false);
 // x += alpha p; p = r + beta p (unless converged) with beta = sum(rho_part) / rho.
 void launch_update_xp(const DevMatrix &m, double *x, double *p, const double *r, DevState *st,
                       const double *rho_part, hipStream_t s);

@@ -477,10 +477,32 @@ __global__ __launch_bounds__(kBlock) void k_scatter_gather(int n, const int32_t 
 // kernel are reduced, so the two memory round trips overlap.
 constexpr int kPre = 4;
 
+// Rows finished by the row pass of a scatter product: GATHER folds that pass
+// (k_scatter_gather's sum, same terms, same order) into the r update, so the
+// product's last writes of y and their re-read are saved.
+struct RowPass {
+    const int32_t *rs_ptr = nullptr, *rs_idx = nullptr;
+    const uint8_t *has_c0 = nullptr;
+    const double *part = nullptr;
+};
+
+template <bool GATHER>
+__device__ __forceinline__ double q_value(const double *__restrict__ q, const RowPass &g, int i)
+{
+    if (!GATHER)
+        return q[i];
+    const int k0 = g.rs_ptr[i], k1 = g.rs_ptr[i + 1];
+    double a = g.has_c0[i] ? q[i] : 0.0;
+    for (int k = k0; k < k1; ++k)
+        a += g.part[g.rs_idx[k]];
+    return a;
+}
+
+template <bool GATHER>
 __global__ __launch_bounds__(kBlock) void k_update_r(int n, int chunk, double *__restrict__ r,
                                                      const double *__restrict__ q, DevState *st,
                                                      const double *__restrict__ sig_part, int n_sig,
-                                                     double *__restrict__ rho_part)
+                                                     double *__restrict__ rho_part, RowPass g)
 {
     __shared__ double red[kWaves];
     if (st->status != kRun)
@@ -492,7 +514,7 @@ __global__ __launch_bounds__(kBlock) void k_update_r(int n, int chunk, double *_
 #pragma unroll
     for (int u = 0; u < kPre; ++u) {
         const int i = i0 + t + u * kBlock;
-        qv[u] = i < i1 ? q[i] : 0.0;
+        qv[u] = i < i1 ? q_value<GATHER>(q, g, i) : 0.0;
         rv[u] = i < i1 ? r[i] : 0.0;
     }
     const double sigma = reduce_partials(sig_part, n_sig, red);
@@ -522,7 +544,7 @@ __global__ __launch_bounds__(kBlock) void k_update_r(int n, int chunk, double *_
         }
     }
     for (int i = i0 + t + kPre * kBlock; i < i1; i += kBlock) {
-        const double ri = fma(-alpha, q[i], r[i]);
+        const double ri = fma(-alpha, q_value<GATHER>(q, g, i), r[i]);
         r[i] = ri;
         acc = fma(ri, ri, acc);
     }
@@ -809,7 +831,7 @@ void scatter_launch(const DevMatrix &m, const VT *val, const PT *x, double *y, d
     hipLaunchKernelGGL((k_scatter_sums<SYM, SU, VT, PT>), dim3(m.scatter_wgs), dim3(kBlock), lds, s, m.ptr, m.idx,
                        val, x, y, m.part, sig, m.blocks, m.nblocks, m.slot_target, m.seg, m.tl, m.lds_entries,
                        m.lds_lines, c.st);
-    if (m.ncolors > 1)
+    if (m.ncolors > 1 && !c.defer_rows)
         hipLaunchKernelGGL(k_scatter_gather, dim3((m.n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, m.n, m.rs_ptr,
                            m.rs_idx, m.has_c0, m.part, y, c.st);
 }
@@ -843,7 +865,7 @@ void spmv_any(const DevMatrix &m, const VT *val, const PT *x, double *y, double 
             hipLaunchKernelGGL((k_panel_rows<VT, PT>), dim3(m.scatter_wgs), dim3(kBlock), 0, s, m.nblocks,
                                m.pn_chunk_slot, m.pn_slot_ptr, m.pn_slot_target, m.pn_col, panel_vals(m, val), x, y,
                                m.part, m.pn_first_parked, sig_part, c.st);
-        if (m.pn_gather)
+        if (m.pn_gather && !c.defer_rows)
             hipLaunchKernelGGL(k_scatter_gather, dim3((m.n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, m.n,
                                m.rs_ptr, m.rs_idx, m.has_c0, m.part, y, c.st);
         return;
@@ -879,10 +901,20 @@ void launch_spmv32(const DevMatrix &m, const float *x, double *y, double *sig_pa
 }
 
 void launch_update_r(const DevMatrix &m, double *r, const double *q, DevState *st, const double *sig_part,
-                     double *rho_part, hipStream_t s)
+                     double *rho_part, hipStream_t s, bool rows_deferred)
 {
-    hipLaunchKernelGGL(k_update_r, dim3(m.vec_blocks), dim3(kBlock), 0, s, m.n, m.vec_chunk, r, q, st, sig_part,
-                       m.spmv_blocks(), rho_part);
+    if (rows_deferred && m.row_pass()) {
+        RowPass g;
+        g.rs_ptr = m.rs_ptr;
+        g.rs_idx = m.rs_idx;
+        g.has_c0 = m.has_c0;
+        g.part = m.part;
+        hipLaunchKernelGGL(k_update_r<true>, dim3(m.vec_blocks), dim3(kBlock), 0, s, m.n, m.vec_chunk, r, q, st,
+                           sig_part, m.spmv_blocks(), rho_part, g);
+    } else {
+        hipLaunchKernelGGL(k_update_r<false>, dim3(m.vec_blocks), dim3(kBlock), 0, s, m.n, m.vec_chunk, r, q, st,
+                           sig_part, m.spmv_blocks(), rho_part, RowPass{});
+    }
 }
 
 void launch_update_xp(const DevMatrix &m, double *x, double *p, const double *r, DevState *st,
