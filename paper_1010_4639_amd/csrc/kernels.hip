@@ -307,41 +307,41 @@ __global__ __launch_bounds__(kBlock) void k_permute(int64_t nnz, const T *__rest
 }
 
 // ------------------------------------------------- coloured scatter
-// Product for the formats whose entries write rows other than their own
-// (symmetric CSR: the mirrored triangle; CSC: every column).  Two kernels:
+// Product of the symmetric format, whose stored entries also write the rows
+// named by their index (the mirrored triangle).  Two kernels:
 //
 // k_scatter_sums -- all blocks of all colours at once (blocks stored in
 //   colour order, each workgroup walks a contiguous range).  Per block every
 //   independent global load is issued first (line pointers, x of the own
-//   lines, the contribution list -> LDS, <= 2048 index / value pairs, 8 per
+//   lines, the contribution list -> LDS, the index / value pairs, E per
 //   thread, and the write-slot descriptors, SU per thread); then the gathers;
-//   then, through one LDS product buffer: (symmetric CSR) the products of
-//   the stored rows themselves, a_e x_idx(e), each own row summed left to
-//   right by the thread that owns that row's slot; then the products bound
-//   for other rows, a_e x_line(e) (mirror / column), and every slot's sum in
-//   the plan's fixed order.  Colour-0 blocks are the
-//   first writers of all their rows and store y directly; the others park
-//   their slot sums in `part`.  The dot x'y is linear in the slot sums, so
-//   each workgroup accumulates sum_slots x_target * sum here, before any y
-//   is final.
+//   then, through one LDS product buffer: the products of the stored rows
+//   themselves, a_e x_idx(e), each own row summed left to right by the thread
+//   that owns that row's slot; then the mirror products a_e x_line(e), and
+//   every slot's sum in the plan's fixed order.  Every value is read once and
+//   used twice.  Colour-0 blocks are the first writers of all their rows and
+//   store y directly; the others park their slot sums in `part`.  The dot x'y
+//   is linear in the slot sums, so each workgroup accumulates
+//   sum_slots x_target * sum here, before any y is final.
 // k_scatter_gather -- one launch: every row adds its parked slot sums, in
 //   ascending colour order, to what its colour-0 writer stored (if any).
 //   Blocks of one colour write disjoint rows, so colour 0 can store without
 //   conflicts; the colour order fixes the accumulation order of the rest.
-template <bool SYM, int SU, class VT, class PT>
+//   (Inside CG iterations this pass is folded into the r update.)
+template <int SU, int E, class VT, class PT>
 __global__ __launch_bounds__(kBlock) void k_scatter_sums(
     const int32_t *__restrict__ ptr, const int32_t *__restrict__ idx, const VT *__restrict__ val,
     const PT *__restrict__ x, double *__restrict__ y, double *__restrict__ part, double *__restrict__ sig_part,
     const ScatterBlock *__restrict__ blocks, int nblocks, const int32_t *__restrict__ slot_target,
     const uint16_t *__restrict__ seg, const uint16_t *__restrict__ tl, int lds_entries, int lds_lines, DevState *st)
 {
-    constexpr int E = kMaxScatterEntries / kBlock; // entries per thread
+    // E entries per thread: E * kBlock >= the largest block
     extern __shared__ double lds[];
     __shared__ double red[kWaves];
     const int wg = xcd_remap(blockIdx.x, gridDim.x);
     if (st != nullptr && !iter_gate(st))
         return;
-    double *sp = lds; // own-row products first (symmetric CSR), then the products bound elsewhere
+    double *sp = lds; // own-row products first, then the mirror products
     double *xl = sp + lds_entries;
     int32_t *lp = reinterpret_cast<int32_t *>(xl + lds_lines);
     uint16_t *lm = reinterpret_cast<uint16_t *>(lp + lds_lines + 1);
@@ -381,11 +381,9 @@ __global__ __launch_bounds__(kBlock) void k_scatter_sums(
         }
         // ---- gathers
         double xg[E];
-        if (SYM) {
 #pragma unroll
-            for (int m = 0; m < E; ++m)
-                xg[m] = c[m] >= 0 ? (double)x[c[m]] : 0.0;
-        }
+        for (int m = 0; m < E; ++m)
+            xg[m] = c[m] >= 0 ? (double)x[c[m]] : 0.0;
         double xt[SU];
 #pragma unroll
         for (int u = 0; u < SU; ++u)
@@ -395,28 +393,25 @@ __global__ __launch_bounds__(kBlock) void k_scatter_sums(
         for (int l = t; l < nl; l += kBlock)
             for (int k = lp[l]; k < lp[l + 1]; ++k)
                 lm[k] = (uint16_t)l;
-        __syncthreads();
-        // ---- symmetric CSR: own rows, stored entries left to right; the sum
-        //      of row l stays in thread l, which owns that row's slot (l < 256)
-        double own = 0.0;
-        if (SYM) {
+        // ---- own rows, stored entries left to right; the sum of row l stays
+        //      in thread l, which owns that row's slot (l < 256)
 #pragma unroll
-            for (int m = 0; m < E; ++m)
-                if (c[m] >= 0)
-                    sp[t + m * kBlock] = v[m] * xg[m];
-            __syncthreads();
-            if (t < nl)
-                for (int k = lp[t]; k < lp[t + 1]; ++k)
-                    own += sp[k];
-            __syncthreads();
-        }
-        // ---- products bound for other rows (mirror / column)
+        for (int m = 0; m < E; ++m)
+            if (c[m] >= 0)
+                sp[t + m * kBlock] = v[m] * xg[m];
+        __syncthreads();
+        double own = 0.0;
+        if (t < nl)
+            for (int k = lp[t]; k < lp[t + 1]; ++k)
+                own += sp[k];
+        __syncthreads();
+        // ---- mirror products (the diagonal has none)
 #pragma unroll
         for (int m = 0; m < E; ++m) {
             const int e = t + m * kBlock;
             if (c[m] >= 0) {
                 const int l = lm[e];
-                if (!SYM || c[m] != bk.line0 + l)
+                if (c[m] != bk.line0 + l)
                     sp[e] = v[m] * xl[l];
             }
         }
@@ -428,7 +423,7 @@ __global__ __launch_bounds__(kBlock) void k_scatter_sums(
             if (tg[u] < 0)
                 continue;
             const int s = t + u * kBlock;
-            double a = (SYM && s < nl) ? own : 0.0; // s < nl <= 256 implies u == 0 and s == t
+            double a = s < nl ? own : 0.0; // s < nl <= 256 implies u == 0 and s == t
             for (int i = lo[u]; i < hi[u]; ++i)
                 a += sp[tv[i]];
             if (first_colour)
@@ -822,33 +817,44 @@ void csr_launch(const DevMatrix &m, const VT *val, const PT *x, double *y, doubl
                        m.csr_rows_per_block, m.ptr, m.idx, val, x, y, sig, c.st);
 }
 
-template <bool SYM, int SU, class VT, class PT>
+template <int SU, int E, class VT, class PT>
 void scatter_launch(const DevMatrix &m, const VT *val, const PT *x, double *y, double *sig, const IterCtx &c,
                     hipStream_t s)
 {
-    const size_t E = (size_t)m.lds_entries, R = (size_t)m.lds_lines;
-    const size_t lds = E * 8 + R * 8 + (R + 1) * 4 + 2 * E * 2;
-    hipLaunchKernelGGL((k_scatter_sums<SYM, SU, VT, PT>), dim3(m.scatter_wgs), dim3(kBlock), lds, s, m.ptr, m.idx,
-                       val, x, y, m.part, sig, m.blocks, m.nblocks, m.slot_target, m.seg, m.tl, m.lds_entries,
-                       m.lds_lines, c.st);
+    const size_t Ent = (size_t)m.lds_entries, R = (size_t)m.lds_lines;
+    const size_t lds = Ent * 8 + R * 8 + (R + 1) * 4 + 2 * Ent * 2;
+    hipLaunchKernelGGL((k_scatter_sums<SU, E, VT, PT>), dim3(m.scatter_wgs), dim3(kBlock), lds, s, m.ptr,
+                       m.idx, val, x, y, m.part, sig, m.blocks, m.nblocks, m.slot_target, m.seg, m.tl,
+                       m.lds_entries, m.lds_lines, c.st);
     if (m.ncolors > 1 && !c.defer_rows)
         hipLaunchKernelGGL(k_scatter_gather, dim3((m.n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, m.n, m.rs_ptr,
                            m.rs_idx, m.has_c0, m.part, y, c.st);
 }
 
-template <bool SYM, class VT, class PT>
-void scatter_dispatch(const DevMatrix &m, const VT *val, const PT *x, double *y, double *sig, const IterCtx &c,
-                      hipStream_t s)
+template <int E, class VT, class PT>
+void scatter_dispatch_su(const DevMatrix &m, const VT *val, const PT *x, double *y, double *sig, const IterCtx &c,
+                         hipStream_t s)
 {
     // write slots held in registers: SU per thread must cover the largest block
     if (m.max_slots <= 2 * kBlock)
-        scatter_launch<SYM, 2>(m, val, x, y, sig, c, s);
+        scatter_launch<2, E>(m, val, x, y, sig, c, s);
     else if (m.max_slots <= 4 * kBlock)
-        scatter_launch<SYM, 4>(m, val, x, y, sig, c, s);
+        scatter_launch<4, E>(m, val, x, y, sig, c, s);
     else if (m.max_slots <= 6 * kBlock)
-        scatter_launch<SYM, 6>(m, val, x, y, sig, c, s);
+        scatter_launch<6, E>(m, val, x, y, sig, c, s);
     else
-        scatter_launch<SYM, 9>(m, val, x, y, sig, c, s);
+        scatter_launch<9, E>(m, val, x, y, sig, c, s);
+}
+
+template <class VT, class PT>
+void scatter_dispatch(const DevMatrix &m, const VT *val, const PT *x, double *y, double *sig, const IterCtx &c,
+                      hipStream_t s)
+{
+    // entries held in registers: E per thread must cover the largest block
+    if (m.lds_entries <= 4 * kBlock)
+        scatter_dispatch_su<4>(m, val, x, y, sig, c, s);
+    else
+        scatter_dispatch_su<kMaxScatterEntries / kBlock>(m, val, x, y, sig, c, s);
 }
 
 inline const double *panel_vals(const DevMatrix &m, const double *) { return m.pn_val; }
@@ -881,10 +887,8 @@ void spmv_any(const DevMatrix &m, const VT *val, const PT *x, double *y, double 
         case 32: csr_launch<32>(m, val, x, y, sig_part, c, s); break;
         default: csr_launch<64>(m, val, x, y, sig_part, c, s); break;
         }
-    } else if (m.format == kSymCsr) {
-        scatter_dispatch<true>(m, val, x, y, sig_part, c, s);
     } else {
-        scatter_dispatch<false>(m, val, x, y, sig_part, c, s);
+        scatter_dispatch(m, val, x, y, sig_part, c, s); // symmetric CSR (CSC runs on panels)
     }
 }
 
