@@ -168,8 +168,8 @@ def main():
     # dominant product kernel: largest share of the step's time
     dom = max(solvers, key=lambda k: spmv[k]["us"] * per_format[k]["iters"])
     kernel_name = {"csr": "k_spmv_csr_rows (CSR product)",
-                   "symcsr": "k_scatter_sums<true> + k_scatter_gather (symmetric-CSR product)",
-                   "csc": "k_scatter_sums<false> + k_scatter_gather (CSC product)"}[dom]
+                   "symcsr": "k_scatter_sums + k_scatter_gather (symmetric-CSR product)",
+                   "csc": "k_panel_rows + k_scatter_gather (CSC product on column panels)"}[dom]
     traffic = load_traffic(dom)
     roofline = dict(bound="hbm", achieved=round(spmv[dom]["GBps"], 1), peak=HBM_PEAK_GBPS, unit="GB/s",
                     frac=round(spmv[dom]["GBps"] / HBM_PEAK_GBPS, 4), traffic=traffic, kernel=kernel_name,
