@@ -161,10 +161,21 @@ int validate_and_normalise(int fmt, int64_t n, const int32_t *ptr, const int32_t
     return CG_OK;
 }
 
+// Entries per block for the row-block kernels: the full 2048 (8 per thread)
+// once the matrix gives >= 1024 such blocks, smaller for small matrices so
+// that the launch still spreads over every compute unit (they are bound by
+// latency, not bytes), never below `floor`.
+static int64_t block_entries(int64_t nnz, int64_t floor)
+{
+    return std::max<int64_t>(floor, std::min<int64_t>(kStreamEntries, (nnz + 1023) / 1024));
+}
+
 static void plan_vectors(Plan &p)
 {
+    // >= 1024 elements per workgroup on large vectors; small vectors use
+    // down to 256 per workgroup so that more compute units take part
     const int64_t n = p.n;
-    int64_t g = (n + 1023) / 1024;
+    int64_t g = std::max<int64_t>((n + 1023) / 1024, std::min<int64_t>((n + 255) / 256, 512));
     g = std::max<int64_t>(1, std::min<int64_t>(g, kMaxVecBlocks));
     p.vec_blocks = (int)g;
     p.vec_chunk = (int)((n + g - 1) / g);
@@ -175,16 +186,16 @@ static void plan_csr(Plan &p, const int32_t *ptr)
     const int64_t n = p.n;
     const double mean = (double)p.nnz / (double)n;
     if (mean <= kStreamMaxMeanRow) {
-        // row blocks: <= kStreamEntries entries and <= kStreamRows rows; a row
-        // longer than kStreamEntries is a block of its own
+        // row blocks: <= `be` entries (<= kStreamEntries) and <= kStreamRows
+        // rows; a row longer than kStreamEntries is a block of its own
+        const int64_t be = block_entries(p.nnz, kBlock);
         p.csr_stream = true;
         p.csr_rb.clear();
         p.csr_rb.push_back(0);
         int64_t r0 = 0;
         for (int64_t r = 0; r < n; ++r) {
             const int64_t len = (int64_t)ptr[r + 1] - ptr[r];
-            if (r > r0 && ((int64_t)ptr[r + 1] - ptr[r0] > kStreamEntries || r - r0 >= kStreamRows ||
-                           len > kStreamEntries)) {
+            if (r > r0 && ((int64_t)ptr[r + 1] - ptr[r0] > be || r - r0 >= kStreamRows || len > kStreamEntries)) {
                 p.csr_rb.push_back((int32_t)r);
                 r0 = r;
             }
@@ -261,15 +272,17 @@ static int plan_panels(Plan &p, const int32_t *ptr, const int32_t *idx, std::str
         err = "internal: panel placement lost entries";
         return CG_ERR_HIP;
     }
-    // chunks: consecutive slots, <= kPanelChunkEntries entries and
-    // <= kPanelChunkSlots slots; a longer slot is a chunk of its own
+    // chunks: consecutive slots, <= ce entries (<= kPanelChunkEntries) and
+    // <= kPanelChunkSlots slots; a slot longer than kPanelChunkEntries is a
+    // chunk of its own
     const int64_t ns = (int64_t)p.pn_slot_target.size();
+    const int64_t ce = block_entries(nnz, kBlock);
     p.pn_chunk_slot.assign(1, 0);
     int64_t s0 = 0;
     for (int64_t s = 0; s < ns; ++s) {
         const int64_t len = (int64_t)p.pn_slot_ptr[s + 1] - p.pn_slot_ptr[s];
-        if (s > s0 && ((int64_t)p.pn_slot_ptr[s + 1] - p.pn_slot_ptr[s0] > kPanelChunkEntries ||
-                       s - s0 >= kPanelChunkSlots || len > kPanelChunkEntries)) {
+        if (s > s0 && ((int64_t)p.pn_slot_ptr[s + 1] - p.pn_slot_ptr[s0] > ce || s - s0 >= kPanelChunkSlots ||
+                       len > kPanelChunkEntries)) {
             p.pn_chunk_slot.push_back((int32_t)s);
             s0 = s;
         }
@@ -509,7 +522,7 @@ int build_plan(int fmt, int64_t n, const int32_t *ptr0, const int32_t *idx0, int
     if (fmt == kCsc)
         return plan_panels(p, ptr0, idx0, err);
     if (target_entries <= 0)
-        target_entries = kDefaultScatterEntries;
+        target_entries = (int)block_entries(p.nnz, 512);
     target_entries = std::min(target_entries, kMaxScatterEntries);
     return plan_scatter(p, ptr0, idx0, target_entries, err);
 }
