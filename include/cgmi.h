@@ -185,10 +185,13 @@ int cg_batch_create(cg_batch **out, int32_t nsys, const int64_t *sys_off, const 
 int cg_batch_set_stream(cg_batch *h, void *hip_stream);
 /* Y = A X for all systems and right-hand sides (device, N*nrhs float64 each). */
 int cg_batch_spmm(cg_batch *h, const double *X, double *Y);
-/* Project-written autotuner: times the product for every row-block size
- * (256, 512, 1024 entries) x workgroup budget (1024, 2048, 4096), keeps the
- * fastest plan and reports it (outputs may be NULL).  Uses the GPU. */
-int cg_batch_autotune(cg_batch *h, int32_t *entries_per_block, int32_t *workgroups, float *best_us);
+/* Project-written autotuner: times the product for every schedule -- row
+ * blocks of 256, 512 or 1024 entries summed through LDS, or 8 or 16 lanes
+ * per row combined by butterflies -- x workgroup budget (1024, 2048, 4096),
+ * keeps the fastest plan and reports it (outputs may be NULL;
+ * lanes_per_row = 0 means the LDS row-block schedule).  Uses the GPU. */
+int cg_batch_autotune(cg_batch *h, int32_t *entries_per_block, int32_t *lanes_per_row, int32_t *workgroups,
+                      float *best_us);
 /* Solves all pairs from X (in: x0, out: solutions) to ||r|| <= tol ||b|| each.
  *   B, X      device, N*nrhs float64, interleaved
  *   iters, status  host, nsys*nrhs int32 each (pair s*nrhs + r), may be NULL:

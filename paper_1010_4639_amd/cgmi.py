@@ -97,7 +97,7 @@ def load():
     lib.cg_batch_create.argtypes = [ctypes.POINTER(_VP), i32, _VP, _VP, _VP, _VP, i32, ctypes.c_int]
     lib.cg_batch_set_stream.argtypes = [_VP, _VP]
     lib.cg_batch_spmm.argtypes = [_VP, _VP, _VP]
-    lib.cg_batch_autotune.argtypes = [_VP, _VP, _VP, _VP]
+    lib.cg_batch_autotune.argtypes = [_VP, _VP, _VP, _VP, _VP]
     lib.cg_batch_solve.argtypes = [_VP, _VP, _VP, dbl, i32, _VP, _VP, ctypes.POINTER(cg_info)]
     lib.cg_batch_destroy.argtypes = [_VP]
     lib.cg_batch_destroy.restype = None
@@ -519,12 +519,12 @@ class Batch:
         return _VP(t.data_ptr())
 
     def autotune(self):
-        e, w, us = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_float()
+        e, ln, w, us = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_float()
         self._stream()
-        st = load().cg_batch_autotune(self.h, ctypes.byref(e), ctypes.byref(w), ctypes.byref(us))
+        st = load().cg_batch_autotune(self.h, ctypes.byref(e), ctypes.byref(ln), ctypes.byref(w), ctypes.byref(us))
         if st != CG_OK:
             raise CgError(st, cg_batch_last_error(self.h))
-        return dict(entries_per_block=e.value, workgroups=w.value, us=us.value)
+        return dict(entries_per_block=e.value, lanes_per_row=ln.value, workgroups=w.value, us=us.value)
 
     def spmm(self, X, Y=None):
         import torch

@@ -23,6 +23,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <memory>
 #include <new>
@@ -81,6 +82,109 @@ __device__ __forceinline__ bool inst_gate(Inst *I, bool lead)
 
 // Q = A P for the R interleaved right-hand sides (row blocks of <= 256*EPT
 // entries staged in LDS, one thread sums each row left to right).
+// Q = A P for the R interleaved right-hand sides, W lanes per row (the
+// second schedule the autotuner can pick): each lane accumulates R partial
+// sums over the entries lane, lane + W, ... of its row, with U rows in flight
+// per lane group, and the W lanes combine them by a butterfly (fixed order);
+// the R values of a gathered row of P come in 16-byte loads.  No LDS, so
+// occupancy is set by registers alone.
+template <int R, int W, int U>
+__global__ __launch_bounds__(kBlock) void k_bspmm_lanes(const WgDesc *__restrict__ wgs,
+                                                        const int32_t *__restrict__ ptr,
+                                                        const int32_t *__restrict__ col,
+                                                        const double *__restrict__ val,
+                                                        const double *__restrict__ P, double *__restrict__ Q,
+                                                        double *__restrict__ sig_part, Inst *inst)
+{
+    static_assert(R <= W, "one storing lane per right-hand side");
+    __shared__ double red[kWaves];
+    __shared__ int act_s[R];
+    constexpr int NG = kBlock / W;
+    const WgDesc Wd = wgs[blockIdx.x];
+    const int t = threadIdx.x;
+    bool any = true;
+    if (inst != nullptr) {
+        if (t < R)
+            act_s[t] = inst_gate(&inst[Wd.sys * R + t], Wd.lead != 0) ? 1 : 0;
+        __syncthreads();
+        any = false;
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+            any |= act_s[r] != 0;
+    }
+    const int g = t / W, lane = t % W;
+    double sg = 0.0; // lane r < R: partial of p'q for right-hand side r
+    if (any) {
+        for (int base = Wd.i0 + g; base < Wd.i1; base += NG * U) {
+            int rs[U], re[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int r = base + u * NG;
+                const bool ok = r < Wd.i1;
+                rs[u] = ok ? __builtin_nontemporal_load(ptr + r) : 0;
+                re[u] = ok ? __builtin_nontemporal_load(ptr + r + 1) : 0;
+            }
+            double acc[U][R];
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+#pragma unroll
+                for (int r = 0; r < R; ++r)
+                    acc[u][r] = 0.0;
+            for (int off = lane;; off += W) {
+                bool anyk = false;
+                int c[U];
+                double v[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int k = rs[u] + off;
+                    const bool ok = k < re[u];
+                    anyk |= ok;
+                    c[u] = ok ? __builtin_nontemporal_load(col + k) : -1;
+                    v[u] = ok ? __builtin_nontemporal_load(val + k) : 0.0;
+                }
+                if (!anyk)
+                    break;
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    if (c[u] < 0)
+                        continue;
+                    if constexpr (R % 2 == 0) {
+                        const double2 *p2 = reinterpret_cast<const double2 *>(P + (size_t)c[u] * R);
+#pragma unroll
+                        for (int h2 = 0; h2 < R / 2; ++h2) {
+                            const double2 pv = p2[h2];
+                            acc[u][2 * h2] = fma(v[u], pv.x, acc[u][2 * h2]);
+                            acc[u][2 * h2 + 1] = fma(v[u], pv.y, acc[u][2 * h2 + 1]);
+                        }
+                    } else {
+#pragma unroll
+                        for (int r = 0; r < R; ++r)
+                            acc[u][r] = fma(v[u], P[(size_t)c[u] * R + r], acc[u][r]);
+                    }
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int row = base + u * NG;
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const double q = group_sum<W>(acc[u][r]);
+                    if (lane == r && row < Wd.i1) {
+                        Q[(size_t)row * R + r] = q;
+                        sg = fma(P[(size_t)row * R + r], q, sg);
+                    }
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const double sr = block_sum(lane == r ? sg : 0.0, red);
+        if (t == 0)
+            sig_part[blockIdx.x * R + r] = sr;
+    }
+}
+
 template <int R, int EPT>
 __global__ __launch_bounds__(kBlock) void k_bspmm(const WgDesc *__restrict__ wgs, const int32_t *__restrict__ rb_row,
                                                   const int32_t *__restrict__ ptr, const int32_t *__restrict__ col,
@@ -423,8 +527,9 @@ struct cg_batch {
     int64_t N = 0, nnz = 0;
     std::vector<int64_t> sys_off;
     std::vector<int32_t> hptr, hidx; // host copy of the structure (re-planning by the autotuner)
-    // plan
-    int ept = 4, G = 0, nrb = 0, wg_target = 2048;
+    // plan: row blocks of 256 * ept entries; lanes = 0 runs the products on
+    // them through LDS, lanes = 8 / 16 uses that many lanes per row instead
+    int ept = 4, G = 0, nrb = 0, wg_target = 2048, lanes = 0;
     // device
     std::vector<void *> allocs, plan_allocs;
     int32_t *ptr = nullptr, *idx = nullptr, *rb_row = nullptr, *sys_wg0 = nullptr;
@@ -586,8 +691,29 @@ void spmm_e(cg_batch *h, const double *P, double *Q, Inst *inst, hipStream_t s)
         spmm_r<R, 4>(h, P, Q, inst, s);
 }
 
+template <int R>
+void spmm_lanes(cg_batch *h, const double *P, double *Q, Inst *inst, hipStream_t s)
+{
+    constexpr int U = R == 4 ? 1 : 2; // rows in flight per lane group (registers: 8 waves per SIMD)
+    if (h->lanes == 8)
+        hipLaunchKernelGGL((k_bspmm_lanes<R, 8, U>), dim3(h->G), dim3(kBlock), 0, s, h->wgs, h->ptr, h->idx, h->val,
+                           P, Q, h->sig, inst);
+    else
+        hipLaunchKernelGGL((k_bspmm_lanes<R, 16, U>), dim3(h->G), dim3(kBlock), 0, s, h->wgs, h->ptr, h->idx,
+                           h->val, P, Q, h->sig, inst);
+}
+
 void spmm(cg_batch *h, const double *P, double *Q, Inst *inst, hipStream_t s)
 {
+    if (h->lanes) {
+        if (h->R == 1)
+            spmm_lanes<1>(h, P, Q, inst, s);
+        else if (h->R == 2)
+            spmm_lanes<2>(h, P, Q, inst, s);
+        else
+            spmm_lanes<4>(h, P, Q, inst, s);
+        return;
+    }
     if (h->R == 1)
         spmm_e<1>(h, P, Q, inst, s);
     else if (h->R == 2)
@@ -758,6 +884,11 @@ int cg_batch_create(cg_batch **out, int32_t nsys, const int64_t *sys_off, const 
             release(h.get());
             return st;
         }
+        // schedule override (tests, experiments): CGMI_BATCH_LANES=8 or 16
+        if (const char *ev = std::getenv("CGMI_BATCH_LANES")) {
+            const int l = std::atoi(ev);
+            h->lanes = (l == 8 || l == 16) ? l : 0;
+        }
     } catch (const std::bad_alloc &) {
         g_berr = "host allocation failed";
         if (h)
@@ -786,13 +917,18 @@ int cg_batch_spmm(cg_batch *h, const double *X, double *Y)
     return e == hipSuccess ? CG_OK : bfail(h, e, "launch");
 }
 
-int cg_batch_autotune(cg_batch *h, int32_t *entries_per_block, int32_t *workgroups, float *best_us)
+int cg_batch_autotune(cg_batch *h, int32_t *entries_per_block, int32_t *lanes_per_row, int32_t *workgroups,
+                      float *best_us)
 {
     if (!h)
         return CG_ERR_ARG;
-    // candidates: row-block size (entries) x workgroup budget; each timed on
-    // 10 products of a fixed vector after one warm-up
-    const int epts_all[3] = {1, 2, 4};
+    // candidates: schedule (row blocks of 256 / 512 / 1024 entries through
+    // LDS, or 8 / 16 lanes per row) x workgroup budget; each timed on 10
+    // products of a fixed vector after one warm-up
+    struct Cand {
+        int ept, lanes;
+    };
+    const Cand cands[5] = {{1, 0}, {2, 0}, {4, 0}, {4, 8}, {4, 16}};
     const int wgt_all[3] = {1024, 2048, 4096};
     const size_t nv = (size_t)h->N * h->R;
     double *X = nullptr, *Y = nullptr;
@@ -809,11 +945,12 @@ int cg_batch_autotune(cg_batch *h, int32_t *entries_per_block, int32_t *workgrou
     (void)hipEventCreate(&a);
     (void)hipEventCreate(&b);
     float best = 1e30f;
-    int best_e = h->ept, best_w = h->wg_target, st = CG_OK;
-    for (int ept : epts_all) {
+    int best_e = h->ept, best_l = h->lanes, best_w = h->wg_target, st = CG_OK;
+    for (const Cand &cd : cands) {
         for (int wgt : wgt_all) {
-            if ((st = build_plan(h, ept, wgt)) != CG_OK)
+            if ((st = build_plan(h, cd.ept, wgt)) != CG_OK)
                 break;
+            h->lanes = cd.lanes;
             spmm(h, X, Y, nullptr, h->stream);
             (void)hipEventRecord(a, h->stream);
             for (int i = 0; i < 10; ++i)
@@ -824,7 +961,8 @@ int cg_batch_autotune(cg_batch *h, int32_t *entries_per_block, int32_t *workgrou
             (void)hipEventElapsedTime(&ms, a, b);
             if (ms < best) {
                 best = ms;
-                best_e = ept;
+                best_e = cd.ept;
+                best_l = cd.lanes;
                 best_w = wgt;
             }
         }
@@ -837,8 +975,11 @@ int cg_batch_autotune(cg_batch *h, int32_t *entries_per_block, int32_t *workgrou
     (void)hipFree(Y);
     if (st == CG_OK)
         st = build_plan(h, best_e, best_w);
+    h->lanes = best_l;
     if (entries_per_block)
         *entries_per_block = kBlock * h->ept;
+    if (lanes_per_row)
+        *lanes_per_row = h->lanes;
     if (workgroups)
         *workgroups = h->G;
     if (best_us)

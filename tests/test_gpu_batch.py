@@ -4,6 +4,8 @@ sequence) vs the oracle run on every (system, right-hand side) pair alone.
 Per pair: same status; true residual (oracle product) <= 2 tol; energy-norm
 difference to the oracle's solution <= 1e-8; iteration count within 3 %.
 The products of every system are checked row by row against the oracle's.
+Both product schedules (row blocks through LDS; 8 or 16 lanes per row) are
+run, selected with CGMI_BATCH_LANES.
 """
 import numpy as np
 import pytest
@@ -30,8 +32,11 @@ def small_batch(nrhs, seed=1):
     return systems, np.concatenate(Bs)
 
 
+@pytest.mark.parametrize("lanes", ["0", "8", "16"])
 @pytest.mark.parametrize("nrhs", [1, 2, 4])
-def test_batch_matches_single_oracle_solves(nrhs):
+def test_batch_matches_single_oracle_solves(nrhs, lanes, monkeypatch):
+    # lanes: the product schedule (0 = row blocks through LDS, else lanes per row)
+    monkeypatch.setenv("CGMI_BATCH_LANES", lanes)
     systems, B = small_batch(nrhs)
     so, ptr, col, val = W.block_diagonal(systems)
     with cgmi.Batch(so, ptr, col, val, nrhs=nrhs) as bt:
@@ -52,7 +57,9 @@ def test_batch_matches_single_oracle_solves(nrhs):
             assert abs(int(iters[s, r]) - oi["iters"]) <= max(2, 0.03 * oi["iters"]), (s, r, iters[s, r], oi)
 
 
-def test_batch_spmm_rowwise():
+@pytest.mark.parametrize("lanes", ["0", "8", "16"])
+def test_batch_spmm_rowwise(lanes, monkeypatch):
+    monkeypatch.setenv("CGMI_BATCH_LANES", lanes)
     systems, B = small_batch(4, seed=2)
     so, ptr, col, val = W.block_diagonal(systems)
     X = np.random.default_rng(3).uniform(-1, 1, size=(so[-1], 4))
@@ -60,8 +67,13 @@ def test_batch_spmm_rowwise():
         Y = bt.spmm(to_dev(X)).cpu().numpy()
     for r in range(4):
         yo = oracle.spmv(0, ptr, col, val, X[:, r])
-        # one thread sums each row left to right from rounded products: bit-identical
-        assert np.array_equal(Y[:, r], yo)
+        if lanes == "0":
+            # one thread sums each row left to right from rounded products: bit-identical
+            assert np.array_equal(Y[:, r], yo)
+        else:
+            # lanes per row: fused multiply-adds and a butterfly, a different rounding order
+            bound = 1e-13 * spmv_bound(0, ptr, col, val, X[:, r])
+            assert np.all(np.abs(Y[:, r] - yo) <= bound), float(np.max(np.abs(Y[:, r] - yo) - bound))
 
 
 def test_batch_statuses_per_pair():
@@ -100,6 +112,7 @@ def test_batch_autotune_and_determinism():
         tuned = bt.autotune()
         say(f"autotune: {tuned}")
         assert tuned["entries_per_block"] in (256, 512, 1024) and tuned["workgroups"] >= len(systems)
+        assert tuned["lanes_per_row"] in (0, 8, 16)
         X3, i3, it3, st3 = bt.solve(to_dev(B))
         assert np.all(st3 == 0)
         d = (X3 - X1).cpu().numpy()
