@@ -505,6 +505,8 @@ __global__ __launch_bounds__(kBlock) void k_update_r(int n, int chunk, double *_
     const int blk = xcd_remap(blockIdx.x, gridDim.x);
     const int i0 = blk * chunk, i1 = min(n, i0 + chunk);
     const int t = threadIdx.x;
+    double pv[kPartPerThread];
+    partials_load(sig_part, n_sig, pv); // first, so their sum does not wait for the vector loads
     double qv[kPre], rv[kPre];
 #pragma unroll
     for (int u = 0; u < kPre; ++u) {
@@ -512,7 +514,7 @@ __global__ __launch_bounds__(kBlock) void k_update_r(int n, int chunk, double *_
         qv[u] = i < i1 ? q_value<GATHER>(q, g, i) : 0.0;
         rv[u] = i < i1 ? r[i] : 0.0;
     }
-    const double sigma = reduce_partials(sig_part, n_sig, red);
+    const double sigma = partials_sum(pv, n_sig, red);
     const bool lead = blockIdx.x == 0 && t == 0;
     if (!(sigma > 0.0) || !isfinite(sigma)) {
         if (lead) {
@@ -565,6 +567,8 @@ __global__ __launch_bounds__(kBlock) void k_update_xp(int n, int chunk, double *
     const int blk = xcd_remap(blockIdx.x, gridDim.x);
     const int i0 = blk * chunk, i1 = min(n, i0 + chunk);
     const int t = threadIdx.x;
+    double part[kPartPerThread];
+    partials_load(rho_part, n_rho, part); // first, so their sum does not wait for the vector loads
     double pv[kPre], xv[kPre], rv[kPre];
 #pragma unroll
     for (int u = 0; u < kPre; ++u) {
@@ -574,7 +578,7 @@ __global__ __launch_bounds__(kBlock) void k_update_xp(int n, int chunk, double *
         xv[u] = ok ? x[i] : 0.0;
         rv[u] = ok ? r[i] : 0.0;
     }
-    const double rho_new = reduce_partials(rho_part, n_rho, red);
+    const double rho_new = partials_sum(part, n_rho, red);
     const double alpha = st->alpha;
     const double beta = rho_new / st->rho;
     const bool conv = sqrt(rho_new) <= st->tol_nb; // last step: x only
