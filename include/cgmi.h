@@ -131,7 +131,8 @@ int cg_set_batch(cg_handle *h, int32_t iters_per_launch);
 /*
  * cg_solve -- CG from x0 to ||r||_2 <= tol ||b||_2 or maxit products.
  *   b     device, n float64 (read only)
- *   x     device, n float64: in x0, out the solution / last iterate.
+ *   x     device, n float64: in x0, out the solution / last iterate; a
+ *         buffer distinct from b (CG_ERR_ARG otherwise).
  *         Untouched on CG_ERR_ARG and CG_ERR_NONFINITE; set to 0 when b == 0.
  *   tol   >= 0, relative to ||b||_2
  *   maxit >= 0

@@ -1000,7 +1000,7 @@ int cg_batch_solve(cg_batch *h, const double *B, double *X, double tol, int32_t 
         info->ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
         return code;
     };
-    if (!h || !B || !X || !(tol >= 0.0) || maxit < 0)
+    if (!h || !B || !X || B == X || !(tol >= 0.0) || maxit < 0)
         return done(CG_ERR_ARG);
     hipStream_t s = h->stream;
     int st = build_graph(h);

@@ -699,8 +699,8 @@ int cg_solve(cg_handle *h, const double *b, double *x, double tol, int32_t maxit
     const int n = h->dm.n;
     if (n == 0)
         return done(CG_OK);
-    if (!b || !x) {
-        h->err = "b / x NULL";
+    if (!b || !x || b == x) {
+        h->err = "b / x NULL or the same buffer";
         return done(CG_ERR_ARG);
     }
     hipStream_t s = h->stream;
@@ -770,8 +770,8 @@ int cg_solve_mixed(cg_handle *h, const double *b, double *x, double tol, int32_t
     const int n = h->dm.n;
     if (n == 0)
         return done(CG_OK);
-    if (!b || !x) {
-        h->err = "b / x NULL";
+    if (!b || !x || b == x) {
+        h->err = "b / x NULL or the same buffer";
         return done(CG_ERR_ARG);
     }
     hipStream_t s = h->stream;

@@ -188,6 +188,9 @@ def test_status_paths(fmt):
         assert st == cgmi.CG_ERR_ARG
         st, _ = cgmi.cg_solve(S.h, to_dev(b).data_ptr(), x.data_ptr(), 1e-8, -1)
         assert st == cgmi.CG_ERR_ARG
+        bb = to_dev(b)
+        st, _ = cgmi.cg_solve(S.h, bb.data_ptr(), bb.data_ptr(), 1e-8, 10)   # b and x the same buffer
+        assert st == cgmi.CG_ERR_ARG and torch.equal(bb, to_dev(b))
 
 
 @pytest.mark.parametrize("fmt", [CSR, SYM, CSC])
