@@ -244,12 +244,25 @@ __global__ __launch_bounds__(kBlock) void k_bspmm(const WgDesc *__restrict__ wgs
                 lptr[t + 1] = ptr[r0 + t + 1] - e0;
             if (t == 0)
                 lptr[0] = 0;
+            // products stored by right-hand side (plane r holds entry e at r*E + e):
+            // consecutive threads write consecutive words, and a row's sum reads
+            // one contiguous run per plane
 #pragma unroll
             for (int m = 0; m < EPT; ++m)
                 if (c[m] >= 0) {
+                    if constexpr (R % 2 == 0) {
+                        const double2 *p2 = reinterpret_cast<const double2 *>(P + (size_t)c[m] * R);
 #pragma unroll
-                    for (int r = 0; r < R; ++r)
-                        prod[(t + m * kBlock) * R + r] = v[m] * P[(size_t)c[m] * R + r];
+                        for (int h2 = 0; h2 < R / 2; ++h2) {
+                            const double2 pv = p2[h2];
+                            prod[(2 * h2) * E + t + m * kBlock] = v[m] * pv.x;
+                            prod[(2 * h2 + 1) * E + t + m * kBlock] = v[m] * pv.y;
+                        }
+                    } else {
+#pragma unroll
+                        for (int r = 0; r < R; ++r)
+                            prod[r * E + t + m * kBlock] = v[m] * P[(size_t)c[m] * R + r];
+                    }
                 }
             __syncthreads();
             if (t < nr) {
@@ -258,7 +271,7 @@ __global__ __launch_bounds__(kBlock) void k_bspmm(const WgDesc *__restrict__ wgs
                 for (int r = 0; r < R; ++r) {
                     double a = 0.0;
                     for (int k = k0; k < k1; ++k)
-                        a += prod[k * R + r];
+                        a += prod[r * E + k];
                     Q[(size_t)(r0 + t) * R + r] = a;
                     sig[r] = fma(P[(size_t)(r0 + t) * R + r], a, sig[r]);
                 }
