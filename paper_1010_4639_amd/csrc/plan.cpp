@@ -3,6 +3,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 
 #include "../../include/cgmi.h"
@@ -226,7 +227,12 @@ static int plan_panels(Plan &p, const int32_t *ptr, const int32_t *idx, std::str
     for (int64_t j = 0; j < n; ++j)
         for (int64_t k = ptr[j]; k < ptr[j + 1]; ++k)
             bw = std::max<int64_t>(bw, std::llabs((int64_t)idx[k] - j));
-    const int64_t W = std::min<int64_t>(n, std::max<int64_t>(2 * bw + 1, kPanelMinWidth));
+    int64_t W = std::max<int64_t>(2 * bw + 1, kPanelMinWidth);
+    // experiments: a wider panel (never narrower than 2 bw + 1, which the
+    // two-colour guarantee needs); at n the product is one row-ordered panel
+    if (const char *e = std::getenv("CGMI_PANEL_WIDTH"))
+        W = std::max<int64_t>(W, std::atoll(e));
+    W = std::min<int64_t>(n, W);
     const int64_t np = (n + W - 1) / W;
     p.panel = true;
     p.pn_width = W;

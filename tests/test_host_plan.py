@@ -222,6 +222,18 @@ def test_panel_plan_long_slot_and_banded():
     assert lens.max() == n and P["stats"]["max_block_entries"] == n
 
 
+def test_panel_width_override(monkeypatch):
+    s = W.fem_p1_system(30, 28, 26, seed=9)
+    monkeypatch.setenv("CGMI_PANEL_WIDTH", "9000")
+    P = check_panel_plan(s.rowptr, s.col)
+    assert P["width"] == 9000 and P["stats"]["colors"] == 2
+    monkeypatch.setenv("CGMI_PANEL_WIDTH", "10")                # never below 2 bw + 1 / 4096
+    assert check_panel_plan(s.rowptr, s.col)["width"] == 4096
+    monkeypatch.setenv("CGMI_PANEL_WIDTH", str(s.n))            # one panel: one colour, nothing parked
+    P = check_panel_plan(s.rowptr, s.col)
+    assert P["stats"]["colors"] == 1 and P["first_parked"] == P["target"].size == s.n
+
+
 def test_analyze_export_refuses_csc():
     s = W.fem_p1_system(4, 4, 4, seed=1)
     st, _ = cgmi.cg_analyze_export(cgmi.CG_FMT_CSC, s.n, s.rowptr, s.col)
