@@ -25,6 +25,8 @@ def main(argv=None):
     ap.add_argument("--workload", default="fem100")
     ap.add_argument("--reps", type=int, default=3)
     ap.add_argument("--tol", type=float, default=1e-10)
+    ap.add_argument("--cpu-iters", type=int, default=50)
+    ap.add_argument("--no-cpu", action="store_true")
     a = ap.parse_args(argv)
     import numpy as np
     import torch
@@ -92,6 +94,8 @@ def main(argv=None):
         return e0.elapsed_time(e1) * 1e3 / reps
 
     us_asm = timed(lambda: FS.fem.assemble(nu_d, out=vals))
+    FS_vals = vals.cpu().numpy()
+    FS_rp, FS_col = FS.fem.pattern()
     us_grad = timed(lambda: FS.fem.nu_grad(lam, xs, out=gout))
     nnz, nelem = FS.nnz, FS.nelem
     ncontrib = int(np.sum(np.count_nonzero(dof[tets] >= 0, axis=1) ** 2))
@@ -111,6 +115,30 @@ def main(argv=None):
         "contributions": ncontrib,
     }
     FS.close()
+    if not a.no_cpu:
+        # the oracle beside it (test infrastructure, timed on a bounded sample):
+        # its CG per iteration on the same matrix, scaled by the GPU's forward +
+        # adjoint iteration counts, plus its element gradient over every element
+        import oracle
+        from oracle import fem as OF
+        vals = FS_vals
+        t1 = time.perf_counter()
+        _, oi, _ = oracle.cg(oracle.FMT_CSR, FS_rp, FS_col, vals, s.b, tol=0.0, maxit=a.cpu_iters)
+        ms_it = oi["ms_loop"] / max(oi["iters"], 1)
+        t2 = time.perf_counter()
+        K = np.empty((nelem, 4, 4))
+        for i in range(0, nelem, 1 << 20):
+            K[i:i + (1 << 20)] = OF.element_matrices(coords, tets[i:i + (1 << 20)])
+        lam_h = W.uniform_vector(s.n, seed=41)
+        t3 = time.perf_counter()
+        OF.nu_grad(K, tets, dof, lam_h, xs.cpu().numpy())
+        t4 = time.perf_counter()
+        out["cpu_baseline"] = dict(kind="oracle", cores=1, unit="ms",
+                                   value=round(ms_it * 2 * info["iters"] + (t4 - t3) * 1e3, 1),
+                                   sample=f"{oi['iters']} oracle CG iterations ({ms_it:.2f} ms each) scaled by "
+                                          f"2 x {info['iters']} (forward + adjoint); element gradient "
+                                          f"{(t4 - t3) * 1e3:.0f} ms (numpy, after {(t3 - t2):.1f} s of element "
+                                          f"matrices)")
     print(json.dumps(out), flush=True)
 
 

@@ -27,6 +27,8 @@ def main(argv=None):
     ap.add_argument("--tol", type=float, default=1e-10)
     ap.add_argument("--workers", type=int, default=8)
     ap.add_argument("--loop-systems", type=int, default=32)
+    ap.add_argument("--cpu-systems", type=int, default=2)
+    ap.add_argument("--no-cpu", action="store_true")
     a = ap.parse_args(argv)
     import numpy as np
     import torch
@@ -74,6 +76,21 @@ def main(argv=None):
     out["loop_ms_timed"] = round(loop_ms, 3)
     out["loop_ms_scaled"] = round(loop_ms * int(ptr[-1]) / loop_nnz, 3)
     out["speedup_vs_loop"] = round(out["loop_ms_scaled"] / out["batched_ms"], 3)
+    if not a.no_cpu:
+        # the oracle beside it: serial C CG on the first looped systems (every
+        # right-hand side, to the same tolerance), scaled by nnz like the loop
+        import oracle
+        t_ms, o_nnz = 0.0, 0
+        for s in range(min(a.cpu_systems, a.nsys)):
+            rp, c, v = systems[s]
+            r0, r1 = so[s], so[s + 1]
+            for r in range(a.nrhs):
+                _, oi, _ = oracle.cg(0, rp, c, v, np.ascontiguousarray(B[r0:r1, r]), tol=a.tol, maxit=50000)
+                t_ms += oi["ms_loop"]
+            o_nnz += int(rp[-1])
+        out["cpu_baseline"] = dict(kind="oracle", cores=1, unit="ms", value=round(t_ms * int(ptr[-1]) / o_nnz, 1),
+                                   sample=f"oracle CG on {min(a.cpu_systems, a.nsys)} systems x {a.nrhs} right-hand "
+                                          f"sides ({t_ms:.0f} ms), scaled by total nnz / sampled nnz")
     print(json.dumps(out), flush=True)
 
 

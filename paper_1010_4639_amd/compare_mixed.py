@@ -26,6 +26,8 @@ def main(argv=None):
     ap.add_argument("--inner-tol", type=float, default=1e-4)
     ap.add_argument("--maxit", type=int, default=200000)
     ap.add_argument("--reps", type=int, default=2)
+    ap.add_argument("--cpu-iters", type=int, default=30)
+    ap.add_argument("--no-cpu", action="store_true")
     a = ap.parse_args(argv)
     import statistics
     import time
@@ -98,6 +100,17 @@ def main(argv=None):
             res["speedup"] = round(res["fp64"]["ms"] / res["mixed"]["ms"], 3)
             res["speedup_vs_scaled_fp64"] = round(res["fp64_scaled"]["ms"] / res["mixed"]["ms"], 3)
             out[name] = res
+    if not a.no_cpu:
+        # the oracle beside it: serial C CG per iteration on the same system
+        # (a bounded sample), scaled by the FP64 iteration count
+        import oracle
+        name = a.formats.split(",")[0]
+        _, oi, _ = oracle.cg(cgmi.FORMATS[name], *arrs[name], s.b, tol=0.0, maxit=a.cpu_iters)
+        ms_it = oi["ms_loop"] / max(oi["iters"], 1)
+        out["cpu_baseline"] = dict(kind="oracle", cores=1, unit="ms",
+                                   value=round(ms_it * out[name]["fp64"]["iters"], 1),
+                                   sample=f"{oi['iters']} oracle CG iterations in {name} at {ms_it:.2f} ms each, "
+                                          f"scaled by the FP64 GPU iteration count")
     print(json.dumps(out), flush=True)
 
 
