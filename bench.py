@@ -144,6 +144,23 @@ def main():
         spmv[name] = dict(us=us, bytes=byts, GBps=byts / us / 1e3, colors=S.stats()["colors"])
         log(f"[bench] spmv {name}: {us:.1f} us/launch, {byts / 1e6:.1f} MB algorithmic, "
             f"{byts / us / 1e3:.0f} GB/s")
+    # cold products: a 1 GiB write evicts the matrix from the caches (L2, and
+    # the 256 MB Infinity Cache) before each single timed launch; median of 5
+    scratch = torch.empty(1 << 27, dtype=torch.float64, device=dev)
+    for name, S in solvers.items():
+        cold = []
+        for i in range(5):
+            scratch.fill_(float(i))
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            S.spmv(xs, ys)
+            e1.record(stream)
+            e1.synchronize()
+            cold.append(e0.elapsed_time(e1) * 1e3)
+        spmv[name]["cold_us"] = float(np.median(cold))
+        log(f"[bench] spmv {name} cold: {spmv[name]['cold_us']:.1f} us/launch, "
+            f"{spmv[name]['bytes'] / spmv[name]['cold_us'] / 1e3:.0f} GB/s")
+    del scratch
     # plain device copy of 1 GiB for the practical bandwidth ceiling
     a = torch.empty(1 << 27, dtype=torch.float64, device=dev)
     c = torch.empty_like(a)
@@ -164,6 +181,8 @@ def main():
         per_format[name] = dict(time_to_tol_ms=round(ms, 3), iters=its[-1], us_per_iter=round(1e3 * ms / its[-1], 3),
                                 relres_true=per[name][-1]["relres_true"],
                                 spmv_us=round(spmv[name]["us"], 3), spmv_GBps=round(spmv[name]["GBps"], 1),
+                                spmv_cold_us=round(spmv[name]["cold_us"], 3),
+                                spmv_cold_GBps=round(spmv[name]["bytes"] / spmv[name]["cold_us"] / 1e3, 1),
                                 spmv_colors=spmv[name]["colors"])
     # dominant product kernel: largest share of the step's time
     dom = max(solvers, key=lambda k: spmv[k]["us"] * per_format[k]["iters"])
