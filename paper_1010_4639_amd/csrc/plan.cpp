@@ -173,10 +173,13 @@ static int64_t block_entries(int64_t nnz, int64_t floor)
 
 static void plan_vectors(Plan &p)
 {
-    // >= 1024 elements per workgroup on large vectors; small vectors use
-    // down to 256 per workgroup so that more compute units take part
+    // 1024 elements per workgroup on large vectors (512 for the symmetric
+    // format, whose r update also finishes ~2 parked sums per row: measured
+    // 3 % faster there, 3 % slower for CSR); small vectors use down to 256
+    // per workgroup so that more compute units take part
     const int64_t n = p.n;
-    int64_t g = std::max<int64_t>((n + 1023) / 1024, std::min<int64_t>((n + 255) / 256, 512));
+    const int64_t per = p.format == kSymCsr ? 512 : 1024;
+    int64_t g = std::max<int64_t>((n + per - 1) / per, std::min<int64_t>((n + 255) / 256, 512));
     g = std::max<int64_t>(1, std::min<int64_t>(g, kMaxVecBlocks));
     p.vec_blocks = (int)g;
     p.vec_chunk = (int)((n + g - 1) / g);

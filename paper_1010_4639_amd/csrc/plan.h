@@ -39,7 +39,7 @@ constexpr int kMaxScatterEntries = 2048;   // 8 entries per thread held in regis
 constexpr int kMaxBlockLines = 256;
 constexpr int kMaxColors = 64;
 constexpr int kMaxSpmvBlocks = 2048;    // CSR product workgroups (= dot partials)
-constexpr int kMaxVecBlocks = 1024;
+constexpr int kMaxVecBlocks = 2048;
 constexpr int kStreamPerThread = 8;                    // CSR row-block kernel: entries per thread
 constexpr int kStreamEntries = kBlock * kStreamPerThread; // entries per CSR row block
 constexpr int kStreamRows = kBlock;                    // rows per CSR row block (one thread each)
