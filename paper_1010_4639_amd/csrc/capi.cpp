@@ -167,6 +167,23 @@ int upload_all(cg_handle *h, const std::vector<int32_t> &ptr0, const std::vector
         m.csr_rbe = rbe;
         m.csr_nrb = (int)p.csr_rb.size() - 1;
     }
+    if (p.format == kCsr && p.csr_slices) {
+        int32_t *off, *col, *src;
+        double *sv;
+        if ((st = upload(h, &off, p.sl_off.data(), p.sl_off.size())) != CG_OK ||
+            (st = upload(h, &col, p.sl_col.data(), p.sl_col.size())) != CG_OK ||
+            (st = upload(h, &src, p.sl_src.data(), p.sl_src.size())) != CG_OK ||
+            (st = dalloc(h, &sv, std::max<size_t>(p.sl_src.size(), 1))) != CG_OK)
+            return st;
+        m.csr_slices = true;
+        m.csr_nslices = (int)p.sl_off.size() - 1;
+        m.sl_off = off;
+        m.sl_col = col;
+        m.sl_src = src;
+        m.sl_val = sv;
+        if (h->mixed && (st = dalloc(h, &m.sl_val32, std::max<size_t>(p.sl_src.size(), 1))) != CG_OK)
+            return st;
+    }
     if (p.panel && n > 0) {
         // CSC column panels: slots of colour 0 first (see plan.h)
         const int64_t ns = (int64_t)p.pn_slot_target.size();
@@ -334,6 +351,7 @@ void fill_stats(const Plan &p, cg_plan_stats *s)
     s->vec_blocks = p.vec_blocks;
     s->colors = p.ncolors;
     s->max_block_entries = p.max_entries;
+    s->csr_slices = p.csr_slices ? 1 : 0;
     s->slots = p.panel ? (int64_t)p.pn_slot_target.size() : (int64_t)p.slot_target.size();
     s->plan_bytes = p.device_bytes();
 }
@@ -469,6 +487,8 @@ int refresh_values(cg_handle *h)
     const int64_t nnz = h->plan.nnz;
     if (m.panel)
         launch_permute(nnz, m.val, m.pn_src, m.pn_val, h->stream);
+    if (m.csr_slices)
+        launch_permute((int64_t)h->plan.sl_src.size(), m.val, m.sl_src, m.sl_val, h->stream);
     HIP_TRY(h, hipGetLastError());
     if (h->mixed && m.n > 0) {
         const int st = mixed_rescale(h);
@@ -476,6 +496,8 @@ int refresh_values(cg_handle *h)
             return st;
         if (m.panel)
             launch_permute(nnz, m.val32, m.pn_src, m.pn_val32, h->stream);
+        if (m.csr_slices)
+            launch_permute((int64_t)h->plan.sl_src.size(), m.val32, m.sl_src, m.sl_val32, h->stream);
         HIP_TRY(h, hipGetLastError());
     }
     return CG_OK;

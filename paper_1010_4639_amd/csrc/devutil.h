@@ -45,27 +45,29 @@ __device__ __forceinline__ double block_sum(double v, double *red)
     return t;
 }
 
-// Partials (m <= kMaxSpmvBlocks) in two steps, so that their loads can be
+// Partials (m <= N * kBlock) in two steps, so that their loads can be
 // issued before a kernel's own loads and summed while those are in flight:
 // partials_load, then partials_sum, which adds them in the order of
 // reduce_partials (same bits).
 constexpr int kPartPerThread = (kMaxSpmvBlocks + kBlock - 1) / kBlock;
 static_assert(kMaxVecBlocks <= kMaxSpmvBlocks, "vector partials fit the same registers");
 
-__device__ __forceinline__ void partials_load(const double *__restrict__ part, int m, double (&pv)[kPartPerThread])
+template <int N>
+__device__ __forceinline__ void partials_load(const double *__restrict__ part, int m, double (&pv)[N])
 {
 #pragma unroll
-    for (int j = 0; j < kPartPerThread; ++j) {
+    for (int j = 0; j < N; ++j) {
         const int i = threadIdx.x + j * kBlock;
         pv[j] = i < m ? part[i] : 0.0;
     }
 }
 
-__device__ __forceinline__ double partials_sum(const double (&pv)[kPartPerThread], int m, double *red)
+template <int N>
+__device__ __forceinline__ double partials_sum(const double (&pv)[N], int m, double *red)
 {
     double s = 0.0;
 #pragma unroll
-    for (int j = 0; j < kPartPerThread; ++j)
+    for (int j = 0; j < N; ++j)
         if ((int)threadIdx.x + j * kBlock < m)
             s += pv[j];
     return block_sum(s, red);

@@ -55,6 +55,11 @@ struct DevMatrix {
     int csr_nrb = 0;
     const int32_t *csr_rb = nullptr;
     const int2 *csr_rbe = nullptr;       // per row-block boundary: {first row, first entry}
+    bool csr_slices = false;             // sliced layout (plan.h)
+    int csr_nslices = 0;
+    const int32_t *sl_off = nullptr, *sl_col = nullptr, *sl_src = nullptr;
+    double *sl_val = nullptr;            // values at the slice positions (0 at padding)
+    float *sl_val32 = nullptr;           // mixed precision: val32 at the slice positions
     // scatter
     int nblocks = 0, ncolors = 0, lds_entries = 0, lds_lines = 0, max_slots = 0;
     std::vector<int32_t> color_off;      // host copy: blocks per colour
@@ -130,7 +135,8 @@ void launch_init_state(const DevMatrix &m, DevState *st, const double *bb_part, 
 void launch_true_residual(const DevMatrix &m, const double *b, const double *q, double *part, DevState *st,
                           hipStream_t s);
 void launch_fill(int n, double *x, double v, hipStream_t s);
-// dst[k] = src[perm[k]] for k < nnz (values into the CSC panel order)
+// dst[k] = src[perm[k]] for k < nnz, 0 where perm[k] < 0 (values into the
+// CSC panel order or the CSR slice positions)
 void launch_permute(int64_t nnz, const double *src, const int32_t *perm, double *dst, hipStream_t s);
 void launch_permute(int64_t nnz, const float *src, const int32_t *perm, float *dst, hipStream_t s);
 // val[k] = src[perm ? perm[k] : k] for k < nnz

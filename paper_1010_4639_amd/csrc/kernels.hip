@@ -206,6 +206,66 @@ __global__ __launch_bounds__(kBlock) void k_spmv_csr_rows(int nrb, const int2 *_
         sig_part[wg] = sig;
 }
 
+// ------------------------------------------------- CSR slices
+// Sliced layout (plan.h): one wavefront per slice of 64 rows, lane l owns row
+// 64 s + l and walks its entries left to right, U positions per round (all
+// index / value loads of a round first -- coalesced, non-temporal -- then the
+// U gathers of x, then the sums).  For a stencil-like matrix the k-th entries
+// of neighbouring rows are neighbouring columns, so each gather touches a few
+// cache lines instead of one per lane.  Each row is summed as a + v x with
+// the product rounded before the add (no fused multiply-add), as the row-block
+// kernel's LDS products are: y is bit-identical to the serial row-by-row
+// loop.  With more slices than 4 x kMaxSliceWgs each wave takes several
+// consecutive slices of its workgroup's range.  Fused epilogue: partial of x'y.
+template <class VT, class PT>
+__global__ __launch_bounds__(kBlock) void k_spmv_csr_slices(int n, int ns, const int32_t *__restrict__ off,
+                                                            const int32_t *__restrict__ col,
+                                                            const VT *__restrict__ val, const PT *__restrict__ x,
+                                                            double *__restrict__ y, double *__restrict__ sig_part,
+                                                            DevState *st)
+{
+#pragma clang fp contract(off)
+    constexpr int U = 8;
+    __shared__ double red[kWaves];
+    const int wg = xcd_remap(blockIdx.x, gridDim.x);
+    if (st != nullptr && !iter_gate(st))
+        return;
+    const int s0 = (int)((int64_t)wg * ns / gridDim.x);
+    const int s1 = (int)((int64_t)(wg + 1) * ns / gridDim.x);
+    const int lane = threadIdx.x & 63;
+    double sig = 0.0;
+    for (int sl = s0 + (int)(threadIdx.x >> 6); sl < s1; sl += kWaves) {
+        const int e0 = off[sl], len = (off[sl + 1] - e0) / kSliceRows;
+        double a = 0.0;
+        for (int k0 = 0; k0 < len; k0 += U) {
+            int c[U];
+            double v[U], xv[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const bool ok = k0 + u < len;
+                const int e = e0 + (k0 + u) * kSliceRows + lane;
+                c[u] = ok ? __builtin_nontemporal_load(col + e) : -1;
+                v[u] = ok ? (double)__builtin_nontemporal_load(val + e) : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                xv[u] = c[u] >= 0 ? (double)x[c[u]] : 0.0;
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (c[u] >= 0)
+                    a = a + v[u] * xv[u];
+        }
+        const int r = sl * kSliceRows + lane;
+        if (r < n) {
+            y[r] = a;
+            sig = fma((double)x[r], a, sig);
+        }
+    }
+    sig = block_sum(sig, red);
+    if (threadIdx.x == 0)
+        sig_part[wg] = sig;
+}
+
 // ------------------------------------------------- CSC column panels
 // One launch over every chunk of every panel (chunks of colour 0 first; a
 // workgroup walks a contiguous range of chunks).  A chunk is a run of write
@@ -296,14 +356,17 @@ __global__ __launch_bounds__(kBlock) void k_panel_rows(int nch, const int32_t *_
         sig_part[wg] = sig;
 }
 
-// dst[k] = src[perm[k]]: values into the panel order
+// dst[k] = src[perm[k]] (0 where perm[k] < 0): values into the panel order
+// or the slice positions
 template <class T>
 __global__ __launch_bounds__(kBlock) void k_permute(int64_t nnz, const T *__restrict__ src,
                                                     const int32_t *__restrict__ perm, T *__restrict__ dst)
 {
     const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (k < nnz)
-        dst[k] = src[perm[k]];
+    if (k < nnz) {
+        const int32_t j = perm[k];
+        dst[k] = j >= 0 ? src[j] : T(0);
+    }
 }
 
 // ------------------------------------------------- coloured scatter
@@ -493,7 +556,8 @@ __device__ __forceinline__ double q_value(const double *__restrict__ q, const Ro
     return a;
 }
 
-template <bool GATHER>
+// PPT: dot partials per thread (n_sig <= PPT * 256)
+template <bool GATHER, int PPT>
 __global__ __launch_bounds__(kBlock) void k_update_r(int n, int chunk, double *__restrict__ r,
                                                      const double *__restrict__ q, DevState *st,
                                                      const double *__restrict__ sig_part, int n_sig,
@@ -505,7 +569,7 @@ __global__ __launch_bounds__(kBlock) void k_update_r(int n, int chunk, double *_
     const int blk = xcd_remap(blockIdx.x, gridDim.x);
     const int i0 = blk * chunk, i1 = min(n, i0 + chunk);
     const int t = threadIdx.x;
-    double pv[kPartPerThread];
+    double pv[PPT];
     partials_load(sig_part, n_sig, pv); // first, so their sum does not wait for the vector loads
     double qv[kPre], rv[kPre];
 #pragma unroll
@@ -863,6 +927,8 @@ void scatter_dispatch(const DevMatrix &m, const VT *val, const PT *x, double *y,
 
 inline const double *panel_vals(const DevMatrix &m, const double *) { return m.pn_val; }
 inline const float *panel_vals(const DevMatrix &m, const float *) { return m.pn_val32; }
+inline const double *slice_vals(const DevMatrix &m, const double *) { return m.sl_val; }
+inline const float *slice_vals(const DevMatrix &m, const float *) { return m.sl_val32; }
 
 template <class VT, class PT>
 void spmv_any(const DevMatrix &m, const VT *val, const PT *x, double *y, double *sig_part, const IterCtx &c,
@@ -880,7 +946,10 @@ void spmv_any(const DevMatrix &m, const VT *val, const PT *x, double *y, double 
                                m.rs_ptr, m.rs_idx, m.has_c0, m.part, y, c.st);
         return;
     }
-    if (m.format == kCsr && m.csr_stream) {
+    if (m.format == kCsr && m.csr_slices) {
+        hipLaunchKernelGGL((k_spmv_csr_slices<VT, PT>), dim3(m.csr_blocks), dim3(kBlock), 0, s, m.n, m.csr_nslices,
+                           m.sl_off, m.sl_col, slice_vals(m, val), x, y, sig_part, c.st);
+    } else if (m.format == kCsr && m.csr_stream) {
         hipLaunchKernelGGL((k_spmv_csr_rows<VT, PT>), dim3(m.csr_blocks), dim3(kBlock), 0, s, m.csr_nrb, m.csr_rbe,
                            m.ptr, m.idx, val, x, y, sig_part, c.st);
     } else if (m.format == kCsr) {
@@ -911,17 +980,21 @@ void launch_spmv32(const DevMatrix &m, const float *x, double *y, double *sig_pa
 void launch_update_r(const DevMatrix &m, double *r, const double *q, DevState *st, const double *sig_part,
                      double *rho_part, hipStream_t s, bool rows_deferred)
 {
+    static_assert(kMaxSliceWgs <= 2 * kPartPerThread * kBlock, "slice partials fit twice the registers");
     if (rows_deferred && m.row_pass()) {
         RowPass g;
         g.rs_ptr = m.rs_ptr;
         g.rs_idx = m.rs_idx;
         g.has_c0 = m.has_c0;
         g.part = m.part;
-        hipLaunchKernelGGL(k_update_r<true>, dim3(m.vec_blocks), dim3(kBlock), 0, s, m.n, m.vec_chunk, r, q, st,
-                           sig_part, m.spmv_blocks(), rho_part, g);
+        hipLaunchKernelGGL((k_update_r<true, kPartPerThread>), dim3(m.vec_blocks), dim3(kBlock), 0, s, m.n,
+                           m.vec_chunk, r, q, st, sig_part, m.spmv_blocks(), rho_part, g);
+    } else if (m.spmv_blocks() > kPartPerThread * kBlock) { // CSR slices: up to kMaxSliceWgs partials
+        hipLaunchKernelGGL((k_update_r<false, 2 * kPartPerThread>), dim3(m.vec_blocks), dim3(kBlock), 0, s, m.n,
+                           m.vec_chunk, r, q, st, sig_part, m.spmv_blocks(), rho_part, RowPass{});
     } else {
-        hipLaunchKernelGGL(k_update_r<false>, dim3(m.vec_blocks), dim3(kBlock), 0, s, m.n, m.vec_chunk, r, q, st,
-                           sig_part, m.spmv_blocks(), rho_part, RowPass{});
+        hipLaunchKernelGGL((k_update_r<false, kPartPerThread>), dim3(m.vec_blocks), dim3(kBlock), 0, s, m.n,
+                           m.vec_chunk, r, q, st, sig_part, m.spmv_blocks(), rho_part, RowPass{});
     }
 }
 

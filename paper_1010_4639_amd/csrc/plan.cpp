@@ -12,8 +12,8 @@ namespace cgmi {
 
 int64_t Plan::device_bytes() const
 {
-    if (format == kCsr)
-        return (int64_t)csr_rb.size() * 4;
+    if (format == kCsr) // row-block starts; slices: offsets + entry source, column, value per position
+        return (int64_t)csr_rb.size() * 4 + (int64_t)sl_off.size() * 4 + (int64_t)sl_src.size() * (4 + 4 + 8);
     if (panel) // entry source + column + reordered value; slot target / pointer / parked sum; row lists
         return nnz * (4 + 4 + 8) + (int64_t)pn_slot_target.size() * (4 + 4 + 8 + 4) +
                (int64_t)pn_chunk_slot.size() * 8 + n * 5;
@@ -185,10 +185,55 @@ static void plan_vectors(Plan &p)
     p.vec_chunk = (int)((n + g - 1) / g);
 }
 
-static void plan_csr(Plan &p, const int32_t *ptr)
+// CSR slices (see plan.h).  mode: 0 = when the padding is small and rows are
+// short, 1 = whenever the padded size fits 32-bit positions.
+static bool plan_slices(Plan &p, const int32_t *ptr, const int32_t *idx, int mode)
+{
+    const int64_t n = p.n, nnz = p.nnz;
+    const int64_t ns = (n + kSliceRows - 1) / kSliceRows;
+    std::vector<int64_t> off((size_t)ns + 1, 0);
+    for (int64_t s = 0; s < ns; ++s) {
+        int64_t w = 0;
+        for (int64_t r = s * kSliceRows; r < std::min(n, (s + 1) * kSliceRows); ++r)
+            w = std::max<int64_t>(w, (int64_t)ptr[r + 1] - ptr[r]);
+        off[s + 1] = off[s] + w * kSliceRows;
+    }
+    const int64_t padded = off[ns];
+    if (padded > INT32_MAX)
+        return false;
+    if (mode == 0 && ((double)nnz / (double)n > kStreamMaxMeanRow || (double)(padded - nnz) > kSliceMaxPadding * nnz))
+        return false;
+    p.csr_slices = true;
+    p.sl_off.assign(off.begin(), off.end());
+    p.sl_src.assign((size_t)padded, -1);
+    p.sl_col.assign((size_t)padded, -1);
+    for (int64_t r = 0; r < n; ++r) {
+        const int64_t base = off[r / kSliceRows] + r % kSliceRows;
+        for (int64_t k = ptr[r]; k < ptr[r + 1]; ++k) {
+            const int64_t q = base + (k - ptr[r]) * kSliceRows;
+            p.sl_src[q] = (int32_t)k;
+            p.sl_col[q] = idx[k];
+        }
+    }
+    // one slice per wavefront up to kMaxSliceWgs workgroups, then each wave
+    // takes several (contiguous per workgroup)
+    const int64_t g = (ns + kWavesPerBlock - 1) / kWavesPerBlock;
+    p.csr_blocks = (int)std::max<int64_t>(1, std::min<int64_t>(g, kMaxSliceWgs));
+    p.csr_rows_per_block = 0;
+    return true;
+}
+
+static void plan_csr(Plan &p, const int32_t *ptr, const int32_t *idx)
 {
     const int64_t n = p.n;
     const double mean = (double)p.nnz / (double)n;
+    // experiments: CGMI_CSR_LAYOUT = rows (row blocks / lanes per row) or
+    // slices (sliced layout whatever its padding)
+    int mode = 0;
+    if (const char *e = std::getenv("CGMI_CSR_LAYOUT"))
+        mode = std::strcmp(e, "slices") == 0 ? 1 : std::strcmp(e, "rows") == 0 ? -1 : 0;
+    if (mode >= 0 && plan_slices(p, ptr, idx, mode))
+        return;
     if (mean <= kStreamMaxMeanRow) {
         // row blocks: <= `be` entries (<= kStreamEntries) and <= kStreamRows
         // rows; a row longer than kStreamEntries is a block of its own
@@ -525,7 +570,7 @@ int build_plan(int fmt, int64_t n, const int32_t *ptr0, const int32_t *idx0, int
     p.lanes = lanes_for_mean_length(mean);
     plan_vectors(p);
     if (fmt == kCsr) {
-        plan_csr(p, ptr0);
+        plan_csr(p, ptr0, idx0);
         return CG_OK;
     }
     if (fmt == kCsc)

@@ -25,6 +25,15 @@
 // y; colour-1 slots are parked and added row by row afterwards.  This is the
 // two-dimensional blocking of compressed-sparse-blocks storage applied to
 // the transpose product: column blocks for the scatter, row order inside.
+//
+// CSR slices.  Rows are grouped in slices of 64 consecutive rows, one per
+// wavefront lane, and a slice stores the k-th entry of each of its rows
+// contiguously (positions off + 64 k + lane; rows shorter than the slice's
+// longest are padded with source -1).  This is the sliced ELLPACK layout
+// (SELL-C-sigma, Kreutzer et al. 2014) with C = 64 and no row sorting: for a
+// stencil-like matrix the lanes of one load read neighbouring x entries, so
+// the gather of x becomes a near-contiguous load.  Chosen when the padding
+// stays small; each row is still summed left to right by one lane.
 #pragma once
 
 #include <cstdint>
@@ -44,6 +53,10 @@ constexpr int kStreamPerThread = 8;                    // CSR row-block kernel: 
 constexpr int kStreamEntries = kBlock * kStreamPerThread; // entries per CSR row block
 constexpr int kStreamRows = kBlock;                    // rows per CSR row block (one thread each)
 constexpr double kStreamMaxMeanRow = 32.0;             // longer mean rows use lanes-per-row
+constexpr int kSliceRows = 64;          // CSR slices: rows per slice (one wavefront, a row per lane)
+constexpr int kWavesPerBlock = kBlock / kSliceRows;
+constexpr int kMaxSliceWgs = 2 * kMaxSpmvBlocks; // CSR slice kernel workgroups (= dot partials)
+constexpr double kSliceMaxPadding = 0.125; // slices only while padding <= this fraction of nnz
 constexpr int kPanelMinWidth = 4096;    // CSC panels span at least this many columns
 constexpr int kPanelChunkEntries = kStreamEntries; // entries per CSC panel chunk
 constexpr int kPanelChunkSlots = kBlock;           // slots per CSC panel chunk (one thread each)
@@ -70,6 +83,10 @@ struct Plan {
     int csr_blocks = 0, csr_rows_per_block = 0;
     bool csr_stream = false;
     std::vector<int32_t> csr_rb;          // row-block starts (nrb + 1), stream mode
+    bool csr_slices = false;              // sliced layout (replaces row blocks / lanes per row)
+    std::vector<int32_t> sl_off;          // [slices + 1] first position of each slice (multiple of 64)
+    std::vector<int32_t> sl_src;          // [positions] caller entry (0-based) at each position, -1 = padding
+    std::vector<int32_t> sl_col;          // [positions] column at each position, -1 = padding
     // scatter formats
     int nblocks = 0, ncolors = 0, max_entries = 0, max_lines = 0, max_slots = 0;
     std::vector<ScatterBlock> blocks;     // by block id

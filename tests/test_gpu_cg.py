@@ -119,6 +119,41 @@ def test_early_iterates_match(fmt):
         assert err <= 1e-12, (k, err)
 
 
+@pytest.mark.parametrize("layout", ["rows", "slices"])
+def test_csr_layouts_in_iterations(monkeypatch, layout):
+    # both CSR product layouts inside the iteration graph (the default picks
+    # slices for FEM matrices)
+    monkeypatch.setenv("CGMI_CSR_LAYOUT", layout)
+    s = fem_cached("fem32x32x30")
+    arrs = formats_of(s.rowptr, s.col, s.val)[CSR]
+    xg, info, xo, oinfo = run_pair(CSR, arrs, s.b, label=f"fem32x32x30 layout={layout}")
+    check_contract(CSR, arrs, s.b, xg, info, xo, oinfo, strict_2norm=False)
+
+
+def test_early_iterates_4096_partials():
+    # 1.2M-row tridiagonal SPD matrix: the sliced product runs on 4096
+    # workgroups (several slices per wave) and the r update sums 4096 partials
+    n = 1_200_000
+    lens = np.full(n, 3)
+    lens[0] = lens[-1] = 2
+    ptr = np.zeros(n + 1, np.int32)
+    ptr[1:] = np.cumsum(lens)
+    i = np.repeat(np.arange(n), lens)
+    col = (i + np.arange(ptr[-1]) - ptr[i] - (i > 0)).astype(np.int32)
+    val = np.where(col == i, 2.5, -1.0)
+    b = W.uniform_vector(n, seed=33)
+    st, stats = cgmi.cg_analyze(CSR, n, ptr, col, val)
+    assert stats["csr_slices"] == 1 and stats["spmv_blocks"] == 4096
+    for k in (1, 5, 20):
+        with cgmi.Solver(CSR, ptr, col, val) as S:
+            xg, info = S.solve(to_dev(b), tol=0.0, maxit=k, check=False)
+        xo, oinfo, _ = oracle.cg(CSR, ptr, col, val, b, tol=0.0, maxit=k)
+        assert info["iters"] == oinfo["iters"] == k
+        err = np.linalg.norm(xg.cpu().numpy() - xo) / np.linalg.norm(xo)
+        say(f"   tridiagonal n={n}: {k} iterations, rel. difference {err:.2e}")
+        assert err <= 1e-12, (k, err)
+
+
 @pytest.mark.parametrize("fmt", [CSR, SYM, CSC])
 def test_nonzero_start(fmt):
     s = W.fem_p1_system(10, 9, 8, nu_iron=1e-2, seed=3)

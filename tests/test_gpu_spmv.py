@@ -110,13 +110,18 @@ def test_split_long_row_symcsr(monkeypatch):
     check_spmv(SYM, ptr, idx, val, W.uniform_vector(n, seed=13), label="arrow")
 
 
+@pytest.mark.parametrize("layout", ["rows", "slices"])
 @pytest.mark.parametrize("mean_len", [2, 6, 30, 120])
-def test_lane_widths(mean_len):
+def test_lane_widths(monkeypatch, mean_len, layout):
+    monkeypatch.setenv("CGMI_CSR_LAYOUT", layout)
     n = 1500
     ptr, col, val = W.random_sparse(n, density=mean_len / n, seed=mean_len)
     st, stats = cgmi.cg_analyze(CSR, n, ptr, col, val)
-    say(f"lanes={stats['lanes_per_line']}")
-    check_spmv(CSR, ptr, col, val, W.uniform_vector(n, seed=14), label=f"mean_len={mean_len}")
+    assert stats["csr_slices"] == (layout == "slices")
+    say(f"lanes={stats['lanes_per_line']} slices={stats['csr_slices']}")
+    y, yo = check_spmv(CSR, ptr, col, val, W.uniform_vector(n, seed=14), label=f"mean_len={mean_len}")
+    if layout == "slices":   # every row summed left to right by one lane
+        assert np.array_equal(y, yo)
 
 
 @pytest.mark.parametrize("fmt", [CSR, SYM, CSC])
@@ -176,10 +181,14 @@ def test_errors_without_fallback():
     assert st == cgmi.CG_ERR_NONFINITE and h is None
 
 
+@pytest.mark.parametrize("layout", ["auto", "rows", "slices"])
 @pytest.mark.parametrize("case", ["fem32x32x30", "fem100", "ragged"])
-def test_csr_bit_identical_to_oracle(case):
+def test_csr_bit_identical_to_oracle(monkeypatch, case, layout):
     # rows of <= 2048 entries with a mean of <= 32: the row-block kernel sums
-    # each row left to right from rounded products, exactly like the oracle
+    # each row left to right from rounded products, exactly like the oracle;
+    # the sliced layout does the same in registers (any row length)
+    if layout != "auto":
+        monkeypatch.setenv("CGMI_CSR_LAYOUT", layout)
     if case == "ragged":
         ptr, col, val = W.random_sparse(5000, density=0.003, seed=21, empty_rows=40, long_rows=2, long_len=1500)
     else:
@@ -187,7 +196,38 @@ def test_csr_bit_identical_to_oracle(case):
         ptr, col, val = s.rowptr, s.col, s.val
     st, stats = cgmi.cg_analyze(CSR, len(ptr) - 1, ptr, col, val)
     assert st == 0
+    say(f"layout={layout} slices={stats['csr_slices']} workgroups={stats['spmv_blocks']}")
     y, yo = check_spmv(CSR, ptr, col, val, W.uniform_vector(len(ptr) - 1, seed=22), label=f"bitwise {case}")
+    assert np.array_equal(y, yo)
+
+
+@pytest.mark.parametrize("n", [1, 63, 64, 65, 200, 4097])
+def test_csr_slices_ragged_shapes(monkeypatch, n):
+    # partial last slice, empty rows, one row far longer than the rest
+    monkeypatch.setenv("CGMI_CSR_LAYOUT", "slices")
+    ptr, col, val = W.random_sparse(n, density=min(1.0, 9.0 / n), seed=n, empty_rows=n // 7,
+                                    long_rows=1 if n > 1 else 0, long_len=min(n, 700))
+    st, stats = cgmi.cg_analyze(CSR, n, ptr, col, val)
+    assert st == 0 and stats["csr_slices"] == 1
+    y, yo = check_spmv(CSR, ptr, col, val, W.uniform_vector(n, seed=n + 1), label=f"slices n={n}")
+    assert np.array_equal(y, yo)
+
+
+def test_csr_slices_several_per_wave():
+    # more than 4 x 4096 slices: every workgroup's waves take several slices,
+    # and the product leaves 4096 dot partials
+    n = 1_200_000
+    ptr = np.zeros(n + 1, np.int32)
+    lens = np.full(n, 3)
+    lens[0] = lens[-1] = 2
+    ptr[1:] = np.cumsum(lens)
+    i = np.repeat(np.arange(n), lens)
+    off = np.arange(ptr[-1]) - ptr[i] - (i > 0)
+    col = (i + off).astype(np.int32)
+    val = np.where(col == i, 2.0, -1.0) + 1e-3 * W.uniform_vector(ptr[-1], seed=30)
+    st, stats = cgmi.cg_analyze(CSR, n, ptr, col, val)
+    assert st == 0 and stats["csr_slices"] == 1 and stats["spmv_blocks"] == 4096
+    y, yo = check_spmv(CSR, ptr, col, val, W.uniform_vector(n, seed=31), label="1.2M rows, 3 per row")
     assert np.array_equal(y, yo)
 
 

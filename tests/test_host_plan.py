@@ -65,7 +65,46 @@ def test_csr_plan_shape():
     assert st == 0
     assert stats["lanes_per_line"] == 16          # ~14.25 entries per row
     assert stats["colors"] == 0 and stats["slots"] == 0
-    assert 1 <= stats["spmv_blocks"] <= 2048 and 1 <= stats["vec_blocks"] <= 1024
+    assert 1 <= stats["spmv_blocks"] <= 4096 and 1 <= stats["vec_blocks"] <= 1024
+
+
+def _slice_positions(ptr):
+    # positions of the sliced layout: every 64-row slice padded to its longest row
+    lens = np.diff(np.asarray(ptr, dtype=np.int64))
+    ns = (lens.size + 63) // 64
+    full = np.zeros(ns * 64, dtype=np.int64)
+    full[:lens.size] = lens
+    return int(full.reshape(ns, 64).max(axis=1).sum()) * 64, ns
+
+
+def test_csr_layout_choice(monkeypatch):
+    CSR = cgmi.CG_FMT_CSR
+    # FEM rows differ little in length: sliced layout, padding within 12.5 %
+    s = W.fem_config("fem32x32x30")
+    st, stats = cgmi.cg_analyze(CSR, s.n, s.rowptr, s.col, s.val)
+    pos, ns = _slice_positions(s.rowptr)
+    assert st == 0 and stats["csr_slices"] == 1
+    assert s.nnz <= pos <= 1.125 * s.nnz
+    assert stats["plan_bytes"] == 4 * (ns + 1) + 16 * pos
+    assert stats["spmv_blocks"] == min((ns + 3) // 4, 4096)
+    # two 1500-entry rows among ~15-entry rows: padding too large, row blocks
+    ptr, col, val = W.random_sparse(5000, density=0.003, seed=21, empty_rows=40, long_rows=2, long_len=1500)
+    st, stats = cgmi.cg_analyze(CSR, 5000, ptr, col, val)
+    assert st == 0 and stats["csr_slices"] == 0 and stats["plan_bytes"] < 5000
+    # the knob forces either layout
+    monkeypatch.setenv("CGMI_CSR_LAYOUT", "slices")
+    st, stats = cgmi.cg_analyze(CSR, 5000, ptr, col, val)
+    pos, ns = _slice_positions(ptr)
+    assert st == 0 and stats["csr_slices"] == 1 and stats["plan_bytes"] == 4 * (ns + 1) + 16 * pos
+    monkeypatch.setenv("CGMI_CSR_LAYOUT", "rows")
+    st, stats = cgmi.cg_analyze(CSR, s.n, s.rowptr, s.col, s.val)
+    assert st == 0 and stats["csr_slices"] == 0
+    # other formats never use it
+    monkeypatch.delenv("CGMI_CSR_LAYOUT")
+    for fmt in (cgmi.CG_FMT_SYM_CSR, cgmi.CG_FMT_CSC):
+        arrs = W.upper_triangle(s.rowptr, s.col, s.val) if fmt == cgmi.CG_FMT_SYM_CSR else (s.rowptr, s.col, s.val)
+        st, stats = cgmi.cg_analyze(fmt, s.n, *arrs)
+        assert st == 0 and stats["csr_slices"] == 0
 
 
 def _expected_targets(fmt, ptr, idx, e0, e1, l0, l1):
