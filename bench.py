@@ -186,9 +186,12 @@ def main():
                                 spmv_colors=spmv[name]["colors"])
     # dominant product kernel: largest share of the step's time
     dom = max(solvers, key=lambda k: spmv[k]["us"] * per_format[k]["iters"])
-    kernel_name = {"csr": "k_spmv_csr_rows (CSR product)",
+    sliced = solvers[dom].stats()["slices"] == 1
+    kernel_name = {"csr": "k_spmv_slices (CSR product, 64-row slices)" if sliced else
+                          "k_spmv_csr_rows (CSR product, row blocks)",
                    "symcsr": "k_scatter_sums + k_scatter_gather (symmetric-CSR product)",
-                   "csc": "k_panel_rows + k_scatter_gather (CSC product on column panels)"}[dom]
+                   "csc": ("k_spmv_slices" if sliced else "k_panel_rows") +
+                          " + k_scatter_gather (CSC product on column panels)"}[dom]
     traffic = load_traffic(dom)
     roofline = dict(bound="hbm", achieved=round(spmv[dom]["GBps"], 1), peak=HBM_PEAK_GBPS, unit="GB/s",
                     frac=round(spmv[dom]["GBps"] / HBM_PEAK_GBPS, 4), traffic=traffic, kernel=kernel_name,

@@ -96,7 +96,8 @@ typedef struct {
     int32_t colors;          /* scatter formats: colour phases per product; CSR: 0 */
     int32_t scatter_blocks;  /* scatter formats: blocks of the plan (sizes of cg_analyze_export) */
     int32_t max_block_entries;
-    int32_t csr_slices;      /* CSR: 1 = sliced layout (64 rows per slice), 0 = row blocks / lanes per row */
+    int32_t slices;          /* 1 = sliced layout (CSR: 64-row slices; CSC: 64-slot slices;
+                                symmetric CSR: blocks stored k-th entry first) */
     int64_t slots;           /* scatter formats: total (block, target) write slots */
     int64_t plan_bytes;      /* device bytes of the plan beyond ptr / idx / vals */
 } cg_plan_stats;

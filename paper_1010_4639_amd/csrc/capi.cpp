@@ -167,7 +167,7 @@ int upload_all(cg_handle *h, const std::vector<int32_t> &ptr0, const std::vector
         m.csr_rbe = rbe;
         m.csr_nrb = (int)p.csr_rb.size() - 1;
     }
-    if (p.format == kCsr && p.csr_slices) {
+    if (p.slices) {
         int32_t *off, *col, *src;
         double *sv;
         if ((st = upload(h, &off, p.sl_off.data(), p.sl_off.size())) != CG_OK ||
@@ -175,8 +175,9 @@ int upload_all(cg_handle *h, const std::vector<int32_t> &ptr0, const std::vector
             (st = upload(h, &src, p.sl_src.data(), p.sl_src.size())) != CG_OK ||
             (st = dalloc(h, &sv, std::max<size_t>(p.sl_src.size(), 1))) != CG_OK)
             return st;
-        m.csr_slices = true;
-        m.csr_nslices = (int)p.sl_off.size() - 1;
+        m.slices = true;
+        m.sl_lines = (int)p.sl_lines;
+        m.nslices = (int)p.sl_off.size() - 1;
         m.sl_off = off;
         m.sl_col = col;
         m.sl_src = src;
@@ -207,15 +208,18 @@ int upload_all(cg_handle *h, const std::vector<int32_t> &ptr0, const std::vector
             for (int64_t q = fp; q < ns; ++q)
                 rsi[next[p.pn_slot_target[q]]++] = (int32_t)(q - fp);
         }
-        int32_t *cs, *sp, *stg, *pc, *src, *drsp, *drsi;
+        int32_t *cs = nullptr, *sp = nullptr, *stg, *pc = nullptr, *src = nullptr, *drsp, *drsi;
         uint8_t *dc0;
-        double *pv, *part;
-        if ((st = upload(h, &cs, p.pn_chunk_slot.data(), p.pn_chunk_slot.size())) != CG_OK ||
-            (st = upload(h, &sp, p.pn_slot_ptr.data(), p.pn_slot_ptr.size())) != CG_OK ||
-            (st = upload(h, &stg, p.pn_slot_target.data(), p.pn_slot_target.size())) != CG_OK ||
-            (st = upload(h, &pc, p.pn_col.data(), p.pn_col.size())) != CG_OK ||
-            (st = upload(h, &src, p.pn_src.data(), p.pn_src.size())) != CG_OK ||
-            (st = dalloc(h, &pv, p.pn_src.size())) != CG_OK || (st = dalloc(h, &part, (size_t)(ns - fp))) != CG_OK ||
+        double *pv = nullptr, *part;
+        if (!p.slices && // chunk kernel: slot pointers, chunks and the entries in panel order
+            ((st = upload(h, &cs, p.pn_chunk_slot.data(), p.pn_chunk_slot.size())) != CG_OK ||
+             (st = upload(h, &sp, p.pn_slot_ptr.data(), p.pn_slot_ptr.size())) != CG_OK ||
+             (st = upload(h, &pc, p.pn_col.data(), p.pn_col.size())) != CG_OK ||
+             (st = upload(h, &src, p.pn_src.data(), p.pn_src.size())) != CG_OK ||
+             (st = dalloc(h, &pv, p.pn_src.size())) != CG_OK))
+            return st;
+        if ((st = upload(h, &stg, p.pn_slot_target.data(), p.pn_slot_target.size())) != CG_OK ||
+            (st = dalloc(h, &part, (size_t)std::max<int64_t>(ns - fp, 1))) != CG_OK ||
             (st = upload(h, &drsp, rsp.data(), rsp.size())) != CG_OK ||
             (st = upload(h, &drsi, rsi.data(), rsi.size())) != CG_OK ||
             (st = upload(h, &dc0, c0.data(), c0.size())) != CG_OK)
@@ -234,7 +238,7 @@ int upload_all(cg_handle *h, const std::vector<int32_t> &ptr0, const std::vector
         m.rs_idx = drsi;
         m.has_c0 = dc0;
         m.scatter_wgs = p.scatter_wgs();
-        if (h->mixed && (st = dalloc(h, &m.pn_val32, p.pn_src.size())) != CG_OK)
+        if (h->mixed && !p.slices && (st = dalloc(h, &m.pn_val32, p.pn_src.size())) != CG_OK)
             return st;
     } else if (p.format != kCsr && n > 0) {
         // device arrays in colour order: the blocks of one colour, and their
@@ -292,7 +296,7 @@ int upload_all(cg_handle *h, const std::vector<int32_t> &ptr0, const std::vector
             (st = upload(h, &tg, otg.data(), otg.size())) != CG_OK ||
             (st = upload(h, &fl, ofl.data(), ofl.size())) != CG_OK ||
             (st = upload(h, &sg, osg.data(), osg.size())) != CG_OK ||
-            (st = upload(h, &tl, p.tl.data(), p.tl.size())) != CG_OK ||
+            (st = upload(h, &tl, (p.sym_slices ? p.ss_tl : p.tl).data(), p.tl.size())) != CG_OK ||
             (st = dalloc(h, &part, otg.size())) != CG_OK || (st = upload(h, &drsp, rsp.data(), rsp.size())) != CG_OK ||
             (st = upload(h, &drsi, rsi.data(), rsi.size())) != CG_OK ||
             (st = upload(h, &dc0, c0.data(), c0.size())) != CG_OK)
@@ -308,6 +312,32 @@ int upload_all(cg_handle *h, const std::vector<int32_t> &ptr0, const std::vector
         m.part = part;
         m.color_slot_off = cso;
         m.scatter_wgs = p.scatter_wgs();
+        if (p.sym_slices) {
+            // per device block (colour order): first position, entries per line
+            std::vector<int2> sb(nb);
+            for (int i = 0; i < nb; ++i) {
+                const ScatterBlock &src = p.blocks[p.phase_blocks[i]];
+                const int32_t q0 = p.ss_pos[src.id], q1 = p.ss_pos[src.id + 1];
+                sb[i] = make_int2(q0, (q1 - q0) / (src.line1 - src.line0));
+            }
+            int2 *dsb;
+            int32_t *sidx, *ssrc;
+            double *sv;
+            const size_t np = std::max<size_t>(p.ss_src.size(), 1);
+            if ((st = upload(h, &dsb, sb.data(), sb.size())) != CG_OK ||
+                (st = upload(h, &sidx, p.ss_idx.data(), p.ss_idx.size())) != CG_OK ||
+                (st = upload(h, &ssrc, p.ss_src.data(), p.ss_src.size())) != CG_OK ||
+                (st = dalloc(h, &sv, np)) != CG_OK)
+                return st;
+            m.sym_slices = true;
+            m.ss_blk = dsb;
+            m.ss_idx = sidx;
+            m.ss_src = ssrc;
+            m.ss_val = sv;
+            m.ss_positions = (int64_t)p.ss_src.size();
+            if (h->mixed && (st = dalloc(h, &m.ss_val32, np)) != CG_OK)
+                return st;
+        }
     }
     const size_t nv = (size_t)std::max<int64_t>(n, 1);
     if ((st = dalloc(h, &h->r, nv)) != CG_OK || (st = dalloc(h, &h->p, nv)) != CG_OK ||
@@ -351,7 +381,7 @@ void fill_stats(const Plan &p, cg_plan_stats *s)
     s->vec_blocks = p.vec_blocks;
     s->colors = p.ncolors;
     s->max_block_entries = p.max_entries;
-    s->csr_slices = p.csr_slices ? 1 : 0;
+    s->slices = p.slices || p.sym_slices ? 1 : 0;
     s->slots = p.panel ? (int64_t)p.pn_slot_target.size() : (int64_t)p.slot_target.size();
     s->plan_bytes = p.device_bytes();
 }
@@ -485,19 +515,23 @@ int refresh_values(cg_handle *h)
 {
     DevMatrix &m = h->dm;
     const int64_t nnz = h->plan.nnz;
-    if (m.panel)
+    if (m.panel && !m.slices)
         launch_permute(nnz, m.val, m.pn_src, m.pn_val, h->stream);
-    if (m.csr_slices)
+    if (m.slices)
         launch_permute((int64_t)h->plan.sl_src.size(), m.val, m.sl_src, m.sl_val, h->stream);
+    if (m.sym_slices)
+        launch_permute(m.ss_positions, m.val, m.ss_src, m.ss_val, h->stream);
     HIP_TRY(h, hipGetLastError());
     if (h->mixed && m.n > 0) {
         const int st = mixed_rescale(h);
         if (st != CG_OK)
             return st;
-        if (m.panel)
+        if (m.panel && !m.slices)
             launch_permute(nnz, m.val32, m.pn_src, m.pn_val32, h->stream);
-        if (m.csr_slices)
+        if (m.slices)
             launch_permute((int64_t)h->plan.sl_src.size(), m.val32, m.sl_src, m.sl_val32, h->stream);
+        if (m.sym_slices)
+            launch_permute(m.ss_positions, m.val32, m.ss_src, m.ss_val32, h->stream);
         HIP_TRY(h, hipGetLastError());
     }
     return CG_OK;

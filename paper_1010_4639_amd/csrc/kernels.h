@@ -55,8 +55,8 @@ struct DevMatrix {
     int csr_nrb = 0;
     const int32_t *csr_rb = nullptr;
     const int2 *csr_rbe = nullptr;       // per row-block boundary: {first row, first entry}
-    bool csr_slices = false;             // sliced layout (plan.h)
-    int csr_nslices = 0;
+    bool slices = false;                 // sliced layout of CSR rows / CSC panel slots (plan.h)
+    int sl_lines = 0, nslices = 0;
     const int32_t *sl_off = nullptr, *sl_col = nullptr, *sl_src = nullptr;
     double *sl_val = nullptr;            // values at the slice positions (0 at padding)
     float *sl_val32 = nullptr;           // mixed precision: val32 at the slice positions
@@ -73,7 +73,14 @@ struct DevMatrix {
     const int32_t *slot_target = nullptr;
     const uint8_t *slot_flag = nullptr;
     const uint16_t *seg = nullptr;
-    const uint16_t *tl = nullptr;
+    const uint16_t *tl = nullptr;          // sliced blocks: local positions
+    // symmetric CSR, sliced blocks (plan.h)
+    bool sym_slices = false;
+    const int2 *ss_blk = nullptr;          // per device block: {first position, entries per line}
+    const int32_t *ss_idx = nullptr, *ss_src = nullptr;
+    double *ss_val = nullptr;              // values at the positions (0 at padding)
+    float *ss_val32 = nullptr;             // mixed precision: val32 at the positions
+    int64_t ss_positions = 0;
     // CSC column panels (nblocks = chunks, scatter_wgs = their workgroups)
     bool panel = false;
     bool pn_gather = false;               // some row has parked sums or no writer
@@ -84,7 +91,7 @@ struct DevMatrix {
     int pn_first_parked = 0;
     // vectors
     int vec_blocks = 0, vec_chunk = 0;
-    int spmv_blocks() const { return format == kCsr ? csr_blocks : scatter_wgs; }
+    int spmv_blocks() const { return format == kCsr || slices ? csr_blocks : scatter_wgs; }
     // the product ends with a row pass (parked slot sums, rows with no writer)
     bool row_pass() const { return panel ? pn_gather : (format == kSymCsr && ncolors > 1); }
 };

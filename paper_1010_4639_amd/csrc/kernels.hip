@@ -206,23 +206,27 @@ __global__ __launch_bounds__(kBlock) void k_spmv_csr_rows(int nrb, const int2 *_
         sig_part[wg] = sig;
 }
 
-// ------------------------------------------------- CSR slices
-// Sliced layout (plan.h): one wavefront per slice of 64 rows, lane l owns row
-// 64 s + l and walks its entries left to right, U positions per round (all
-// index / value loads of a round first -- coalesced, non-temporal -- then the
-// U gathers of x, then the sums).  For a stencil-like matrix the k-th entries
-// of neighbouring rows are neighbouring columns, so each gather touches a few
-// cache lines instead of one per lane.  Each row is summed as a + v x with
-// the product rounded before the add (no fused multiply-add), as the row-block
-// kernel's LDS products are: y is bit-identical to the serial row-by-row
-// loop.  With more slices than 4 x kMaxSliceWgs each wave takes several
-// consecutive slices of its workgroup's range.  Fused epilogue: partial of x'y.
-template <class VT, class PT>
-__global__ __launch_bounds__(kBlock) void k_spmv_csr_slices(int n, int ns, const int32_t *__restrict__ off,
-                                                            const int32_t *__restrict__ col,
-                                                            const VT *__restrict__ val, const PT *__restrict__ x,
-                                                            double *__restrict__ y, double *__restrict__ sig_part,
-                                                            DevState *st)
+// ------------------------------------------------- slices
+// Sliced layout (plan.h): one wavefront per slice of 64 lines, lane l owns
+// line 64 s + l and walks its entries left to right, U positions per round
+// (all index / value loads of a round first -- coalesced, non-temporal --
+// then the U gathers of x, then the sums).  For a stencil-like matrix the
+// k-th entries of neighbouring lines are neighbouring columns, so each gather
+// touches a few cache lines instead of one per lane.  Each line is summed as
+// a + v x with the product rounded before the add (no fused multiply-add), as
+// the row-block kernels' LDS products are: a CSR row is bit-identical to the
+// serial row-by-row loop.  With more slices than 4 x kMaxSliceWgs each wave
+// takes several consecutive slices of its workgroup's range.
+// PANEL = false: lines are the rows of y.  PANEL = true: lines are the CSC
+// panel slots; a colour-0 slot stores y[target], a colour-1 slot parks its
+// sum for the row pass.  Fused epilogue: partial of x'y (linear in the line
+// sums, so x_target * sum per line).
+template <bool PANEL, class VT, class PT>
+__global__ __launch_bounds__(kBlock) void k_spmv_slices(int nl, int ns, const int32_t *__restrict__ off,
+                                                        const int32_t *__restrict__ col, const VT *__restrict__ val,
+                                                        const PT *__restrict__ x, double *__restrict__ y,
+                                                        const int32_t *__restrict__ target, double *__restrict__ part,
+                                                        int first_parked, double *__restrict__ sig_part, DevState *st)
 {
 #pragma clang fp contract(off)
     constexpr int U = 8;
@@ -236,6 +240,10 @@ __global__ __launch_bounds__(kBlock) void k_spmv_csr_slices(int n, int ns, const
     double sig = 0.0;
     for (int sl = s0 + (int)(threadIdx.x >> 6); sl < s1; sl += kWaves) {
         const int e0 = off[sl], len = (off[sl + 1] - e0) / kSliceRows;
+        const int l = sl * kSliceRows + lane;
+        int tg = l;
+        if (PANEL)
+            tg = l < nl ? __builtin_nontemporal_load(target + l) : -1;
         double a = 0.0;
         for (int k0 = 0; k0 < len; k0 += U) {
             int c[U];
@@ -255,10 +263,12 @@ __global__ __launch_bounds__(kBlock) void k_spmv_csr_slices(int n, int ns, const
                 if (c[u] >= 0)
                     a = a + v[u] * xv[u];
         }
-        const int r = sl * kSliceRows + lane;
-        if (r < n) {
-            y[r] = a;
-            sig = fma((double)x[r], a, sig);
+        if (l < nl) {
+            if (!PANEL || l < first_parked)
+                y[tg] = a;
+            else
+                part[l - first_parked] = a;
+            sig = fma((double)x[tg], a, sig);
         }
     }
     sig = block_sum(sig, red);
@@ -478,6 +488,103 @@ __global__ __launch_bounds__(kBlock) void k_scatter_sums(
                     sp[e] = v[m] * xl[l];
             }
         }
+        __syncthreads();
+        // ---- slot sums
+        const bool first_colour = bk.pad == 0;
+#pragma unroll
+        for (int u = 0; u < SU; ++u) {
+            if (tg[u] < 0)
+                continue;
+            const int s = t + u * kBlock;
+            double a = s < nl ? own : 0.0; // s < nl <= 256 implies u == 0 and s == t
+            for (int i = lo[u]; i < hi[u]; ++i)
+                a += sp[tv[i]];
+            if (first_colour)
+                y[tg[u]] = a;
+            else
+                part[bk.slot0 + s] = a;
+            sig = fma(xt[u], a, sig);
+        }
+        __syncthreads(); // LDS is reused by the next block
+    }
+    sig = block_sum(sig, red);
+    if (t == 0)
+        sig_part[wg] = sig;
+}
+
+// Sliced blocks of the symmetric format: the same blocks, slots, colours and
+// contribution lists as k_scatter_sums, with each block's entries stored
+// k-th-entry-major (position k * nl + l for line l), so thread l loads line
+// l's entries itself (coalesced over l, and so are the gathers of x for a
+// stencil-like matrix), sums its own row in registers left to right from
+// rounded products (the same bits as the LDS sum), and parks only the mirror
+// products a_e x_l in LDS, where the slot sums read them through the
+// contribution list (local positions).  Two barriers per block, no line map.
+template <int SU, class VT, class PT>
+__global__ __launch_bounds__(kBlock) void k_scatter_slices(
+    const int32_t *__restrict__ sidx, const VT *__restrict__ sval, const int2 *__restrict__ sblk,
+    const PT *__restrict__ x, double *__restrict__ y, double *__restrict__ part, double *__restrict__ sig_part,
+    const ScatterBlock *__restrict__ blocks, int nblocks, const int32_t *__restrict__ slot_target,
+    const uint16_t *__restrict__ seg, const uint16_t *__restrict__ tl, DevState *st)
+{
+#pragma clang fp contract(off)
+    constexpr int E = kStreamPerThread;
+    __shared__ double sp[kMaxScatterEntries];
+    __shared__ uint16_t tv[kMaxScatterEntries];
+    __shared__ double red[kWaves];
+    const int wg = xcd_remap(blockIdx.x, gridDim.x);
+    if (st != nullptr && !iter_gate(st))
+        return;
+    const int t = threadIdx.x;
+    const int b0 = (int)((int64_t)wg * nblocks / gridDim.x);
+    const int b1 = (int)((int64_t)(wg + 1) * nblocks / gridDim.x);
+    double sig = 0.0;
+    for (int b = b0; b < b1; ++b) {
+        const ScatterBlock bk = blocks[b];
+        const int2 sb = sblk[b];
+        const int nl = bk.line1 - bk.line0, L = sb.y;
+        const bool mine = t < nl;
+        // ---- independent loads
+        for (int i = t; i < bk.ntl; i += kBlock)
+            tv[i] = tl[bk.tl0 + i];
+        int c[E];
+        double v[E];
+#pragma unroll
+        for (int m = 0; m < E; ++m) {
+            const bool ok = mine && m < L;
+            const int q = sb.x + m * nl + t;
+            c[m] = ok ? __builtin_nontemporal_load(sidx + q) : -1;
+            v[m] = ok ? (double)__builtin_nontemporal_load(sval + q) : 0.0;
+        }
+        const double xo = mine ? (double)x[bk.line0 + t] : 0.0;
+        int tg[SU], lo[SU], hi[SU];
+        const uint16_t *sg = seg + bk.slot0 + bk.id;
+#pragma unroll
+        for (int u = 0; u < SU; ++u) {
+            const int s = t + u * kBlock;
+            const bool ok = s < bk.nslots;
+            tg[u] = ok ? slot_target[bk.slot0 + s] : -1;
+            lo[u] = ok ? sg[s] : 0;
+            hi[u] = ok ? sg[s + 1] : 0;
+        }
+        // ---- gathers
+        double xg[E];
+#pragma unroll
+        for (int m = 0; m < E; ++m)
+            xg[m] = c[m] >= 0 ? (double)x[c[m]] : 0.0;
+        double xt[SU];
+#pragma unroll
+        for (int u = 0; u < SU; ++u)
+            xt[u] = tg[u] >= 0 ? (double)x[tg[u]] : 0.0;
+        // ---- own row in registers; mirror products (not the diagonal) to LDS
+        double own = 0.0;
+#pragma unroll
+        for (int m = 0; m < E; ++m)
+            if (c[m] >= 0) {
+                own = own + v[m] * xg[m];
+                if (c[m] != bk.line0 + t)
+                    sp[m * nl + t] = v[m] * xo;
+            }
         __syncthreads();
         // ---- slot sums
         const bool first_colour = bk.pad == 0;
@@ -899,11 +1006,37 @@ void scatter_launch(const DevMatrix &m, const VT *val, const PT *x, double *y, d
                            m.rs_idx, m.has_c0, m.part, y, c.st);
 }
 
+inline const double *sym_slice_vals(const DevMatrix &m, const double *) { return m.ss_val; }
+inline const float *sym_slice_vals(const DevMatrix &m, const float *) { return m.ss_val32; }
+
+template <int SU, class VT, class PT>
+void scatter_slices_launch(const DevMatrix &m, const VT *val, const PT *x, double *y, double *sig, const IterCtx &c,
+                           hipStream_t s)
+{
+    hipLaunchKernelGGL((k_scatter_slices<SU, VT, PT>), dim3(m.scatter_wgs), dim3(kBlock), 0, s, m.ss_idx,
+                       sym_slice_vals(m, val), m.ss_blk, x, y, m.part, sig, m.blocks, m.nblocks, m.slot_target,
+                       m.seg, m.tl, c.st);
+    if (m.ncolors > 1 && !c.defer_rows)
+        hipLaunchKernelGGL(k_scatter_gather, dim3((m.n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, m.n, m.rs_ptr,
+                           m.rs_idx, m.has_c0, m.part, y, c.st);
+}
+
 template <int E, class VT, class PT>
 void scatter_dispatch_su(const DevMatrix &m, const VT *val, const PT *x, double *y, double *sig, const IterCtx &c,
                          hipStream_t s)
 {
     // write slots held in registers: SU per thread must cover the largest block
+    if (m.sym_slices) {
+        if (m.max_slots <= 2 * kBlock)
+            scatter_slices_launch<2>(m, val, x, y, sig, c, s);
+        else if (m.max_slots <= 4 * kBlock)
+            scatter_slices_launch<4>(m, val, x, y, sig, c, s);
+        else if (m.max_slots <= 6 * kBlock)
+            scatter_slices_launch<6>(m, val, x, y, sig, c, s);
+        else
+            scatter_slices_launch<9>(m, val, x, y, sig, c, s);
+        return;
+    }
     if (m.max_slots <= 2 * kBlock)
         scatter_launch<2, E>(m, val, x, y, sig, c, s);
     else if (m.max_slots <= 4 * kBlock)
@@ -936,20 +1069,29 @@ void spmv_any(const DevMatrix &m, const VT *val, const PT *x, double *y, double 
 {
     if (m.n == 0)
         return;
+    if (m.slices) {
+        if (m.panel)
+            hipLaunchKernelGGL((k_spmv_slices<true, VT, PT>), dim3(m.csr_blocks), dim3(kBlock), 0, s, m.sl_lines,
+                               m.nslices, m.sl_off, m.sl_col, slice_vals(m, val), x, y, m.pn_slot_target, m.part,
+                               m.pn_first_parked, sig_part, c.st);
+        else
+            hipLaunchKernelGGL((k_spmv_slices<false, VT, PT>), dim3(m.csr_blocks), dim3(kBlock), 0, s, m.sl_lines,
+                               m.nslices, m.sl_off, m.sl_col, slice_vals(m, val), x, y, nullptr, nullptr, 0,
+                               sig_part, c.st);
+    } else if (m.panel && m.nblocks > 0) {
+        hipLaunchKernelGGL((k_panel_rows<VT, PT>), dim3(m.scatter_wgs), dim3(kBlock), 0, s, m.nblocks,
+                           m.pn_chunk_slot, m.pn_slot_ptr, m.pn_slot_target, m.pn_col, panel_vals(m, val), x, y,
+                           m.part, m.pn_first_parked, sig_part, c.st);
+    }
     if (m.panel) {
-        if (m.nblocks > 0)
-            hipLaunchKernelGGL((k_panel_rows<VT, PT>), dim3(m.scatter_wgs), dim3(kBlock), 0, s, m.nblocks,
-                               m.pn_chunk_slot, m.pn_slot_ptr, m.pn_slot_target, m.pn_col, panel_vals(m, val), x, y,
-                               m.part, m.pn_first_parked, sig_part, c.st);
         if (m.pn_gather && !c.defer_rows)
             hipLaunchKernelGGL(k_scatter_gather, dim3((m.n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, m.n,
                                m.rs_ptr, m.rs_idx, m.has_c0, m.part, y, c.st);
         return;
     }
-    if (m.format == kCsr && m.csr_slices) {
-        hipLaunchKernelGGL((k_spmv_csr_slices<VT, PT>), dim3(m.csr_blocks), dim3(kBlock), 0, s, m.n, m.csr_nslices,
-                           m.sl_off, m.sl_col, slice_vals(m, val), x, y, sig_part, c.st);
-    } else if (m.format == kCsr && m.csr_stream) {
+    if (m.slices)
+        return;
+    if (m.format == kCsr && m.csr_stream) {
         hipLaunchKernelGGL((k_spmv_csr_rows<VT, PT>), dim3(m.csr_blocks), dim3(kBlock), 0, s, m.csr_nrb, m.csr_rbe,
                            m.ptr, m.idx, val, x, y, sig_part, c.st);
     } else if (m.format == kCsr) {
@@ -981,20 +1123,26 @@ void launch_update_r(const DevMatrix &m, double *r, const double *q, DevState *s
                      double *rho_part, hipStream_t s, bool rows_deferred)
 {
     static_assert(kMaxSliceWgs <= 2 * kPartPerThread * kBlock, "slice partials fit twice the registers");
+    // slices: up to kMaxSliceWgs dot partials
+    const bool wide = m.spmv_blocks() > kPartPerThread * kBlock;
+    RowPass g;
     if (rows_deferred && m.row_pass()) {
-        RowPass g;
         g.rs_ptr = m.rs_ptr;
         g.rs_idx = m.rs_idx;
         g.has_c0 = m.has_c0;
         g.part = m.part;
-        hipLaunchKernelGGL((k_update_r<true, kPartPerThread>), dim3(m.vec_blocks), dim3(kBlock), 0, s, m.n,
-                           m.vec_chunk, r, q, st, sig_part, m.spmv_blocks(), rho_part, g);
-    } else if (m.spmv_blocks() > kPartPerThread * kBlock) { // CSR slices: up to kMaxSliceWgs partials
+        if (wide)
+            hipLaunchKernelGGL((k_update_r<true, 2 * kPartPerThread>), dim3(m.vec_blocks), dim3(kBlock), 0, s, m.n,
+                               m.vec_chunk, r, q, st, sig_part, m.spmv_blocks(), rho_part, g);
+        else
+            hipLaunchKernelGGL((k_update_r<true, kPartPerThread>), dim3(m.vec_blocks), dim3(kBlock), 0, s, m.n,
+                               m.vec_chunk, r, q, st, sig_part, m.spmv_blocks(), rho_part, g);
+    } else if (wide) {
         hipLaunchKernelGGL((k_update_r<false, 2 * kPartPerThread>), dim3(m.vec_blocks), dim3(kBlock), 0, s, m.n,
-                           m.vec_chunk, r, q, st, sig_part, m.spmv_blocks(), rho_part, RowPass{});
+                           m.vec_chunk, r, q, st, sig_part, m.spmv_blocks(), rho_part, g);
     } else {
         hipLaunchKernelGGL((k_update_r<false, kPartPerThread>), dim3(m.vec_blocks), dim3(kBlock), 0, s, m.n,
-                           m.vec_chunk, r, q, st, sig_part, m.spmv_blocks(), rho_part, RowPass{});
+                           m.vec_chunk, r, q, st, sig_part, m.spmv_blocks(), rho_part, g);
     }
 }
 

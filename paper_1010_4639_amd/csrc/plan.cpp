@@ -12,15 +12,22 @@ namespace cgmi {
 
 int64_t Plan::device_bytes() const
 {
-    if (format == kCsr) // row-block starts; slices: offsets + entry source, column, value per position
-        return (int64_t)csr_rb.size() * 4 + (int64_t)sl_off.size() * 4 + (int64_t)sl_src.size() * (4 + 4 + 8);
+    // slices: offsets + entry source, column, value per position
+    const int64_t sl = (int64_t)sl_off.size() * 4 + (int64_t)sl_src.size() * (4 + 4 + 8);
+    if (format == kCsr) // row-block starts or slices
+        return (int64_t)csr_rb.size() * 4 + sl;
+    if (panel && slices) // slices; slot target; parked sums; row lists
+        return sl + (int64_t)pn_slot_target.size() * 4 + (int64_t)(pn_slot_target.size() - pn_first_parked) * 8 +
+               (int64_t)(pn_slot_target.size() - pn_first_parked) * 4 + (n + 1) * 4 + n;
     if (panel) // entry source + column + reordered value; slot target / pointer / parked sum; row lists
         return nnz * (4 + 4 + 8) + (int64_t)pn_slot_target.size() * (4 + 4 + 8 + 4) +
                (int64_t)pn_chunk_slot.size() * 8 + n * 5;
     // descriptors, slot target / flag / segment offsets, contributions, parked
-    // sums and their per-row index (upper bounds: every slot counted)
+    // sums and their per-row index (upper bounds: every slot counted); sliced
+    // blocks: positions (source, column, value) and their block offsets
     return (int64_t)blocks.size() * sizeof(ScatterBlock) + (int64_t)slot_target.size() * (4 + 1 + 8 + 4) +
-           (int64_t)seg.size() * 2 + (int64_t)tl.size() * 2 + n * 5;
+           (int64_t)seg.size() * 2 + (int64_t)tl.size() * 2 + n * 5 + (int64_t)ss_pos.size() * 8 +
+           (int64_t)ss_src.size() * (4 + 4 + 8);
 }
 
 int lanes_for_mean_length(double mean_len)
@@ -185,34 +192,39 @@ static void plan_vectors(Plan &p)
     p.vec_chunk = (int)((n + g - 1) / g);
 }
 
-// CSR slices (see plan.h).  mode: 0 = when the padding is small and rows are
-// short, 1 = whenever the padded size fits 32-bit positions.
-static bool plan_slices(Plan &p, const int32_t *ptr, const int32_t *idx, int mode)
+// Slices (see plan.h) over `nl` lines whose entries are seg_ptr[l] ..
+// seg_ptr[l + 1] - 1, with columns seg_col and caller entries seg_src (null:
+// the position itself).  mode: 0 = when lines are short and the padding is
+// small, 1 = whenever the padded size fits 32-bit positions.
+static bool plan_slices(Plan &p, int64_t nl, const int32_t *seg_ptr, const int32_t *seg_col, const int32_t *seg_src,
+                        int mode)
 {
-    const int64_t n = p.n, nnz = p.nnz;
-    const int64_t ns = (n + kSliceRows - 1) / kSliceRows;
+    const int64_t nnz = nl > 0 ? seg_ptr[nl] : 0;
+    const int64_t ns = (nl + kSliceRows - 1) / kSliceRows;
     std::vector<int64_t> off((size_t)ns + 1, 0);
     for (int64_t s = 0; s < ns; ++s) {
         int64_t w = 0;
-        for (int64_t r = s * kSliceRows; r < std::min(n, (s + 1) * kSliceRows); ++r)
-            w = std::max<int64_t>(w, (int64_t)ptr[r + 1] - ptr[r]);
+        for (int64_t r = s * kSliceRows; r < std::min(nl, (s + 1) * kSliceRows); ++r)
+            w = std::max<int64_t>(w, (int64_t)seg_ptr[r + 1] - seg_ptr[r]);
         off[s + 1] = off[s] + w * kSliceRows;
     }
     const int64_t padded = off[ns];
-    if (padded > INT32_MAX)
+    if (padded > INT32_MAX || nl > INT32_MAX)
         return false;
-    if (mode == 0 && ((double)nnz / (double)n > kStreamMaxMeanRow || (double)(padded - nnz) > kSliceMaxPadding * nnz))
+    if (mode == 0 && (nl == 0 || (double)nnz / (double)nl > kStreamMaxMeanRow ||
+                      (double)(padded - nnz) > kSliceMaxPadding * nnz))
         return false;
-    p.csr_slices = true;
+    p.slices = true;
+    p.sl_lines = nl;
     p.sl_off.assign(off.begin(), off.end());
     p.sl_src.assign((size_t)padded, -1);
     p.sl_col.assign((size_t)padded, -1);
-    for (int64_t r = 0; r < n; ++r) {
+    for (int64_t r = 0; r < nl; ++r) {
         const int64_t base = off[r / kSliceRows] + r % kSliceRows;
-        for (int64_t k = ptr[r]; k < ptr[r + 1]; ++k) {
-            const int64_t q = base + (k - ptr[r]) * kSliceRows;
-            p.sl_src[q] = (int32_t)k;
-            p.sl_col[q] = idx[k];
+        for (int64_t k = seg_ptr[r]; k < seg_ptr[r + 1]; ++k) {
+            const int64_t q = base + (k - seg_ptr[r]) * kSliceRows;
+            p.sl_src[q] = seg_src ? seg_src[k] : (int32_t)k;
+            p.sl_col[q] = seg_col[k];
         }
     }
     // one slice per wavefront up to kMaxSliceWgs workgroups, then each wave
@@ -223,16 +235,22 @@ static bool plan_slices(Plan &p, const int32_t *ptr, const int32_t *idx, int mod
     return true;
 }
 
+// experiments: CGMI_ROW_LAYOUT = rows (CSR row blocks / lanes per row, CSC
+// panel chunks) or slices (the sliced layout whatever its padding)
+static int slice_mode()
+{
+    const char *e = std::getenv("CGMI_ROW_LAYOUT");
+    if (!e)
+        return 0;
+    return std::strcmp(e, "slices") == 0 ? 1 : std::strcmp(e, "rows") == 0 ? -1 : 0;
+}
+
 static void plan_csr(Plan &p, const int32_t *ptr, const int32_t *idx)
 {
     const int64_t n = p.n;
     const double mean = (double)p.nnz / (double)n;
-    // experiments: CGMI_CSR_LAYOUT = rows (row blocks / lanes per row) or
-    // slices (sliced layout whatever its padding)
-    int mode = 0;
-    if (const char *e = std::getenv("CGMI_CSR_LAYOUT"))
-        mode = std::strcmp(e, "slices") == 0 ? 1 : std::strcmp(e, "rows") == 0 ? -1 : 0;
-    if (mode >= 0 && plan_slices(p, ptr, idx, mode))
+    const int mode = slice_mode();
+    if (mode >= 0 && plan_slices(p, n, ptr, idx, nullptr, mode))
         return;
     if (mean <= kStreamMaxMeanRow) {
         // row blocks: <= `be` entries (<= kStreamEntries) and <= kStreamRows
@@ -356,6 +374,9 @@ static int plan_panels(Plan &p, const int32_t *ptr, const int32_t *idx, std::str
                                                          p.pn_slot_ptr[p.pn_chunk_slot[c]]);
     p.max_slots = kPanelChunkSlots;
     p.max_lines = 0;
+    const int mode = slice_mode();
+    if (mode >= 0)
+        plan_slices(p, ns, p.pn_slot_ptr.data(), p.pn_col.data(), p.pn_src.data(), mode);
     return CG_OK;
 }
 
@@ -557,6 +578,57 @@ static int plan_scatter(Plan &p, const int32_t *ptr, const int32_t *idx, int tar
     return CG_OK;
 }
 
+// Symmetric CSR, sliced blocks (plan.h): every block keeps its lines and
+// slots; only the order of its entries changes (k-th entries of its lines
+// contiguous), so that thread l holds line l's entries in registers.  Taken
+// when no line of any block has more than kStreamPerThread entries (and, by
+// default, the padding stays small).
+static void plan_sym_slices(Plan &p, const int32_t *ptr, const int32_t *idx, int mode)
+{
+    if (p.format != kSymCsr || mode < 0 || p.nblocks == 0)
+        return;
+    const int nb = p.nblocks;
+    std::vector<int32_t> pos((size_t)nb + 1, 0);
+    int64_t total = 0;
+    for (int b = 0; b < nb; ++b) {
+        const ScatterBlock &bk = p.blocks[b];
+        const int64_t nl = bk.line1 - bk.line0;
+        int64_t L = 0;
+        for (int64_t l = bk.line0; l < bk.line1; ++l)
+            L = std::max<int64_t>(L, std::min<int64_t>(ptr[l + 1], bk.k1) - std::max<int64_t>(ptr[l], bk.k0));
+        if (L > kStreamPerThread || nl > kBlock)
+            return;
+        total += nl * L;
+        if (total > INT32_MAX)
+            return;
+        pos[b + 1] = (int32_t)total;
+    }
+    if (mode == 0 && (double)(total - p.nnz) > kSliceMaxPadding * (double)p.nnz)
+        return;
+    p.ss_pos = pos;
+    p.ss_src.assign((size_t)total, -1);
+    p.ss_idx.assign((size_t)total, -1);
+    p.ss_tl = p.tl;
+    std::vector<uint16_t> local;
+    for (int b = 0; b < nb; ++b) {
+        const ScatterBlock &bk = p.blocks[b];
+        const int64_t nl = bk.line1 - bk.line0;
+        local.assign((size_t)(bk.k1 - bk.k0), 0);
+        for (int64_t l = bk.line0; l < bk.line1; ++l) {
+            const int64_t e0 = std::max<int64_t>(ptr[l], bk.k0), e1 = std::min<int64_t>(ptr[l + 1], bk.k1);
+            for (int64_t e = e0; e < e1; ++e) {
+                const int64_t lp = (e - e0) * nl + (l - bk.line0);
+                p.ss_src[pos[b] + lp] = (int32_t)e;
+                p.ss_idx[pos[b] + lp] = idx[e];
+                local[e - bk.k0] = (uint16_t)lp;
+            }
+        }
+        for (int32_t i = bk.tl0; i < bk.tl0 + bk.ntl; ++i)
+            p.ss_tl[i] = local[p.tl[i]];
+    }
+    p.sym_slices = true;
+}
+
 int build_plan(int fmt, int64_t n, const int32_t *ptr0, const int32_t *idx0, int target_entries, Plan &p,
                std::string &err)
 {
@@ -578,7 +650,10 @@ int build_plan(int fmt, int64_t n, const int32_t *ptr0, const int32_t *idx0, int
     if (target_entries <= 0)
         target_entries = (int)block_entries(p.nnz, 512);
     target_entries = std::min(target_entries, kMaxScatterEntries);
-    return plan_scatter(p, ptr0, idx0, target_entries, err);
+    const int st = plan_scatter(p, ptr0, idx0, target_entries, err);
+    if (st == CG_OK)
+        plan_sym_slices(p, ptr0, idx0, slice_mode());
+    return st;
 }
 
 } // namespace cgmi

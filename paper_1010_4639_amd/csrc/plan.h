@@ -26,14 +26,15 @@
 // two-dimensional blocking of compressed-sparse-blocks storage applied to
 // the transpose product: column blocks for the scatter, row order inside.
 //
-// CSR slices.  Rows are grouped in slices of 64 consecutive rows, one per
-// wavefront lane, and a slice stores the k-th entry of each of its rows
-// contiguously (positions off + 64 k + lane; rows shorter than the slice's
-// longest are padded with source -1).  This is the sliced ELLPACK layout
-// (SELL-C-sigma, Kreutzer et al. 2014) with C = 64 and no row sorting: for a
-// stencil-like matrix the lanes of one load read neighbouring x entries, so
-// the gather of x becomes a near-contiguous load.  Chosen when the padding
-// stays small; each row is still summed left to right by one lane.
+// Slices.  Rows (CSR) or write slots (CSC panels: one (panel, row) segment
+// each) are grouped in slices of 64 consecutive lines, one per wavefront
+// lane, and a slice stores the k-th entry of each of its lines contiguously
+// (positions off + 64 k + lane; lines shorter than the slice's longest are
+// padded with source -1).  This is the sliced ELLPACK layout (SELL-C-sigma,
+// Kreutzer et al. 2014) with C = 64 and no sorting: for a stencil-like matrix
+// the lanes of one load read neighbouring x entries, so the gather of x
+// becomes a near-contiguous load.  Chosen when the padding stays small; each
+// line is still summed left to right by one lane.
 #pragma once
 
 #include <cstdint>
@@ -53,9 +54,9 @@ constexpr int kStreamPerThread = 8;                    // CSR row-block kernel: 
 constexpr int kStreamEntries = kBlock * kStreamPerThread; // entries per CSR row block
 constexpr int kStreamRows = kBlock;                    // rows per CSR row block (one thread each)
 constexpr double kStreamMaxMeanRow = 32.0;             // longer mean rows use lanes-per-row
-constexpr int kSliceRows = 64;          // CSR slices: rows per slice (one wavefront, a row per lane)
+constexpr int kSliceRows = 64;          // slices: lines per slice (one wavefront, a line per lane)
 constexpr int kWavesPerBlock = kBlock / kSliceRows;
-constexpr int kMaxSliceWgs = 2 * kMaxSpmvBlocks; // CSR slice kernel workgroups (= dot partials)
+constexpr int kMaxSliceWgs = 2 * kMaxSpmvBlocks; // slice kernel workgroups (= dot partials)
 constexpr double kSliceMaxPadding = 0.125; // slices only while padding <= this fraction of nnz
 constexpr int kPanelMinWidth = 4096;    // CSC panels span at least this many columns
 constexpr int kPanelChunkEntries = kStreamEntries; // entries per CSC panel chunk
@@ -83,7 +84,10 @@ struct Plan {
     int csr_blocks = 0, csr_rows_per_block = 0;
     bool csr_stream = false;
     std::vector<int32_t> csr_rb;          // row-block starts (nrb + 1), stream mode
-    bool csr_slices = false;              // sliced layout (replaces row blocks / lanes per row)
+    // sliced layout of the CSR rows or of the CSC panel slots (replaces row
+    // blocks / lanes per row / panel chunks); workgroups in csr_blocks
+    bool slices = false;
+    int64_t sl_lines = 0;                 // rows (CSR) or slots (CSC)
     std::vector<int32_t> sl_off;          // [slices + 1] first position of each slice (multiple of 64)
     std::vector<int32_t> sl_src;          // [positions] caller entry (0-based) at each position, -1 = padding
     std::vector<int32_t> sl_col;          // [positions] column at each position, -1 = padding
@@ -98,6 +102,15 @@ struct Plan {
     std::vector<int32_t> slot_count;      // contributions per slot (export / checks only)
     std::vector<uint16_t> seg;            // per block nslots + 1 local offsets into its contributions
     std::vector<uint16_t> tl;             // local entry index (k - k0) of every contribution
+    // symmetric CSR, sliced blocks (every line of every block <= 8 entries):
+    // block b's entries at positions ss_pos[b] + k * nl_b + l (line l of the
+    // block, its k-th entry), padded with source -1; contributions then name
+    // local positions (ss_tl) instead of local entries
+    bool sym_slices = false;
+    std::vector<int32_t> ss_pos;          // [nblocks + 1] by block id
+    std::vector<int32_t> ss_src;          // [positions] caller entry (0-based), -1 = padding
+    std::vector<int32_t> ss_idx;          // [positions] column, -1 = padding
+    std::vector<uint16_t> ss_tl;          // [contributions] local position of each contribution
     // CSC column panels (format kCsc): entries in panel order
     bool panel = false;
     int64_t pn_width = 0;
@@ -113,7 +126,7 @@ struct Plan {
     int vec_blocks = 0, vec_chunk = 0;
 
     int scatter_wgs() const { return nblocks < kMaxSpmvBlocks ? nblocks : kMaxSpmvBlocks; }
-    int spmv_blocks() const { return format == kCsr ? csr_blocks : scatter_wgs(); }
+    int spmv_blocks() const { return format == kCsr || slices ? csr_blocks : scatter_wgs(); }
     int64_t device_bytes() const;
 };
 

@@ -120,14 +120,15 @@ def test_early_iterates_match(fmt):
 
 
 @pytest.mark.parametrize("layout", ["rows", "slices"])
-def test_csr_layouts_in_iterations(monkeypatch, layout):
-    # both CSR product layouts inside the iteration graph (the default picks
-    # slices for FEM matrices)
-    monkeypatch.setenv("CGMI_CSR_LAYOUT", layout)
+@pytest.mark.parametrize("fmt", [CSR, SYM, CSC])
+def test_layouts_in_iterations(monkeypatch, fmt, layout):
+    # both product layouts of every format inside the iteration graph (the
+    # default picks slices for FEM matrices)
+    monkeypatch.setenv("CGMI_ROW_LAYOUT", layout)
     s = fem_cached("fem32x32x30")
-    arrs = formats_of(s.rowptr, s.col, s.val)[CSR]
-    xg, info, xo, oinfo = run_pair(CSR, arrs, s.b, label=f"fem32x32x30 layout={layout}")
-    check_contract(CSR, arrs, s.b, xg, info, xo, oinfo, strict_2norm=False)
+    arrs = formats_of(s.rowptr, s.col, s.val)[fmt]
+    xg, info, xo, oinfo = run_pair(fmt, arrs, s.b, label=f"fem32x32x30 layout={layout}")
+    check_contract(fmt, arrs, s.b, xg, info, xo, oinfo, strict_2norm=False)
 
 
 def test_early_iterates_4096_partials():
@@ -143,7 +144,7 @@ def test_early_iterates_4096_partials():
     val = np.where(col == i, 2.5, -1.0)
     b = W.uniform_vector(n, seed=33)
     st, stats = cgmi.cg_analyze(CSR, n, ptr, col, val)
-    assert stats["csr_slices"] == 1 and stats["spmv_blocks"] == 4096
+    assert stats["slices"] == 1 and stats["spmv_blocks"] == 4096
     for k in (1, 5, 20):
         with cgmi.Solver(CSR, ptr, col, val) as S:
             xg, info = S.solve(to_dev(b), tol=0.0, maxit=k, check=False)

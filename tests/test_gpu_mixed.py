@@ -51,13 +51,15 @@ def test_mixed_paper_sized(fmt):
     check_vs_fp64(fmt, arrs, s.b, xg, info)
 
 
-def test_mixed_csr_row_blocks(monkeypatch):
-    # the FP32 product through the row-block layout (FEM matrices default to slices)
-    monkeypatch.setenv("CGMI_CSR_LAYOUT", "rows")
+@pytest.mark.parametrize("fmt", [CSR, SYM, CSC])
+def test_mixed_row_blocks(monkeypatch, fmt):
+    # the FP32 product through the row-block / panel-chunk layout (FEM
+    # matrices default to slices)
+    monkeypatch.setenv("CGMI_ROW_LAYOUT", "rows")
     s = fem_cached("fem32x32x30")
-    arrs = formats_of(s.rowptr, s.col, s.val)[CSR]
-    xg, info = run_mixed(CSR, arrs, s.b, label="fem32x32x30 row blocks")
-    check_vs_fp64(CSR, arrs, s.b, xg, info)
+    arrs = formats_of(s.rowptr, s.col, s.val)[fmt]
+    xg, info = run_mixed(fmt, arrs, s.b, label="fem32x32x30 row blocks")
+    check_vs_fp64(fmt, arrs, s.b, xg, info)
 
 
 @pytest.mark.parametrize("fmt", [CSR, SYM])

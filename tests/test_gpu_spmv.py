@@ -43,8 +43,10 @@ def test_fem_full_size_1m(fmt):
     check_spmv(fmt, *three_formats(s)[fmt], x, label="fem100 (1.0M rows)")
 
 
+@pytest.mark.parametrize("layout", ["rows", "slices"])
 @pytest.mark.parametrize("fmt", [CSR, CSC])
-def test_ragged_nonsymmetric(fmt):
+def test_ragged_nonsymmetric(monkeypatch, fmt, layout):
+    monkeypatch.setenv("CGMI_ROW_LAYOUT", layout)
     # empty rows/columns, lines far longer than a scatter block and than 64 lanes
     ptr, col, val = W.random_sparse(3000, density=0.004, seed=4, empty_rows=60, long_rows=3, long_len=2900)
     x = W.uniform_vector(3000, seed=5)
@@ -68,10 +70,13 @@ def test_sym_random_spd():
     check_spmv(SYM, up, uc, uv, x, label="random spd")
 
 
+@pytest.mark.parametrize("layout", ["rows", "slices"])
 @pytest.mark.parametrize("case", ["fem_two_colours", "banded_empty_lines", "dense_row"])
-def test_csc_panels(case):
+def test_csc_panels(monkeypatch, case, layout):
     """CSC column panels: several panels in two colours, empty rows and
-    columns, and a slot longer than a chunk (one row dense across a panel)."""
+    columns, and a slot longer than a chunk (one row dense across a panel);
+    slots summed by panel chunks or by slices."""
+    monkeypatch.setenv("CGMI_ROW_LAYOUT", layout)
     if case == "fem_two_colours":
         s = W.fem_p1_system(30, 28, 26, seed=9)
         ptr, idx, val = s.rowptr, s.col, s.val
@@ -86,6 +91,7 @@ def test_csc_panels(case):
         val = W.uniform_vector(idx.size, seed=15)
     n = len(ptr) - 1
     st, P = cgmi.cg_analyze_panels(n, ptr, idx)
+    assert P["stats"]["slices"] == (layout == "slices")
     say(f"panels {case}: width={P['width']} colours={P['stats']['colors']} chunks={P['stats']['scatter_blocks']}")
     check_spmv(CSC, ptr, idx, val, W.uniform_vector(n, seed=16), label=case)
 
@@ -97,6 +103,24 @@ def test_scatter_block_sizes(monkeypatch, fmt, entries):
     s = W.fem_p1_system(14, 13, 12, seed=10)
     x = W.uniform_vector(s.n, seed=11)
     check_spmv(fmt, *three_formats(s)[fmt], x, label=f"entries={entries}")
+
+
+@pytest.mark.parametrize("entries", [None, "32", "200"])
+def test_sym_sliced_blocks_same_bits(monkeypatch, entries):
+    # sliced blocks keep the blocks, slots and summation order of the plain
+    # symmetric kernel: identical bits, and the oracle's bar
+    if entries:
+        monkeypatch.setenv("CGMI_SCATTER_ENTRIES", entries)
+    s = W.fem_p1_system(20, 18, 16, seed=25)
+    up = W.upper_triangle(s.rowptr, s.col, s.val)
+    x = W.uniform_vector(s.n, seed=26)
+    ys = {}
+    for layout in ("rows", "slices"):
+        monkeypatch.setenv("CGMI_ROW_LAYOUT", layout)
+        st, stats = cgmi.cg_analyze(SYM, s.n, *up)
+        assert stats["slices"] == (layout == "slices")
+        ys[layout], _ = check_spmv(SYM, *up, x, label=f"symcsr {layout} entries={entries}")
+    assert np.array_equal(ys["rows"], ys["slices"])
 
 
 def test_split_long_row_symcsr(monkeypatch):
@@ -113,12 +137,12 @@ def test_split_long_row_symcsr(monkeypatch):
 @pytest.mark.parametrize("layout", ["rows", "slices"])
 @pytest.mark.parametrize("mean_len", [2, 6, 30, 120])
 def test_lane_widths(monkeypatch, mean_len, layout):
-    monkeypatch.setenv("CGMI_CSR_LAYOUT", layout)
+    monkeypatch.setenv("CGMI_ROW_LAYOUT", layout)
     n = 1500
     ptr, col, val = W.random_sparse(n, density=mean_len / n, seed=mean_len)
     st, stats = cgmi.cg_analyze(CSR, n, ptr, col, val)
-    assert stats["csr_slices"] == (layout == "slices")
-    say(f"lanes={stats['lanes_per_line']} slices={stats['csr_slices']}")
+    assert stats["slices"] == (layout == "slices")
+    say(f"lanes={stats['lanes_per_line']} slices={stats['slices']}")
     y, yo = check_spmv(CSR, ptr, col, val, W.uniform_vector(n, seed=14), label=f"mean_len={mean_len}")
     if layout == "slices":   # every row summed left to right by one lane
         assert np.array_equal(y, yo)
@@ -188,7 +212,7 @@ def test_csr_bit_identical_to_oracle(monkeypatch, case, layout):
     # each row left to right from rounded products, exactly like the oracle;
     # the sliced layout does the same in registers (any row length)
     if layout != "auto":
-        monkeypatch.setenv("CGMI_CSR_LAYOUT", layout)
+        monkeypatch.setenv("CGMI_ROW_LAYOUT", layout)
     if case == "ragged":
         ptr, col, val = W.random_sparse(5000, density=0.003, seed=21, empty_rows=40, long_rows=2, long_len=1500)
     else:
@@ -196,7 +220,7 @@ def test_csr_bit_identical_to_oracle(monkeypatch, case, layout):
         ptr, col, val = s.rowptr, s.col, s.val
     st, stats = cgmi.cg_analyze(CSR, len(ptr) - 1, ptr, col, val)
     assert st == 0
-    say(f"layout={layout} slices={stats['csr_slices']} workgroups={stats['spmv_blocks']}")
+    say(f"layout={layout} slices={stats['slices']} workgroups={stats['spmv_blocks']}")
     y, yo = check_spmv(CSR, ptr, col, val, W.uniform_vector(len(ptr) - 1, seed=22), label=f"bitwise {case}")
     assert np.array_equal(y, yo)
 
@@ -204,11 +228,11 @@ def test_csr_bit_identical_to_oracle(monkeypatch, case, layout):
 @pytest.mark.parametrize("n", [1, 63, 64, 65, 200, 4097])
 def test_csr_slices_ragged_shapes(monkeypatch, n):
     # partial last slice, empty rows, one row far longer than the rest
-    monkeypatch.setenv("CGMI_CSR_LAYOUT", "slices")
+    monkeypatch.setenv("CGMI_ROW_LAYOUT", "slices")
     ptr, col, val = W.random_sparse(n, density=min(1.0, 9.0 / n), seed=n, empty_rows=n // 7,
                                     long_rows=1 if n > 1 else 0, long_len=min(n, 700))
     st, stats = cgmi.cg_analyze(CSR, n, ptr, col, val)
-    assert st == 0 and stats["csr_slices"] == 1
+    assert st == 0 and stats["slices"] == 1
     y, yo = check_spmv(CSR, ptr, col, val, W.uniform_vector(n, seed=n + 1), label=f"slices n={n}")
     assert np.array_equal(y, yo)
 
@@ -226,7 +250,7 @@ def test_csr_slices_several_per_wave():
     col = (i + off).astype(np.int32)
     val = np.where(col == i, 2.0, -1.0) + 1e-3 * W.uniform_vector(ptr[-1], seed=30)
     st, stats = cgmi.cg_analyze(CSR, n, ptr, col, val)
-    assert st == 0 and stats["csr_slices"] == 1 and stats["spmv_blocks"] == 4096
+    assert st == 0 and stats["slices"] == 1 and stats["spmv_blocks"] == 4096
     y, yo = check_spmv(CSR, ptr, col, val, W.uniform_vector(n, seed=31), label="1.2M rows, 3 per row")
     assert np.array_equal(y, yo)
 

@@ -83,28 +83,46 @@ def test_csr_layout_choice(monkeypatch):
     s = W.fem_config("fem32x32x30")
     st, stats = cgmi.cg_analyze(CSR, s.n, s.rowptr, s.col, s.val)
     pos, ns = _slice_positions(s.rowptr)
-    assert st == 0 and stats["csr_slices"] == 1
+    assert st == 0 and stats["slices"] == 1
     assert s.nnz <= pos <= 1.125 * s.nnz
     assert stats["plan_bytes"] == 4 * (ns + 1) + 16 * pos
     assert stats["spmv_blocks"] == min((ns + 3) // 4, 4096)
     # two 1500-entry rows among ~15-entry rows: padding too large, row blocks
     ptr, col, val = W.random_sparse(5000, density=0.003, seed=21, empty_rows=40, long_rows=2, long_len=1500)
     st, stats = cgmi.cg_analyze(CSR, 5000, ptr, col, val)
-    assert st == 0 and stats["csr_slices"] == 0 and stats["plan_bytes"] < 5000
+    assert st == 0 and stats["slices"] == 0 and stats["plan_bytes"] < 5000
     # the knob forces either layout
-    monkeypatch.setenv("CGMI_CSR_LAYOUT", "slices")
+    monkeypatch.setenv("CGMI_ROW_LAYOUT", "slices")
     st, stats = cgmi.cg_analyze(CSR, 5000, ptr, col, val)
     pos, ns = _slice_positions(ptr)
-    assert st == 0 and stats["csr_slices"] == 1 and stats["plan_bytes"] == 4 * (ns + 1) + 16 * pos
-    monkeypatch.setenv("CGMI_CSR_LAYOUT", "rows")
+    assert st == 0 and stats["slices"] == 1 and stats["plan_bytes"] == 4 * (ns + 1) + 16 * pos
+    monkeypatch.setenv("CGMI_ROW_LAYOUT", "rows")
     st, stats = cgmi.cg_analyze(CSR, s.n, s.rowptr, s.col, s.val)
-    assert st == 0 and stats["csr_slices"] == 0
-    # other formats never use it
-    monkeypatch.delenv("CGMI_CSR_LAYOUT")
-    for fmt in (cgmi.CG_FMT_SYM_CSR, cgmi.CG_FMT_CSC):
-        arrs = W.upper_triangle(s.rowptr, s.col, s.val) if fmt == cgmi.CG_FMT_SYM_CSR else (s.rowptr, s.col, s.val)
-        st, stats = cgmi.cg_analyze(fmt, s.n, *arrs)
-        assert st == 0 and stats["csr_slices"] == 0
+    assert st == 0 and stats["slices"] == 0
+    # CSC: slices over the panel slots (their segments are the lines)
+    st, stats = cgmi.cg_analyze(cgmi.CG_FMT_CSC, s.n, s.rowptr, s.col, s.val)
+    assert st == 0 and stats["slices"] == 0
+    monkeypatch.delenv("CGMI_ROW_LAYOUT")
+    st, stats = cgmi.cg_analyze(cgmi.CG_FMT_CSC, s.n, s.rowptr, s.col, s.val)
+    st2, P = cgmi.cg_analyze_panels(s.n, s.rowptr, s.col)
+    pos, ns = _slice_positions(P["slot_ptr"])
+    assert st == 0 and stats["slices"] == 1 and stats["spmv_blocks"] == min((ns + 3) // 4, 4096)
+    assert s.nnz <= pos <= 1.125 * s.nnz
+    # symmetric CSR: sliced blocks when no stored line has more than 8
+    # entries (FEM upper triangle: the diagonal and 7 neighbours at most)
+    up = W.upper_triangle(s.rowptr, s.col, s.val)
+    assert np.diff(up[0]).max() <= 8
+    st, stats = cgmi.cg_analyze(cgmi.CG_FMT_SYM_CSR, s.n, *up)
+    assert st == 0 and stats["slices"] == 1
+    monkeypatch.setenv("CGMI_ROW_LAYOUT", "rows")
+    st, stats = cgmi.cg_analyze(cgmi.CG_FMT_SYM_CSR, s.n, *up)
+    assert st == 0 and stats["slices"] == 0
+    monkeypatch.delenv("CGMI_ROW_LAYOUT")
+    ptr, col, val = W.random_spd_sparse(2000, density=0.01, seed=8)
+    up = W.upper_triangle(ptr, col, val)
+    assert np.diff(up[0]).max() > 8
+    st, stats = cgmi.cg_analyze(cgmi.CG_FMT_SYM_CSR, 2000, *up)
+    assert st == 0 and stats["slices"] == 0
 
 
 def _expected_targets(fmt, ptr, idx, e0, e1, l0, l1):
