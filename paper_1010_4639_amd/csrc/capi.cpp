@@ -186,29 +186,26 @@ int upload_all(cg_handle *h, const std::vector<int32_t> &ptr0, const std::vector
             return st;
     }
     if (p.panel && n > 0) {
-        // CSC column panels: slots of colour 0 first (see plan.h)
+        // CSC column panels: slots of colour 0 first (see plan.h).  A row
+        // meets at most two panels, one of each colour (W >= 2 bw + 1), so it
+        // has at most one parked sum: parked sums are stored by row, and one
+        // flag byte per row says which of y_i (bit 0) and part_i (bit 1) hold
+        // a share of (A x)_i.
         const int64_t ns = (int64_t)p.pn_slot_target.size();
         const int32_t fp = p.pn_first_parked;
-        std::vector<int32_t> rsp((size_t)n + 1, 0), rsi;
         std::vector<uint8_t> c0((size_t)n, 0);
         for (int64_t q = 0; q < ns; ++q) {
-            if (q < fp)
-                c0[p.pn_slot_target[q]] = 1;
-            else
-                rsp[p.pn_slot_target[q] + 1]++;
+            const uint8_t bit = q < fp ? 1 : 2;
+            if (c0[p.pn_slot_target[q]] & bit) {
+                h->err = "internal: a row has two panel slots of one colour";
+                return CG_ERR_HIP;
+            }
+            c0[p.pn_slot_target[q]] |= bit;
         }
-        bool gather = ns > fp;
-        for (int64_t i = 0; i < n; ++i) {
-            gather = gather || (!c0[i] && rsp[i + 1] == 0);
-            rsp[i + 1] += rsp[i];
-        }
-        rsi.resize(rsp[n]);
-        {
-            std::vector<int32_t> next(rsp.begin(), rsp.end() - 1);
-            for (int64_t q = fp; q < ns; ++q)
-                rsi[next[p.pn_slot_target[q]]++] = (int32_t)(q - fp);
-        }
-        int32_t *cs = nullptr, *sp = nullptr, *stg, *pc = nullptr, *src = nullptr, *drsp, *drsi;
+        bool gather = false;
+        for (int64_t i = 0; i < n; ++i)
+            gather = gather || c0[i] != 1;
+        int32_t *cs = nullptr, *sp = nullptr, *stg, *pc = nullptr, *src = nullptr;
         uint8_t *dc0;
         double *pv = nullptr, *part;
         if (!p.slices && // chunk kernel: slot pointers, chunks and the entries in panel order
@@ -219,10 +216,7 @@ int upload_all(cg_handle *h, const std::vector<int32_t> &ptr0, const std::vector
              (st = dalloc(h, &pv, p.pn_src.size())) != CG_OK))
             return st;
         if ((st = upload(h, &stg, p.pn_slot_target.data(), p.pn_slot_target.size())) != CG_OK ||
-            (st = dalloc(h, &part, (size_t)std::max<int64_t>(ns - fp, 1))) != CG_OK ||
-            (st = upload(h, &drsp, rsp.data(), rsp.size())) != CG_OK ||
-            (st = upload(h, &drsi, rsi.data(), rsi.size())) != CG_OK ||
-            (st = upload(h, &dc0, c0.data(), c0.size())) != CG_OK)
+            (st = dalloc(h, &part, (size_t)n)) != CG_OK || (st = upload(h, &dc0, c0.data(), c0.size())) != CG_OK)
             return st;
         m.panel = true;
         m.pn_gather = gather;
@@ -234,8 +228,6 @@ int upload_all(cg_handle *h, const std::vector<int32_t> &ptr0, const std::vector
         m.pn_val = pv;
         m.pn_first_parked = fp;
         m.part = part;
-        m.rs_ptr = drsp;
-        m.rs_idx = drsi;
         m.has_c0 = dc0;
         m.scatter_wgs = p.scatter_wgs();
         if (h->mixed && !p.slices && (st = dalloc(h, &m.pn_val32, p.pn_src.size())) != CG_OK)

@@ -66,10 +66,10 @@ struct DevMatrix {
     std::vector<int32_t> color_slot_off; // host copy: slots per colour (device arrays in colour order)
     int scatter_wgs = 0;                 // workgroups of k_scatter_sums (= dot partials)
     const ScatterBlock *blocks = nullptr; // in colour order; slot0 / id refer to the colour-ordered arrays
-    double *part = nullptr;              // parked slot sums (colours >= 1)
+    double *part = nullptr;              // parked slot sums (colours >= 1); CSC panels: by row
     const int32_t *rs_ptr = nullptr;     // per row: its parked slots [rs_ptr[i], rs_ptr[i+1]) of rs_idx
-    const int32_t *rs_idx = nullptr;     //   slot indices, ascending colour
-    const uint8_t *has_c0 = nullptr;     // per row: written by a colour-0 block
+    const int32_t *rs_idx = nullptr;     //   slot indices, ascending colour (symmetric CSR)
+    const uint8_t *has_c0 = nullptr;     // per row: written by a colour-0 block; CSC panels: bit 1 = part_i
     const int32_t *slot_target = nullptr;
     const uint8_t *slot_flag = nullptr;
     const uint16_t *seg = nullptr;

@@ -219,7 +219,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv_csr_rows(int nrb, const int2 *_
 // takes several consecutive slices of its workgroup's range.
 // PANEL = false: lines are the rows of y.  PANEL = true: lines are the CSC
 // panel slots; a colour-0 slot stores y[target], a colour-1 slot parks its
-// sum for the row pass.  Fused epilogue: partial of x'y (linear in the line
+// sum at part[target] for the row pass.  Fused epilogue: partial of x'y (linear in the line
 // sums, so x_target * sum per line).
 template <bool PANEL, class VT, class PT>
 __global__ __launch_bounds__(kBlock) void k_spmv_slices(int nl, int ns, const int32_t *__restrict__ off,
@@ -267,7 +267,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv_slices(int nl, int ns, const in
             if (!PANEL || l < first_parked)
                 y[tg] = a;
             else
-                part[l - first_parked] = a;
+                part[tg] = a; // parked by row: at most one colour-1 slot per row
             sig = fma((double)x[tg], a, sig);
         }
     }
@@ -320,7 +320,7 @@ __global__ __launch_bounds__(kBlock) void k_panel_rows(int nch, const int32_t *_
                 if (s0 < first_parked)
                     y[tg] = a;
                 else
-                    part[s0 - first_parked] = a;
+                    part[tg] = a; // parked by row: at most one colour-1 slot per row
                 sig = fma((double)x[tg], a, sig);
             }
             continue;
@@ -356,7 +356,7 @@ __global__ __launch_bounds__(kBlock) void k_panel_rows(int nch, const int32_t *_
             if (sl < first_parked)
                 y[tg] = a;
             else
-                part[sl - first_parked] = a;
+                part[tg] = a;
             sig = fma(xt, a, sig);
         }
         __syncthreads();
@@ -636,6 +636,28 @@ __global__ __launch_bounds__(kBlock) void k_scatter_gather(int n, const int32_t 
     y[i] = a;
 }
 
+// Row pass of the CSC panels: y_i = (colour-0 share) + (parked share), the
+// same terms and order as k_scatter_gather, with the parked sum stored by
+// row (flag bit 0: y_i holds a share, bit 1: part_i does; neither: no entry
+// writes row i, y_i = 0).
+__global__ __launch_bounds__(kBlock) void k_panel_gather(int n, const uint8_t *__restrict__ flags,
+                                                         const double *__restrict__ part, double *__restrict__ y,
+                                                         const DevState *st)
+{
+    if (st != nullptr && st->status != kRun)
+        return;
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n)
+        return;
+    const int f = flags[i];
+    if (f == 1)
+        return; // written once, by its colour-0 slot
+    double a = (f & 1) ? y[i] : 0.0;
+    if (f & 2)
+        a += part[i];
+    y[i] = a;
+}
+
 // ------------------------------------------------------ vector kernels
 // Each workgroup owns a contiguous chunk (XCD-remapped).  The first kPre
 // elements per thread are loaded before the dot partials of the previous
@@ -645,17 +667,27 @@ constexpr int kPre = 4;
 // Rows finished by the row pass of a scatter product: GATHER folds that pass
 // (k_scatter_gather's sum, same terms, same order) into the r update, so the
 // product's last writes of y and their re-read are saved.
+// GATHER: 0 = no row pass; 1 = per-row lists of parked slots (symmetric
+// CSR); 2 = at most one parked sum per row, stored by row, with a flag byte
+// (bit 0: y_i holds a share, bit 1: part_i does; CSC panels).
 struct RowPass {
     const int32_t *rs_ptr = nullptr, *rs_idx = nullptr;
     const uint8_t *has_c0 = nullptr;
     const double *part = nullptr;
 };
 
-template <bool GATHER>
+template <int GATHER>
 __device__ __forceinline__ double q_value(const double *__restrict__ q, const RowPass &g, int i)
 {
-    if (!GATHER)
+    if (GATHER == 0)
         return q[i];
+    if (GATHER == 2) {
+        const int f = g.has_c0[i];
+        double a = (f & 1) ? q[i] : 0.0;
+        if (f & 2)
+            a += g.part[i];
+        return a;
+    }
     const int k0 = g.rs_ptr[i], k1 = g.rs_ptr[i + 1];
     double a = g.has_c0[i] ? q[i] : 0.0;
     for (int k = k0; k < k1; ++k)
@@ -664,7 +696,7 @@ __device__ __forceinline__ double q_value(const double *__restrict__ q, const Ro
 }
 
 // PPT: dot partials per thread (n_sig <= PPT * 256)
-template <bool GATHER, int PPT>
+template <int GATHER, int PPT>
 __global__ __launch_bounds__(kBlock) void k_update_r(int n, int chunk, double *__restrict__ r,
                                                      const double *__restrict__ q, DevState *st,
                                                      const double *__restrict__ sig_part, int n_sig,
@@ -1085,8 +1117,8 @@ void spmv_any(const DevMatrix &m, const VT *val, const PT *x, double *y, double 
     }
     if (m.panel) {
         if (m.pn_gather && !c.defer_rows)
-            hipLaunchKernelGGL(k_scatter_gather, dim3((m.n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, m.n,
-                               m.rs_ptr, m.rs_idx, m.has_c0, m.part, y, c.st);
+            hipLaunchKernelGGL(k_panel_gather, dim3((m.n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, m.n,
+                               m.has_c0, m.part, y, c.st);
         return;
     }
     if (m.slices)
@@ -1126,24 +1158,31 @@ void launch_update_r(const DevMatrix &m, double *r, const double *q, DevState *s
     // slices: up to kMaxSliceWgs dot partials
     const bool wide = m.spmv_blocks() > kPartPerThread * kBlock;
     RowPass g;
-    if (rows_deferred && m.row_pass()) {
-        g.rs_ptr = m.rs_ptr;
-        g.rs_idx = m.rs_idx;
-        g.has_c0 = m.has_c0;
-        g.part = m.part;
+    g.rs_ptr = m.rs_ptr;
+    g.rs_idx = m.rs_idx;
+    g.has_c0 = m.has_c0;
+    g.part = m.part;
+    const int mode = rows_deferred && m.row_pass() ? (m.panel ? 2 : 1) : 0;
+    const dim3 grid(m.vec_blocks), blk(kBlock);
+#define CGMI_UPDATE_R(G, P)                                                                                  \
+    hipLaunchKernelGGL((k_update_r<G, P>), grid, blk, 0, s, m.n, m.vec_chunk, r, q, st, sig_part, m.spmv_blocks(), \
+                       rho_part, g)
+    if (mode == 2) {
         if (wide)
-            hipLaunchKernelGGL((k_update_r<true, 2 * kPartPerThread>), dim3(m.vec_blocks), dim3(kBlock), 0, s, m.n,
-                               m.vec_chunk, r, q, st, sig_part, m.spmv_blocks(), rho_part, g);
+            CGMI_UPDATE_R(2, 2 * kPartPerThread);
         else
-            hipLaunchKernelGGL((k_update_r<true, kPartPerThread>), dim3(m.vec_blocks), dim3(kBlock), 0, s, m.n,
-                               m.vec_chunk, r, q, st, sig_part, m.spmv_blocks(), rho_part, g);
+            CGMI_UPDATE_R(2, kPartPerThread);
+    } else if (mode == 1) {
+        if (wide)
+            CGMI_UPDATE_R(1, 2 * kPartPerThread);
+        else
+            CGMI_UPDATE_R(1, kPartPerThread);
     } else if (wide) {
-        hipLaunchKernelGGL((k_update_r<false, 2 * kPartPerThread>), dim3(m.vec_blocks), dim3(kBlock), 0, s, m.n,
-                           m.vec_chunk, r, q, st, sig_part, m.spmv_blocks(), rho_part, g);
+        CGMI_UPDATE_R(0, 2 * kPartPerThread);
     } else {
-        hipLaunchKernelGGL((k_update_r<false, kPartPerThread>), dim3(m.vec_blocks), dim3(kBlock), 0, s, m.n,
-                           m.vec_chunk, r, q, st, sig_part, m.spmv_blocks(), rho_part, g);
+        CGMI_UPDATE_R(0, kPartPerThread);
     }
+#undef CGMI_UPDATE_R
 }
 
 void launch_update_xp(const DevMatrix &m, double *x, double *p, const double *r, DevState *st,

@@ -16,12 +16,11 @@ int64_t Plan::device_bytes() const
     const int64_t sl = (int64_t)sl_off.size() * 4 + (int64_t)sl_src.size() * (4 + 4 + 8);
     if (format == kCsr) // row-block starts or slices
         return (int64_t)csr_rb.size() * 4 + sl;
-    if (panel && slices) // slices; slot target; parked sums; row lists
-        return sl + (int64_t)pn_slot_target.size() * 4 + (int64_t)(pn_slot_target.size() - pn_first_parked) * 8 +
-               (int64_t)(pn_slot_target.size() - pn_first_parked) * 4 + (n + 1) * 4 + n;
-    if (panel) // entry source + column + reordered value; slot target / pointer / parked sum; row lists
-        return nnz * (4 + 4 + 8) + (int64_t)pn_slot_target.size() * (4 + 4 + 8 + 4) +
-               (int64_t)pn_chunk_slot.size() * 8 + n * 5;
+    if (panel && slices) // slices; slot targets; parked sums and flags by row
+        return sl + (int64_t)pn_slot_target.size() * 4 + n * 9;
+    if (panel) // entry source + column + reordered value; slot target / pointer; chunks; parked sums, flags
+        return nnz * (4 + 4 + 8) + (int64_t)pn_slot_target.size() * (4 + 4) + (int64_t)pn_chunk_slot.size() * 4 +
+               n * 9;
     // descriptors, slot target / flag / segment offsets, contributions, parked
     // sums and their per-row index (upper bounds: every slot counted); sliced
     // blocks: positions (source, column, value) and their block offsets
