@@ -1154,9 +1154,12 @@ void launch_spmv32(const DevMatrix &m, const float *x, double *y, double *sig_pa
 void launch_update_r(const DevMatrix &m, double *r, const double *q, DevState *st, const double *sig_part,
                      double *rho_part, hipStream_t s, bool rows_deferred)
 {
-    static_assert(kMaxSliceWgs <= 2 * kPartPerThread * kBlock, "slice partials fit twice the registers");
-    // slices: up to kMaxSliceWgs dot partials
-    const bool wide = m.spmv_blocks() > kPartPerThread * kBlock;
+    static_assert(kMaxSliceWgs <= 4 * kPartPerThread * kBlock, "slice partials fit four times the registers");
+    // slices: up to kMaxSliceWgs dot partials (one slice per wavefront); the
+    // r update then holds 16 or 32 of them per thread (it runs at ~4 waves
+    // per SIMD anyway, so the registers cost no occupancy that matters)
+    const int nsig = m.spmv_blocks();
+    const int ppt = nsig <= kPartPerThread * kBlock ? 1 : nsig <= 2 * kPartPerThread * kBlock ? 2 : 4;
     RowPass g;
     g.rs_ptr = m.rs_ptr;
     g.rs_idx = m.rs_idx;
@@ -1165,23 +1168,24 @@ void launch_update_r(const DevMatrix &m, double *r, const double *q, DevState *s
     const int mode = rows_deferred && m.row_pass() ? (m.panel ? 2 : 1) : 0;
     const dim3 grid(m.vec_blocks), blk(kBlock);
 #define CGMI_UPDATE_R(G, P)                                                                                  \
-    hipLaunchKernelGGL((k_update_r<G, P>), grid, blk, 0, s, m.n, m.vec_chunk, r, q, st, sig_part, m.spmv_blocks(), \
-                       rho_part, g)
-    if (mode == 2) {
-        if (wide)
-            CGMI_UPDATE_R(2, 2 * kPartPerThread);
-        else
-            CGMI_UPDATE_R(2, kPartPerThread);
-    } else if (mode == 1) {
-        if (wide)
-            CGMI_UPDATE_R(1, 2 * kPartPerThread);
-        else
-            CGMI_UPDATE_R(1, kPartPerThread);
-    } else if (wide) {
-        CGMI_UPDATE_R(0, 2 * kPartPerThread);
-    } else {
-        CGMI_UPDATE_R(0, kPartPerThread);
-    }
+    hipLaunchKernelGGL((k_update_r<G, P * kPartPerThread>), grid, blk, 0, s, m.n, m.vec_chunk, r, q, st, sig_part, \
+                       nsig, rho_part, g)
+#define CGMI_UPDATE_R_PPT(G)                                                                                 \
+    do {                                                                                                     \
+        if (ppt == 1)                                                                                        \
+            CGMI_UPDATE_R(G, 1);                                                                             \
+        else if (ppt == 2)                                                                                   \
+            CGMI_UPDATE_R(G, 2);                                                                             \
+        else                                                                                                 \
+            CGMI_UPDATE_R(G, 4);                                                                             \
+    } while (0)
+    if (mode == 2)
+        CGMI_UPDATE_R_PPT(2);
+    else if (mode == 1)
+        CGMI_UPDATE_R_PPT(1);
+    else
+        CGMI_UPDATE_R_PPT(0);
+#undef CGMI_UPDATE_R_PPT
 #undef CGMI_UPDATE_R
 }
 

@@ -56,7 +56,7 @@ constexpr int kStreamRows = kBlock;                    // rows per CSR row block
 constexpr double kStreamMaxMeanRow = 32.0;             // longer mean rows use lanes-per-row
 constexpr int kSliceRows = 64;          // slices: lines per slice (one wavefront, a line per lane)
 constexpr int kWavesPerBlock = kBlock / kSliceRows;
-constexpr int kMaxSliceWgs = 2 * kMaxSpmvBlocks; // slice kernel workgroups (= dot partials)
+constexpr int kMaxSliceWgs = 4 * kMaxSpmvBlocks; // slice kernel workgroups (= dot partials)
 constexpr double kSliceMaxPadding = 0.125; // slices only while padding <= this fraction of nnz
 constexpr int kPanelMinWidth = 4096;    // CSC panels span at least this many columns
 constexpr int kPanelChunkEntries = kStreamEntries; // entries per CSC panel chunk

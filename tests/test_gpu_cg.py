@@ -131,10 +131,10 @@ def test_layouts_in_iterations(monkeypatch, fmt, layout):
     check_contract(fmt, arrs, s.b, xg, info, xo, oinfo, strict_2norm=False)
 
 
-def test_early_iterates_4096_partials():
-    # 1.2M-row tridiagonal SPD matrix: the sliced product runs on 4096
-    # workgroups (several slices per wave) and the r update sums 4096 partials
-    n = 1_200_000
+def test_early_iterates_8192_partials():
+    # 2.2M-row tridiagonal SPD matrix: the sliced product runs on 8192
+    # workgroups (several slices per wave) and the r update sums 8192 partials
+    n = 2_200_000
     lens = np.full(n, 3)
     lens[0] = lens[-1] = 2
     ptr = np.zeros(n + 1, np.int32)
@@ -144,7 +144,7 @@ def test_early_iterates_4096_partials():
     val = np.where(col == i, 2.5, -1.0)
     b = W.uniform_vector(n, seed=33)
     st, stats = cgmi.cg_analyze(CSR, n, ptr, col, val)
-    assert stats["slices"] == 1 and stats["spmv_blocks"] == 4096
+    assert stats["slices"] == 1 and stats["spmv_blocks"] == 8192
     for k in (1, 5, 20):
         with cgmi.Solver(CSR, ptr, col, val) as S:
             xg, info = S.solve(to_dev(b), tol=0.0, maxit=k, check=False)

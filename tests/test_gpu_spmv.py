@@ -238,9 +238,9 @@ def test_csr_slices_ragged_shapes(monkeypatch, n):
 
 
 def test_csr_slices_several_per_wave():
-    # more than 4 x 4096 slices: every workgroup's waves take several slices,
-    # and the product leaves 4096 dot partials
-    n = 1_200_000
+    # more than 4 x 8192 slices: waves take several slices, and the product
+    # leaves 8192 dot partials
+    n = 2_200_000
     ptr = np.zeros(n + 1, np.int32)
     lens = np.full(n, 3)
     lens[0] = lens[-1] = 2
@@ -250,8 +250,8 @@ def test_csr_slices_several_per_wave():
     col = (i + off).astype(np.int32)
     val = np.where(col == i, 2.0, -1.0) + 1e-3 * W.uniform_vector(ptr[-1], seed=30)
     st, stats = cgmi.cg_analyze(CSR, n, ptr, col, val)
-    assert st == 0 and stats["slices"] == 1 and stats["spmv_blocks"] == 4096
-    y, yo = check_spmv(CSR, ptr, col, val, W.uniform_vector(n, seed=31), label="1.2M rows, 3 per row")
+    assert st == 0 and stats["slices"] == 1 and stats["spmv_blocks"] == 8192
+    y, yo = check_spmv(CSR, ptr, col, val, W.uniform_vector(n, seed=31), label="2.2M rows, 3 per row")
     assert np.array_equal(y, yo)
 
 

@@ -65,7 +65,7 @@ def test_csr_plan_shape():
     assert st == 0
     assert stats["lanes_per_line"] == 16          # ~14.25 entries per row
     assert stats["colors"] == 0 and stats["slots"] == 0
-    assert 1 <= stats["spmv_blocks"] <= 4096 and 1 <= stats["vec_blocks"] <= 1024
+    assert 1 <= stats["spmv_blocks"] <= 8192 and 1 <= stats["vec_blocks"] <= 1024
 
 
 def _slice_positions(ptr):
@@ -86,7 +86,7 @@ def test_csr_layout_choice(monkeypatch):
     assert st == 0 and stats["slices"] == 1
     assert s.nnz <= pos <= 1.125 * s.nnz
     assert stats["plan_bytes"] == 4 * (ns + 1) + 16 * pos
-    assert stats["spmv_blocks"] == min((ns + 3) // 4, 4096)
+    assert stats["spmv_blocks"] == min((ns + 3) // 4, 8192)
     # two 1500-entry rows among ~15-entry rows: padding too large, row blocks
     ptr, col, val = W.random_sparse(5000, density=0.003, seed=21, empty_rows=40, long_rows=2, long_len=1500)
     st, stats = cgmi.cg_analyze(CSR, 5000, ptr, col, val)
@@ -106,7 +106,7 @@ def test_csr_layout_choice(monkeypatch):
     st, stats = cgmi.cg_analyze(cgmi.CG_FMT_CSC, s.n, s.rowptr, s.col, s.val)
     st2, P = cgmi.cg_analyze_panels(s.n, s.rowptr, s.col)
     pos, ns = _slice_positions(P["slot_ptr"])
-    assert st == 0 and stats["slices"] == 1 and stats["spmv_blocks"] == min((ns + 3) // 4, 4096)
+    assert st == 0 and stats["slices"] == 1 and stats["spmv_blocks"] == min((ns + 3) // 4, 8192)
     assert s.nnz <= pos <= 1.125 * s.nnz
     # symmetric CSR: sliced blocks when no stored line has more than 8
     # entries (FEM upper triangle: the diagonal and 7 neighbours at most)
