@@ -190,9 +190,11 @@ int cg_batch_set_stream(cg_batch *h, void *hip_stream);
 int cg_batch_spmm(cg_batch *h, const double *X, double *Y);
 /* Project-written autotuner: times the product for every schedule -- row
  * blocks of 256, 512 or 1024 entries summed through LDS, or 8 or 16 lanes
- * per row combined by butterflies -- x workgroup budget (1024, 2048, 4096),
- * keeps the fastest plan and reports it (outputs may be NULL;
- * lanes_per_row = 0 means the LDS row-block schedule).  Uses the GPU. */
+ * per row combined by butterflies, or one lane per row over 64-row slices of
+ * each system stored k-th entry first -- x workgroup budget (1024, 2048,
+ * 4096; twice that for the slices), keeps the fastest plan and reports it
+ * (outputs may be NULL; lanes_per_row = 0 means the LDS row-block schedule,
+ * 1 the slices, whose entries_per_block is 0).  Uses the GPU. */
 int cg_batch_autotune(cg_batch *h, int32_t *entries_per_block, int32_t *lanes_per_row, int32_t *workgroups,
                       float *best_us);
 /* Solves all pairs from X (in: x0, out: solutions) to ||r|| <= tol ||b|| each.

@@ -287,6 +287,100 @@ __global__ __launch_bounds__(kBlock) void k_bspmm(const WgDesc *__restrict__ wgs
     }
 }
 
+// Q = A P for the R interleaved right-hand sides over the sliced layout (the
+// third schedule): each system's rows in slices of 64, lane l of a wave owns
+// row 64 s + l, and a slice stores the k-th entries of its rows contiguously
+// (padding: column -1).  The lanes of one load gather neighbouring rows of P
+// for a stencil-like matrix, each 8R bytes, so the gathers coalesce.  A row
+// is summed left to right from rounded products, the order of the LDS
+// schedule (same bits).  Waves of a workgroup take its slices in turn.
+template <int R, int U>
+__global__ __launch_bounds__(kBlock) void k_bspmm_slices(const WgDesc *__restrict__ wgs,
+                                                         const int32_t *__restrict__ sl_row,
+                                                         const int32_t *__restrict__ sl_off,
+                                                         const int32_t *__restrict__ col,
+                                                         const double *__restrict__ val,
+                                                         const double *__restrict__ P, double *__restrict__ Q,
+                                                         double *__restrict__ sig_part, Inst *inst)
+{
+#pragma clang fp contract(off)
+    __shared__ double red[kWaves];
+    __shared__ int act_s[R];
+    const WgDesc W = wgs[blockIdx.x];
+    const int t = threadIdx.x;
+    bool any = true;
+    if (inst != nullptr) {
+        if (t < R)
+            act_s[t] = inst_gate(&inst[W.sys * R + t], W.lead != 0) ? 1 : 0;
+        __syncthreads();
+        any = false;
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+            any |= act_s[r] != 0;
+    }
+    double sig[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+        sig[r] = 0.0;
+    const int lane = t & 63;
+    if (any) {
+        for (int sl = W.rb0 + (t >> 6); sl < W.rb1; sl += kWaves) {
+            const int e0 = sl_off[sl], L = (sl_off[sl + 1] - e0) / 64;
+            const int row = sl_row[sl] + lane;
+            double a[R];
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+                a[r] = 0.0;
+            for (int k0 = 0; k0 < L; k0 += U) {
+                int c[U];
+                double v[U], pv[U][R];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const bool ok = k0 + u < L;
+                    const int e = e0 + (k0 + u) * 64 + lane;
+                    c[u] = ok ? __builtin_nontemporal_load(col + e) : -1;
+                    v[u] = ok ? __builtin_nontemporal_load(val + e) : 0.0;
+                }
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    if constexpr (R % 2 == 0) {
+                        const double2 *p2 = reinterpret_cast<const double2 *>(P + (size_t)max(c[u], 0) * R);
+#pragma unroll
+                        for (int h2 = 0; h2 < R / 2; ++h2) {
+                            const double2 q2 = c[u] >= 0 ? p2[h2] : double2{0.0, 0.0};
+                            pv[u][2 * h2] = q2.x;
+                            pv[u][2 * h2 + 1] = q2.y;
+                        }
+                    } else {
+#pragma unroll
+                        for (int r = 0; r < R; ++r)
+                            pv[u][r] = c[u] >= 0 ? P[(size_t)c[u] * R + r] : 0.0;
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+                    if (c[u] >= 0)
+#pragma unroll
+                        for (int r = 0; r < R; ++r)
+                            a[r] = a[r] + v[u] * pv[u][r];
+            }
+            if (row < W.i1) {
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    Q[(size_t)row * R + r] = a[r];
+                    sig[r] = fma(P[(size_t)row * R + r], a[r], sig[r]);
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const double sr = block_sum(sig[r], red);
+        if (t == 0)
+            sig_part[blockIdx.x * R + r] = sr;
+    }
+}
+
 // Per instance r of this workgroup's system: sum of the system's partials
 // (fixed order), by thread r.
 template <int R>
@@ -541,8 +635,14 @@ struct cg_batch {
     std::vector<int64_t> sys_off;
     std::vector<int32_t> hptr, hidx; // host copy of the structure (re-planning by the autotuner)
     // plan: row blocks of 256 * ept entries; lanes = 0 runs the products on
-    // them through LDS, lanes = 8 / 16 uses that many lanes per row instead
+    // them through LDS, lanes = 8 / 16 uses that many lanes per row instead,
+    // lanes = 1 runs one lane per row over the sliced layout (the workgroups
+    // then own runs of slices instead of row blocks)
     int ept = 4, G = 0, nrb = 0, wg_target = 2048, lanes = 0;
+    // sliced layout (built once, on first use): per system, slices of 64 rows
+    std::vector<int32_t> hsl_row, hsl_sys0; // first row of each slice; first slice of each system (+ end)
+    int32_t *sl_row = nullptr, *sl_off = nullptr, *sl_col = nullptr;
+    double *sl_val = nullptr;
     // device
     std::vector<void *> allocs, plan_allocs;
     int32_t *ptr = nullptr, *idx = nullptr, *rb_row = nullptr, *sys_wg0 = nullptr;
@@ -685,6 +785,115 @@ int build_plan(cg_batch *h, int ept, int wg_target)
     return CG_OK;
 }
 
+// The sliced layout of the block-diagonal matrix, once: each system's rows
+// in slices of 64 (the last one of a system may be short), positions
+// off + 64 k + lane, padded with column -1 / value 0.
+int ensure_slices(cg_batch *h)
+{
+    if (h->sl_col)
+        return CG_OK;
+    const int32_t *ptr = h->hptr.data(), *idx = h->hidx.data();
+    std::vector<int32_t> row0, off(1, 0), sys0(h->nsys + 1, 0);
+    for (int s = 0; s < h->nsys; ++s) {
+        sys0[s] = (int32_t)row0.size();
+        const int64_t a = h->sys_off[s], b = h->sys_off[s + 1];
+        for (int64_t r = a; r < b; r += 64) {
+            int64_t L = 0;
+            for (int64_t i = r; i < std::min(b, r + 64); ++i)
+                L = std::max<int64_t>(L, (int64_t)ptr[i + 1] - ptr[i]);
+            if ((int64_t)off.back() + 64 * L > INT32_MAX) {
+                h->err = "sliced layout too large for 32-bit positions";
+                return CG_ERR_UNSUPPORTED;
+            }
+            row0.push_back((int32_t)r);
+            off.push_back(off.back() + (int32_t)(64 * L));
+        }
+    }
+    sys0[h->nsys] = (int32_t)row0.size();
+    const size_t npos = (size_t)off.back();
+    std::vector<int32_t> col(npos, -1), src(npos, -1);
+    for (int s = 0; s < h->nsys; ++s) {
+        const int64_t b = h->sys_off[s + 1];
+        for (int32_t q = sys0[s]; q < sys0[s + 1]; ++q)
+            for (int64_t i = row0[q]; i < std::min<int64_t>(b, (int64_t)row0[q] + 64); ++i)
+                for (int64_t k = ptr[i]; k < ptr[i + 1]; ++k) {
+                    const int64_t e = off[q] + (k - ptr[i]) * 64 + (i - row0[q]);
+                    col[e] = idx[k];
+                    src[e] = (int32_t)k;
+                }
+    }
+    // values: gathered on the device from the CSR copy through src
+    std::vector<void *> tmp;
+    int32_t *dsrc = nullptr;
+    int st;
+    if ((st = bupload(h, h->allocs, &h->sl_row, row0.data(), row0.size())) != CG_OK ||
+        (st = bupload(h, h->allocs, &h->sl_off, off.data(), off.size())) != CG_OK ||
+        (st = bupload(h, h->allocs, &h->sl_col, col.data(), col.size())) != CG_OK ||
+        (st = balloc(h, h->allocs, &h->sl_val, npos)) != CG_OK || (st = bupload(h, tmp, &dsrc, src.data(), npos)) != CG_OK) {
+        free_list(tmp);
+        return st;
+    }
+    launch_permute((int64_t)npos, h->val, dsrc, h->sl_val, h->stream);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(h->stream);
+    free_list(tmp);
+    if (e != hipSuccess)
+        return bfail(h, e, "sliced values");
+    h->hsl_row.swap(row0);
+    h->hsl_sys0.swap(sys0);
+    return CG_OK;
+}
+
+// Workgroup split over the slices: system s gets max(1, round(wg_target *
+// nnz_s / nnz)) workgroups (at most one per slice), each a contiguous run of
+// its slices.
+int build_plan_slices(cg_batch *h, int wg_target)
+{
+    int st = ensure_slices(h);
+    if (st != CG_OK)
+        return st;
+    const int32_t *ptr = h->hptr.data();
+    std::vector<WgDesc> w;
+    std::vector<int32_t> wg0(h->nsys);
+    for (int s = 0; s < h->nsys; ++s) {
+        const int q0 = h->hsl_sys0[s], nq = h->hsl_sys0[s + 1] - q0;
+        const int64_t nnzs = (int64_t)ptr[h->sys_off[s + 1]] - ptr[h->sys_off[s]];
+        int g = (int)std::llround((double)wg_target * (double)nnzs / (double)std::max<int64_t>(h->nnz, 1));
+        g = std::max(1, std::min(g, nq));
+        wg0[s] = (int32_t)w.size();
+        for (int k = 0; k < g; ++k) {
+            WgDesc d{};
+            d.sys = s;
+            d.lead = k == 0;
+            d.rb0 = q0 + (int)((int64_t)k * nq / g);
+            d.rb1 = q0 + (int)((int64_t)(k + 1) * nq / g);
+            d.i0 = h->hsl_row[d.rb0];
+            d.i1 = d.rb1 < q0 + nq ? h->hsl_row[d.rb1] : (int32_t)h->sys_off[s + 1];
+            w.push_back(d);
+        }
+    }
+    for (auto &d : w) {
+        d.wg0 = wg0[d.sys];
+        d.wg1 = d.sys + 1 < h->nsys ? wg0[d.sys + 1] : (int32_t)w.size();
+    }
+    drop_graph(h);
+    free_list(h->plan_allocs);
+    const size_t np = w.size() * (size_t)h->R;
+    if ((st = bupload(h, h->plan_allocs, &h->wgs, w.data(), w.size())) != CG_OK ||
+        (st = bupload(h, h->plan_allocs, &h->sys_wg0, wg0.data(), wg0.size())) != CG_OK ||
+        (st = balloc(h, h->plan_allocs, &h->sig, np)) != CG_OK ||
+        (st = balloc(h, h->plan_allocs, &h->rho, np)) != CG_OK ||
+        (st = balloc(h, h->plan_allocs, &h->bb, np)) != CG_OK)
+        return st;
+    h->rb_row = nullptr;
+    h->G = (int)w.size();
+    h->nrb = 0;
+    h->wg_target = wg_target;
+    h->lanes = 1;
+    return CG_OK;
+}
+
 template <int R, int EPT>
 void spmm_r(cg_batch *h, const double *P, double *Q, Inst *inst, hipStream_t s)
 {
@@ -716,8 +925,37 @@ void spmm_lanes(cg_batch *h, const double *P, double *Q, Inst *inst, hipStream_t
                            h->val, P, Q, h->sig, inst);
 }
 
+template <int R>
+void spmm_slices(cg_batch *h, const double *P, double *Q, Inst *inst, hipStream_t s)
+{
+    constexpr int U = R == 4 ? 4 : 8; // positions per round (registers: 11 per position at R = 4)
+    hipLaunchKernelGGL((k_bspmm_slices<R, U>), dim3(h->G), dim3(kBlock), 0, s, h->wgs, h->sl_row, h->sl_off,
+                       h->sl_col, h->sl_val, P, Q, h->sig, inst);
+}
+
+// the product of the current plan and schedule
+template <int R>
+void spmm_any(cg_batch *h, const double *P, double *Q, Inst *inst, hipStream_t s)
+{
+    if (h->lanes == 1)
+        spmm_slices<R>(h, P, Q, inst, s);
+    else if (h->lanes)
+        spmm_lanes<R>(h, P, Q, inst, s);
+    else
+        spmm_e<R>(h, P, Q, inst, s);
+}
+
 void spmm(cg_batch *h, const double *P, double *Q, Inst *inst, hipStream_t s)
 {
+    if (h->lanes == 1) {
+        if (h->R == 1)
+            spmm_slices<1>(h, P, Q, inst, s);
+        else if (h->R == 2)
+            spmm_slices<2>(h, P, Q, inst, s);
+        else
+            spmm_slices<4>(h, P, Q, inst, s);
+        return;
+    }
     if (h->lanes) {
         if (h->R == 1)
             spmm_lanes<1>(h, P, Q, inst, s);
@@ -738,7 +976,7 @@ void spmm(cg_batch *h, const double *P, double *Q, Inst *inst, hipStream_t s)
 template <int R>
 void iteration_r(cg_batch *h, hipStream_t s)
 {
-    spmm_e<R>(h, h->P, h->Q, h->inst, s);
+    spmm_any<R>(h, h->P, h->Q, h->inst, s);
     hipLaunchKernelGGL(k_bupdate_r<R>, dim3(h->G), dim3(kBlock), 0, s, h->wgs, h->Rv, h->Q, h->inst, h->sig, h->rho);
     hipLaunchKernelGGL(k_bupdate_xp<R>, dim3(h->G), dim3(kBlock), 0, s, h->wgs, h->Xw, h->P, h->Rv, h->inst, h->rho);
 }
@@ -757,7 +995,7 @@ template <int R>
 void init_r(cg_batch *h, const double *B, const double *X0, double tol, int maxit, hipStream_t s)
 {
     const int ninst = h->nsys * R;
-    spmm_e<R>(h, X0, h->Q, nullptr, s);
+    spmm_any<R>(h, X0, h->Q, nullptr, s);
     hipLaunchKernelGGL(k_binit_vec<R>, dim3(h->G), dim3(kBlock), 0, s, h->wgs, B, X0, h->Q, h->Rv, h->P, h->Xw,
                        h->rho, h->bb);
     hipLaunchKernelGGL(k_binit_state<R>, dim3((ninst + kBlock - 1) / kBlock), dim3(kBlock), 0, s, h->wgs,
@@ -767,7 +1005,7 @@ void init_r(cg_batch *h, const double *B, const double *X0, double tol, int maxi
 template <int R>
 void finish_r(cg_batch *h, const double *B, double *X, hipStream_t s)
 {
-    spmm_e<R>(h, h->Xw, h->Q, nullptr, s);
+    spmm_any<R>(h, h->Xw, h->Q, nullptr, s);
     hipLaunchKernelGGL(k_bresid<R>, dim3(h->G), dim3(kBlock), 0, s, h->wgs, B, h->Q, h->bb);
     hipLaunchKernelGGL(k_bfinish<R>, dim3(h->G), dim3(kBlock), 0, s, h->wgs, h->sys_wg0, h->inst, h->bb, h->Xw, X);
 }
@@ -898,9 +1136,18 @@ int cg_batch_create(cg_batch **out, int32_t nsys, const int64_t *sys_off, const 
             return st;
         }
         // schedule override (tests, experiments): CGMI_BATCH_LANES=8 or 16
+        // (lanes per row), 1 (the sliced layout)
         if (const char *ev = std::getenv("CGMI_BATCH_LANES")) {
             const int l = std::atoi(ev);
-            h->lanes = (l == 8 || l == 16) ? l : 0;
+            if (l == 1)
+                st = build_plan_slices(h.get(), 4096);
+            else
+                h->lanes = (l == 8 || l == 16) ? l : 0;
+            if (st != CG_OK) {
+                g_berr = h->err;
+                release(h.get());
+                return st;
+            }
         }
     } catch (const std::bad_alloc &) {
         g_berr = "host allocation failed";
@@ -939,9 +1186,9 @@ int cg_batch_autotune(cg_batch *h, int32_t *entries_per_block, int32_t *lanes_pe
     // LDS, or 8 / 16 lanes per row) x workgroup budget; each timed on 10
     // products of a fixed vector after one warm-up
     struct Cand {
-        int ept, lanes;
+        int ept, lanes; // lanes = 1: the sliced layout (ept unused)
     };
-    const Cand cands[5] = {{1, 0}, {2, 0}, {4, 0}, {4, 8}, {4, 16}};
+    const Cand cands[6] = {{1, 0}, {2, 0}, {4, 0}, {4, 8}, {4, 16}, {0, 1}};
     const int wgt_all[3] = {1024, 2048, 4096};
     const size_t nv = (size_t)h->N * h->R;
     double *X = nullptr, *Y = nullptr;
@@ -961,7 +1208,7 @@ int cg_batch_autotune(cg_batch *h, int32_t *entries_per_block, int32_t *lanes_pe
     int best_e = h->ept, best_l = h->lanes, best_w = h->wg_target, st = CG_OK;
     for (const Cand &cd : cands) {
         for (int wgt : wgt_all) {
-            if ((st = build_plan(h, cd.ept, wgt)) != CG_OK)
+            if ((st = cd.lanes == 1 ? build_plan_slices(h, 2 * wgt) : build_plan(h, cd.ept, wgt)) != CG_OK)
                 break;
             h->lanes = cd.lanes;
             spmm(h, X, Y, nullptr, h->stream);
@@ -976,7 +1223,7 @@ int cg_batch_autotune(cg_batch *h, int32_t *entries_per_block, int32_t *lanes_pe
                 best = ms;
                 best_e = cd.ept;
                 best_l = cd.lanes;
-                best_w = wgt;
+                best_w = cd.lanes == 1 ? 2 * wgt : wgt;
             }
         }
         if (st != CG_OK)
@@ -987,10 +1234,10 @@ int cg_batch_autotune(cg_batch *h, int32_t *entries_per_block, int32_t *lanes_pe
     (void)hipFree(X);
     (void)hipFree(Y);
     if (st == CG_OK)
-        st = build_plan(h, best_e, best_w);
+        st = best_l == 1 ? build_plan_slices(h, best_w) : build_plan(h, best_e, best_w);
     h->lanes = best_l;
     if (entries_per_block)
-        *entries_per_block = kBlock * h->ept;
+        *entries_per_block = best_l == 1 ? 0 : kBlock * h->ept;
     if (lanes_per_row)
         *lanes_per_row = h->lanes;
     if (workgroups)

