@@ -189,9 +189,10 @@ def main():
     sliced = solvers[dom].stats()["slices"] == 1
     kernel_name = {"csr": "k_spmv_slices (CSR product, 64-row slices)" if sliced else
                           "k_spmv_csr_rows (CSR product, row blocks)",
-                   "symcsr": "k_scatter_sums + k_scatter_gather (symmetric-CSR product)",
+                   "symcsr": ("k_scatter_slices" if sliced else "k_scatter_sums") +
+                             " + k_scatter_gather (symmetric-CSR product)",
                    "csc": ("k_spmv_slices" if sliced else "k_panel_rows") +
-                          " + k_scatter_gather (CSC product on column panels)"}[dom]
+                          " + k_panel_gather (CSC product on column panels)"}[dom]
     traffic = load_traffic(dom)
     roofline = dict(bound="hbm", achieved=round(spmv[dom]["GBps"], 1), peak=HBM_PEAK_GBPS, unit="GB/s",
                     frac=round(spmv[dom]["GBps"] / HBM_PEAK_GBPS, 4), traffic=traffic, kernel=kernel_name,
