@@ -221,7 +221,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv_csr_rows(int nrb, const int2 *_
 // panel slots; a colour-0 slot stores y[target], a colour-1 slot parks its
 // sum at part[target] for the row pass.  Fused epilogue: partial of x'y (linear in the line
 // sums, so x_target * sum per line).
-template <bool PANEL, class VT, class PT>
+template <bool PANEL, int S, class VT, class PT>
 __global__ __launch_bounds__(kBlock) void k_spmv_slices(int nl, int ns, const int32_t *__restrict__ off,
                                                         const int32_t *__restrict__ col, const VT *__restrict__ val,
                                                         const PT *__restrict__ x, double *__restrict__ y,
@@ -238,38 +238,58 @@ __global__ __launch_bounds__(kBlock) void k_spmv_slices(int nl, int ns, const in
     const int s1 = (int)((int64_t)(wg + 1) * ns / gridDim.x);
     const int lane = threadIdx.x & 63;
     double sig = 0.0;
-    for (int sl = s0 + (int)(threadIdx.x >> 6); sl < s1; sl += kWaves) {
-        const int e0 = off[sl], len = (off[sl + 1] - e0) / kSliceRows;
-        const int l = sl * kSliceRows + lane;
-        int tg = l;
-        if (PANEL)
-            tg = l < nl ? __builtin_nontemporal_load(target + l) : -1;
-        double a = 0.0;
-        for (int k0 = 0; k0 < len; k0 += U) {
-            int c[U];
-            double v[U], xv[U];
+    // S slices per wave at a time (sl, sl + kWaves, ...): their loads are
+    // issued together, so a wave with several slices keeps S chains in flight
+    for (int sl = s0 + (int)(threadIdx.x >> 6); sl < s1; sl += S * kWaves) {
+        int e0[S], len[S], l[S], tg[S];
+        double a[S];
+        int lmax = 0;
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const bool ok = k0 + u < len;
-                const int e = e0 + (k0 + u) * kSliceRows + lane;
-                c[u] = ok ? __builtin_nontemporal_load(col + e) : -1;
-                v[u] = ok ? (double)__builtin_nontemporal_load(val + e) : 0.0;
+        for (int j = 0; j < S; ++j) {
+            const int q = sl + j * kWaves;
+            const bool has = q < s1;
+            e0[j] = has ? off[q] : 0;
+            len[j] = has ? (off[q + 1] - e0[j]) / kSliceRows : 0;
+            l[j] = has ? q * kSliceRows + lane : nl;
+            tg[j] = l[j];
+            if (PANEL)
+                tg[j] = l[j] < nl ? __builtin_nontemporal_load(target + l[j]) : -1;
+            a[j] = 0.0;
+            lmax = max(lmax, len[j]);
+        }
+        for (int k0 = 0; k0 < lmax; k0 += U) {
+            int c[S][U];
+            double v[S][U], xv[S][U];
+#pragma unroll
+            for (int j = 0; j < S; ++j)
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const bool ok = k0 + u < len[j];
+                    const int e = e0[j] + (k0 + u) * kSliceRows + lane;
+                    c[j][u] = ok ? __builtin_nontemporal_load(col + e) : -1;
+                    v[j][u] = ok ? (double)__builtin_nontemporal_load(val + e) : 0.0;
+                }
+#pragma unroll
+            for (int j = 0; j < S; ++j)
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+                    xv[j][u] = c[j][u] >= 0 ? (double)x[c[j][u]] : 0.0;
+#pragma unroll
+            for (int j = 0; j < S; ++j)
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+                    if (c[j][u] >= 0)
+                        a[j] = a[j] + v[j][u] * xv[j][u];
+        }
+#pragma unroll
+        for (int j = 0; j < S; ++j)
+            if (l[j] < nl) {
+                if (!PANEL || l[j] < first_parked)
+                    y[tg[j]] = a[j];
+                else
+                    part[tg[j]] = a[j]; // parked by row: at most one colour-1 slot per row
+                sig = fma((double)x[tg[j]], a[j], sig);
             }
-#pragma unroll
-            for (int u = 0; u < U; ++u)
-                xv[u] = c[u] >= 0 ? (double)x[c[u]] : 0.0;
-#pragma unroll
-            for (int u = 0; u < U; ++u)
-                if (c[u] >= 0)
-                    a = a + v[u] * xv[u];
-        }
-        if (l < nl) {
-            if (!PANEL || l < first_parked)
-                y[tg] = a;
-            else
-                part[tg] = a; // parked by row: at most one colour-1 slot per row
-            sig = fma((double)x[tg], a, sig);
-        }
     }
     sig = block_sum(sig, red);
     if (threadIdx.x == 0)
@@ -1095,6 +1115,15 @@ inline const float *panel_vals(const DevMatrix &m, const float *) { return m.pn_
 inline const double *slice_vals(const DevMatrix &m, const double *) { return m.sl_val; }
 inline const float *slice_vals(const DevMatrix &m, const float *) { return m.sl_val32; }
 
+template <bool PANEL, int S, class VT, class PT>
+void slices_launch(const DevMatrix &m, const VT *val, const PT *x, double *y, double *sig_part, const IterCtx &c,
+                   hipStream_t s)
+{
+    hipLaunchKernelGGL((k_spmv_slices<PANEL, S, VT, PT>), dim3(m.csr_blocks), dim3(kBlock), 0, s, m.sl_lines,
+                       m.nslices, m.sl_off, m.sl_col, val, x, y, PANEL ? m.pn_slot_target : nullptr,
+                       PANEL ? m.part : nullptr, PANEL ? m.pn_first_parked : 0, sig_part, c.st);
+}
+
 template <class VT, class PT>
 void spmv_any(const DevMatrix &m, const VT *val, const PT *x, double *y, double *sig_part, const IterCtx &c,
               hipStream_t s)
@@ -1102,14 +1131,18 @@ void spmv_any(const DevMatrix &m, const VT *val, const PT *x, double *y, double 
     if (m.n == 0)
         return;
     if (m.slices) {
-        if (m.panel)
-            hipLaunchKernelGGL((k_spmv_slices<true, VT, PT>), dim3(m.csr_blocks), dim3(kBlock), 0, s, m.sl_lines,
-                               m.nslices, m.sl_off, m.sl_col, slice_vals(m, val), x, y, m.pn_slot_target, m.part,
-                               m.pn_first_parked, sig_part, c.st);
+        // two slices per wave at a time once the waves average 1.5 or more, for
+        // FP64 values (160^3: 163 -> 158 us; the FP32 product of mixed
+        // precision measured slower that way, 150 -> 209 us, and keeps one)
+        const bool two = sizeof(VT) == 8 && 2 * (int64_t)m.nslices >= (int64_t)3 * kWaves * m.csr_blocks;
+        if (m.panel && two)
+            slices_launch<true, 2>(m, slice_vals(m, val), x, y, sig_part, c, s);
+        else if (m.panel)
+            slices_launch<true, 1>(m, slice_vals(m, val), x, y, sig_part, c, s);
+        else if (two)
+            slices_launch<false, 2>(m, slice_vals(m, val), x, y, sig_part, c, s);
         else
-            hipLaunchKernelGGL((k_spmv_slices<false, VT, PT>), dim3(m.csr_blocks), dim3(kBlock), 0, s, m.sl_lines,
-                               m.nslices, m.sl_off, m.sl_col, slice_vals(m, val), x, y, nullptr, nullptr, 0,
-                               sig_part, c.st);
+            slices_launch<false, 1>(m, slice_vals(m, val), x, y, sig_part, c, s);
     } else if (m.panel && m.nblocks > 0) {
         hipLaunchKernelGGL((k_panel_rows<VT, PT>), dim3(m.scatter_wgs), dim3(kBlock), 0, s, m.nblocks,
                            m.pn_chunk_slot, m.pn_slot_ptr, m.pn_slot_target, m.pn_col, panel_vals(m, val), x, y,

@@ -132,9 +132,10 @@ def test_layouts_in_iterations(monkeypatch, fmt, layout):
 
 
 def test_early_iterates_8192_partials():
-    # 2.2M-row tridiagonal SPD matrix: the sliced product runs on 8192
-    # workgroups (several slices per wave) and the r update sums 8192 partials
-    n = 2_200_000
+    # 3.3M-row tridiagonal SPD matrix: the sliced product runs on 8192
+    # workgroups (two slices per wave at a time) and the r update sums 8192
+    # partials
+    n = 3_300_000
     lens = np.full(n, 3)
     lens[0] = lens[-1] = 2
     ptr = np.zeros(n + 1, np.int32)

@@ -238,9 +238,9 @@ def test_csr_slices_ragged_shapes(monkeypatch, n):
 
 
 def test_csr_slices_several_per_wave():
-    # more than 4 x 8192 slices: waves take several slices, and the product
-    # leaves 8192 dot partials
-    n = 2_200_000
+    # 51 563 slices on 8192 workgroups: waves take two slices at a time, and
+    # the product leaves 8192 dot partials
+    n = 3_300_000
     ptr = np.zeros(n + 1, np.int32)
     lens = np.full(n, 3)
     lens[0] = lens[-1] = 2
@@ -251,7 +251,7 @@ def test_csr_slices_several_per_wave():
     val = np.where(col == i, 2.0, -1.0) + 1e-3 * W.uniform_vector(ptr[-1], seed=30)
     st, stats = cgmi.cg_analyze(CSR, n, ptr, col, val)
     assert st == 0 and stats["slices"] == 1 and stats["spmv_blocks"] == 8192
-    y, yo = check_spmv(CSR, ptr, col, val, W.uniform_vector(n, seed=31), label="2.2M rows, 3 per row")
+    y, yo = check_spmv(CSR, ptr, col, val, W.uniform_vector(n, seed=31), label="3.3M rows, 3 per row")
     assert np.array_equal(y, yo)
 
 
