@@ -98,6 +98,10 @@ typedef struct {
     int32_t max_block_entries;
     int32_t slices;          /* 1 = sliced layout (CSR: 64-row slices; CSC: 64-slot slices;
                                 symmetric CSR: blocks stored k-th entry first) */
+    int32_t cached_loads;    /* 1 = the sliced product reads the matrix with ordinary loads, so that
+                                it stays in the Infinity Cache between iterations (small enough);
+                                0 = non-temporal loads */
+    int32_t reserved;
     int64_t slots;           /* scatter formats: total (block, target) write slots */
     int64_t plan_bytes;      /* device bytes of the plan beyond ptr / idx / vals */
 } cg_plan_stats;

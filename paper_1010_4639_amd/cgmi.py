@@ -47,11 +47,12 @@ class cg_plan_stats(ctypes.Structure):
                 ("lanes_per_line", ctypes.c_int32), ("spmv_blocks", ctypes.c_int32),
                 ("vec_blocks", ctypes.c_int32), ("colors", ctypes.c_int32),
                 ("scatter_blocks", ctypes.c_int32), ("max_block_entries", ctypes.c_int32),
-                ("slices", ctypes.c_int32), ("slots", ctypes.c_int64),
+                ("slices", ctypes.c_int32),
+                ("cached_loads", ctypes.c_int32), ("reserved", ctypes.c_int32), ("slots", ctypes.c_int64),
                 ("plan_bytes", ctypes.c_int64)]
 
     def as_dict(self):
-        return {f: getattr(self, f) for f, _ in self._fields_}
+        return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
 
 
 class CgError(RuntimeError):

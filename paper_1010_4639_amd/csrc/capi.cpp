@@ -141,6 +141,7 @@ int upload_all(cg_handle *h, const std::vector<int32_t> &ptr0, const std::vector
     m.color_off = p.color_off;
     m.vec_blocks = p.vec_blocks;
     m.vec_chunk = p.vec_chunk;
+    m.matrix_cached = p.matrix_cached();
     int st;
     int32_t *dptr, *didx;
     double *dval;
@@ -374,6 +375,7 @@ void fill_stats(const Plan &p, cg_plan_stats *s)
     s->colors = p.ncolors;
     s->max_block_entries = p.max_entries;
     s->slices = p.slices || p.sym_slices ? 1 : 0;
+    s->cached_loads = p.matrix_cached() ? 1 : 0;
     s->slots = p.panel ? (int64_t)p.pn_slot_target.size() : (int64_t)p.slot_target.size();
     s->plan_bytes = p.device_bytes();
 }

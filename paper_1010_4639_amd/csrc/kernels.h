@@ -89,6 +89,9 @@ struct DevMatrix {
     double *pn_val = nullptr;             // values in panel order (from val through pn_src)
     float *pn_val32 = nullptr;            // mixed precision: val32 in panel order
     int pn_first_parked = 0;
+    // sliced kernels: ordinary (cache-allocating) loads of the matrix streams
+    // when the product's bytes fit the Infinity Cache, non-temporal otherwise
+    bool matrix_cached = false;
     // vectors
     int vec_blocks = 0, vec_chunk = 0;
     int spmv_blocks() const { return format == kCsr || slices ? csr_blocks : scatter_wgs; }

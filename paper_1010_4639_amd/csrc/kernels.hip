@@ -17,6 +17,19 @@ namespace {
 
 using namespace dev;
 
+// Loads of the matrix streams.  NT: non-temporal (read once per product, do
+// not displace the vectors); otherwise ordinary loads, so that a matrix that
+// fits the 256 MB Infinity Cache together with the vectors stays resident
+// from one CG iteration to the next.
+template <bool NT, class T>
+__device__ __forceinline__ T matrix_load(const T *p)
+{
+    if constexpr (NT)
+        return __builtin_nontemporal_load(p);
+    else
+        return *p;
+}
+
 // Start of an iteration (before its product): stop when the current residual
 // meets the tolerance (decided and published by the previous x/p update, or by
 // the initialisation) or maxit products are done.  Every workgroup reads the
@@ -221,7 +234,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv_csr_rows(int nrb, const int2 *_
 // panel slots; a colour-0 slot stores y[target], a colour-1 slot parks its
 // sum at part[target] for the row pass.  Fused epilogue: partial of x'y (linear in the line
 // sums, so x_target * sum per line).
-template <bool PANEL, int S, class VT, class PT>
+template <bool PANEL, int S, bool NT, class VT, class PT>
 __global__ __launch_bounds__(kBlock) void k_spmv_slices(int nl, int ns, const int32_t *__restrict__ off,
                                                         const int32_t *__restrict__ col, const VT *__restrict__ val,
                                                         const PT *__restrict__ x, double *__restrict__ y,
@@ -253,7 +266,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv_slices(int nl, int ns, const in
             l[j] = has ? q * kSliceRows + lane : nl;
             tg[j] = l[j];
             if (PANEL)
-                tg[j] = l[j] < nl ? __builtin_nontemporal_load(target + l[j]) : -1;
+                tg[j] = l[j] < nl ? matrix_load<NT>(target + l[j]) : -1;
             a[j] = 0.0;
             lmax = max(lmax, len[j]);
         }
@@ -266,8 +279,8 @@ __global__ __launch_bounds__(kBlock) void k_spmv_slices(int nl, int ns, const in
                 for (int u = 0; u < U; ++u) {
                     const bool ok = k0 + u < len[j];
                     const int e = e0[j] + (k0 + u) * kSliceRows + lane;
-                    c[j][u] = ok ? __builtin_nontemporal_load(col + e) : -1;
-                    v[j][u] = ok ? (double)__builtin_nontemporal_load(val + e) : 0.0;
+                    c[j][u] = ok ? matrix_load<NT>(col + e) : -1;
+                    v[j][u] = ok ? (double)matrix_load<NT>(val + e) : 0.0;
                 }
 #pragma unroll
             for (int j = 0; j < S; ++j)
@@ -540,7 +553,7 @@ __global__ __launch_bounds__(kBlock) void k_scatter_sums(
 // rounded products (the same bits as the LDS sum), and parks only the mirror
 // products a_e x_l in LDS, where the slot sums read them through the
 // contribution list (local positions).  Two barriers per block, no line map.
-template <int SU, class VT, class PT>
+template <int SU, bool NT, class VT, class PT>
 __global__ __launch_bounds__(kBlock) void k_scatter_slices(
     const int32_t *__restrict__ sidx, const VT *__restrict__ sval, const int2 *__restrict__ sblk,
     const PT *__restrict__ x, double *__restrict__ y, double *__restrict__ part, double *__restrict__ sig_part,
@@ -573,8 +586,8 @@ __global__ __launch_bounds__(kBlock) void k_scatter_slices(
         for (int m = 0; m < E; ++m) {
             const bool ok = mine && m < L;
             const int q = sb.x + m * nl + t;
-            c[m] = ok ? __builtin_nontemporal_load(sidx + q) : -1;
-            v[m] = ok ? (double)__builtin_nontemporal_load(sval + q) : 0.0;
+            c[m] = ok ? matrix_load<NT>(sidx + q) : -1;
+            v[m] = ok ? (double)matrix_load<NT>(sval + q) : 0.0;
         }
         const double xo = mine ? (double)x[bk.line0 + t] : 0.0;
         int tg[SU], lo[SU], hi[SU];
@@ -1065,9 +1078,14 @@ template <int SU, class VT, class PT>
 void scatter_slices_launch(const DevMatrix &m, const VT *val, const PT *x, double *y, double *sig, const IterCtx &c,
                            hipStream_t s)
 {
-    hipLaunchKernelGGL((k_scatter_slices<SU, VT, PT>), dim3(m.scatter_wgs), dim3(kBlock), 0, s, m.ss_idx,
-                       sym_slice_vals(m, val), m.ss_blk, x, y, m.part, sig, m.blocks, m.nblocks, m.slot_target,
-                       m.seg, m.tl, c.st);
+    if (m.matrix_cached)
+        hipLaunchKernelGGL((k_scatter_slices<SU, false, VT, PT>), dim3(m.scatter_wgs), dim3(kBlock), 0, s, m.ss_idx,
+                           sym_slice_vals(m, val), m.ss_blk, x, y, m.part, sig, m.blocks, m.nblocks, m.slot_target,
+                           m.seg, m.tl, c.st);
+    else
+        hipLaunchKernelGGL((k_scatter_slices<SU, true, VT, PT>), dim3(m.scatter_wgs), dim3(kBlock), 0, s, m.ss_idx,
+                           sym_slice_vals(m, val), m.ss_blk, x, y, m.part, sig, m.blocks, m.nblocks, m.slot_target,
+                           m.seg, m.tl, c.st);
     if (m.ncolors > 1 && !c.defer_rows)
         hipLaunchKernelGGL(k_scatter_gather, dim3((m.n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, m.n, m.rs_ptr,
                            m.rs_idx, m.has_c0, m.part, y, c.st);
@@ -1115,13 +1133,23 @@ inline const float *panel_vals(const DevMatrix &m, const float *) { return m.pn_
 inline const double *slice_vals(const DevMatrix &m, const double *) { return m.sl_val; }
 inline const float *slice_vals(const DevMatrix &m, const float *) { return m.sl_val32; }
 
+template <bool PANEL, int S, bool NT, class VT, class PT>
+void slices_launch_nt(const DevMatrix &m, const VT *val, const PT *x, double *y, double *sig_part, const IterCtx &c,
+                      hipStream_t s)
+{
+    hipLaunchKernelGGL((k_spmv_slices<PANEL, S, NT, VT, PT>), dim3(m.csr_blocks), dim3(kBlock), 0, s, m.sl_lines,
+                       m.nslices, m.sl_off, m.sl_col, val, x, y, PANEL ? m.pn_slot_target : nullptr,
+                       PANEL ? m.part : nullptr, PANEL ? m.pn_first_parked : 0, sig_part, c.st);
+}
+
 template <bool PANEL, int S, class VT, class PT>
 void slices_launch(const DevMatrix &m, const VT *val, const PT *x, double *y, double *sig_part, const IterCtx &c,
                    hipStream_t s)
 {
-    hipLaunchKernelGGL((k_spmv_slices<PANEL, S, VT, PT>), dim3(m.csr_blocks), dim3(kBlock), 0, s, m.sl_lines,
-                       m.nslices, m.sl_off, m.sl_col, val, x, y, PANEL ? m.pn_slot_target : nullptr,
-                       PANEL ? m.part : nullptr, PANEL ? m.pn_first_parked : 0, sig_part, c.st);
+    if (m.matrix_cached)
+        slices_launch_nt<PANEL, S, false>(m, val, x, y, sig_part, c, s);
+    else
+        slices_launch_nt<PANEL, S, true>(m, val, x, y, sig_part, c, s);
 }
 
 template <class VT, class PT>

@@ -29,6 +29,26 @@ int64_t Plan::device_bytes() const
            (int64_t)ss_src.size() * (4 + 4 + 8);
 }
 
+int64_t Plan::slice_stream_bytes() const
+{
+    if (slices) // positions, slice offsets; CSC: slot targets, parked sums written and read
+        return (int64_t)sl_src.size() * 12 + (int64_t)sl_off.size() * 4 +
+               (panel ? (int64_t)pn_slot_target.size() * 4 + n * 17 : 0);
+    if (sym_slices) // positions; slot targets, segments, flags; contributions; parked sums and row lists
+        return (int64_t)ss_src.size() * 12 + (int64_t)slot_target.size() * (4 + 2 + 1 + 8 + 8 + 4) +
+               (int64_t)tl.size() * 2 + n * 5;
+    return 0;
+}
+
+static bool decide_cached(const Plan &p)
+{
+    const int64_t mb = p.slice_stream_bytes();
+    bool c = mb > 0 && mb + 40 * p.n <= kCacheResidentBytes;
+    if (const char *e = std::getenv("CGMI_MATRIX_LOADS"))
+        c = mb > 0 && (std::strcmp(e, "cached") == 0 ? true : std::strcmp(e, "stream") == 0 ? false : c);
+    return c;
+}
+
 int lanes_for_mean_length(double mean_len)
 {
     int w = 4;
@@ -642,16 +662,22 @@ int build_plan(int fmt, int64_t n, const int32_t *ptr0, const int32_t *idx0, int
     plan_vectors(p);
     if (fmt == kCsr) {
         plan_csr(p, ptr0, idx0);
+        p.cached = decide_cached(p);
         return CG_OK;
     }
-    if (fmt == kCsc)
-        return plan_panels(p, ptr0, idx0, err);
+    if (fmt == kCsc) {
+        const int st = plan_panels(p, ptr0, idx0, err);
+        p.cached = st == CG_OK && decide_cached(p);
+        return st;
+    }
     if (target_entries <= 0)
         target_entries = (int)block_entries(p.nnz, 512);
     target_entries = std::min(target_entries, kMaxScatterEntries);
     const int st = plan_scatter(p, ptr0, idx0, target_entries, err);
-    if (st == CG_OK)
+    if (st == CG_OK) {
         plan_sym_slices(p, ptr0, idx0, slice_mode());
+        p.cached = decide_cached(p);
+    }
     return st;
 }
 

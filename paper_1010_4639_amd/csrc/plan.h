@@ -58,6 +58,13 @@ constexpr int kSliceRows = 64;          // slices: lines per slice (one wavefron
 constexpr int kWavesPerBlock = kBlock / kSliceRows;
 constexpr int kMaxSliceWgs = 4 * kMaxSpmvBlocks; // slice kernel workgroups (= dot partials)
 constexpr double kSliceMaxPadding = 0.125; // slices only while padding <= this fraction of nnz
+// Sliced products read the matrix with ordinary (cache-allocating) loads
+// while the bytes of one iteration (matrix side + 40 B per row of vectors)
+// stay below this, so the matrix stays resident in the 256 MB Infinity Cache
+// from one CG iteration to the next; non-temporal loads above.  Measured on
+// FEM systems: at 110^3 (~325 MB) ordinary loads are 6-12 % faster per
+// iteration, at 120^3 (~378 MB) 4-14 % slower.
+constexpr int64_t kCacheResidentBytes = 336ll << 20;
 constexpr int kPanelMinWidth = 4096;    // CSC panels span at least this many columns
 constexpr int kPanelChunkEntries = kStreamEntries; // entries per CSC panel chunk
 constexpr int kPanelChunkSlots = kBlock;           // slots per CSC panel chunk (one thread each)
@@ -125,6 +132,14 @@ struct Plan {
     // vector kernels
     int vec_blocks = 0, vec_chunk = 0;
 
+    // bytes one sliced product reads from the matrix side (positions, slot
+    // descriptors, contribution lists, parked sums); 0 if not sliced
+    int64_t slice_stream_bytes() const;
+    // ordinary instead of non-temporal matrix loads (kCacheResidentBytes;
+    // experiments: CGMI_MATRIX_LOADS = cached | stream); decided once by
+    // build_plan
+    bool cached = false;
+    bool matrix_cached() const { return cached; }
     int scatter_wgs() const { return nblocks < kMaxSpmvBlocks ? nblocks : kMaxSpmvBlocks; }
     int spmv_blocks() const { return format == kCsr || slices ? csr_blocks : scatter_wgs(); }
     int64_t device_bytes() const;

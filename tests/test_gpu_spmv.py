@@ -123,6 +123,26 @@ def test_sym_sliced_blocks_same_bits(monkeypatch, entries):
     assert np.array_equal(ys["rows"], ys["slices"])
 
 
+@pytest.mark.parametrize("fmt", [CSR, SYM, CSC])
+def test_matrix_loads_same_bits(monkeypatch, fmt):
+    # ordinary or non-temporal matrix loads: the same instructions otherwise,
+    # so the same bits, for the product and for a whole solve
+    s = W.fem_p1_system(20, 18, 16, seed=27)
+    arrs = three_formats(s)[fmt]
+    x = to_dev(W.uniform_vector(s.n, seed=28))
+    b = to_dev(s.b)
+    out = {}
+    for mode in ("cached", "stream"):
+        monkeypatch.setenv("CGMI_MATRIX_LOADS", mode)
+        with cgmi.Solver(fmt, *arrs) as S:
+            assert S.stats()["cached_loads"] == (mode == "cached")
+            xs, info = S.solve(b, tol=1e-10, maxit=5000)
+            out[mode] = (S.spmv(x).cpu().numpy(), xs.cpu().numpy(), info["iters"])
+    assert np.array_equal(out["cached"][0], out["stream"][0])
+    assert np.array_equal(out["cached"][1], out["stream"][1]) and out["cached"][2] == out["stream"][2]
+    check_spmv(fmt, *arrs, x.cpu().numpy(), label="loads")
+
+
 def test_split_long_row_symcsr(monkeypatch):
     monkeypatch.setenv("CGMI_SCATTER_ENTRIES", "32")
     n = 300

@@ -125,6 +125,36 @@ def test_csr_layout_choice(monkeypatch):
     assert st == 0 and stats["slices"] == 0
 
 
+def test_matrix_loads_choice(monkeypatch):
+    # ordinary (Infinity-Cache-resident) matrix loads while one iteration's
+    # bytes stay below 336 MiB, non-temporal above; the knob forces either
+    s = W.fem_config("fem32x32x30")
+    up = W.upper_triangle(s.rowptr, s.col, s.val)
+    for fmt, arrs in ((cgmi.CG_FMT_CSR, (s.rowptr, s.col, s.val)), (cgmi.CG_FMT_SYM_CSR, up),
+                      (cgmi.CG_FMT_CSC, (s.rowptr, s.col, s.val))):
+        st, stats = cgmi.cg_analyze(fmt, s.n, *arrs)
+        assert st == 0 and stats["slices"] == 1 and stats["cached_loads"] == 1
+    n = 5_000_000                      # tridiagonal: 15 M positions, 180 MB + 40 B per row > 336 MiB
+    lens = np.full(n, 3)
+    lens[0] = lens[-1] = 2
+    ptr = np.zeros(n + 1, np.int32)
+    ptr[1:] = np.cumsum(lens)
+    i = np.repeat(np.arange(n), lens)
+    col = (i + np.arange(ptr[-1]) - ptr[i] - (i > 0)).astype(np.int32)
+    st, stats = cgmi.cg_analyze(cgmi.CG_FMT_CSR, n, ptr, col, None)
+    assert st == 0 and stats["slices"] == 1 and stats["cached_loads"] == 0
+    monkeypatch.setenv("CGMI_MATRIX_LOADS", "cached")
+    st, stats = cgmi.cg_analyze(cgmi.CG_FMT_CSR, n, ptr, col, None)
+    assert st == 0 and stats["cached_loads"] == 1
+    monkeypatch.setenv("CGMI_MATRIX_LOADS", "stream")
+    st, stats = cgmi.cg_analyze(cgmi.CG_FMT_CSR, s.n, s.rowptr, s.col, s.val)
+    assert st == 0 and stats["cached_loads"] == 0
+    monkeypatch.setenv("CGMI_ROW_LAYOUT", "rows")          # only the sliced kernels have the choice
+    monkeypatch.setenv("CGMI_MATRIX_LOADS", "cached")
+    st, stats = cgmi.cg_analyze(cgmi.CG_FMT_CSR, s.n, s.rowptr, s.col, s.val)
+    assert st == 0 and stats["slices"] == 0 and stats["cached_loads"] == 0
+
+
 def _expected_targets(fmt, ptr, idx, e0, e1, l0, l1):
     rows = np.repeat(np.arange(len(ptr) - 1), np.diff(ptr))[e0:e1]
     cols = idx[e0:e1]
