@@ -144,13 +144,17 @@ def main():
         spmv[name] = dict(us=us, bytes=byts, GBps=byts / us / 1e3, colors=S.stats()["colors"])
         log(f"[bench] spmv {name}: {us:.1f} us/launch, {byts / 1e6:.1f} MB algorithmic, "
             f"{byts / us / 1e3:.0f} GB/s")
-    # cold products: a 1 GiB write evicts the matrix from the caches (L2, and
-    # the 256 MB Infinity Cache) before each single timed launch; median of 5
-    scratch = torch.empty(1 << 27, dtype=torch.float64, device=dev)
+    # cold products: a 1 GiB read evicts the matrix from the caches (L2, and
+    # the 256 MB Infinity Cache) before each single timed launch, leaving
+    # clean lines behind (a write would leave dirty ones to be written back
+    # during the timed launch); median of 5
+    scratch = torch.ones(1 << 27, dtype=torch.float64, device=dev)
+    flushed = torch.empty(1, dtype=torch.float64, device=dev)
+    torch.sum(scratch, dim=0, keepdim=True, out=flushed)
     for name, S in solvers.items():
         cold = []
         for i in range(5):
-            scratch.fill_(float(i))
+            torch.sum(scratch, dim=0, keepdim=True, out=flushed)
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             e0.record(stream)
             S.spmv(xs, ys)
@@ -160,7 +164,7 @@ def main():
         spmv[name]["cold_us"] = float(np.median(cold))
         log(f"[bench] spmv {name} cold: {spmv[name]['cold_us']:.1f} us/launch, "
             f"{spmv[name]['bytes'] / spmv[name]['cold_us'] / 1e3:.0f} GB/s")
-    del scratch
+    del scratch, flushed
     # plain device copy of 1 GiB for the practical bandwidth ceiling
     a = torch.empty(1 << 27, dtype=torch.float64, device=dev)
     c = torch.empty_like(a)
