@@ -928,7 +928,7 @@ void spmm_lanes(cg_batch *h, const double *P, double *Q, Inst *inst, hipStream_t
 template <int R>
 void spmm_slices(cg_batch *h, const double *P, double *Q, Inst *inst, hipStream_t s)
 {
-    constexpr int U = R == 4 ? 4 : 8; // positions per round (registers: 11 per position at R = 4)
+    constexpr int U = 8; // positions per round
     hipLaunchKernelGGL((k_bspmm_slices<R, U>), dim3(h->G), dim3(kBlock), 0, s, h->wgs, h->sl_row, h->sl_off,
                        h->sl_col, h->sl_val, P, Q, h->sig, inst);
 }
