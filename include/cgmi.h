@@ -158,10 +158,13 @@ int cg_solve(cg_handle *h, const double *b, double *x, double tol, int32_t maxit
  * product), all dot products and the alpha / beta recurrences stay FP64:
  *   r = b - A x ; repeat { solve (D^-1/2 A D^-1/2) c = D^-1/2 r by CG to
  *   ||r_c|| <= inner_tol ||D^-1/2 r|| ; x += D^-1/2 c ; r = b - A x }
- *   until ||r|| <= tol ||b|| (the TRUE residual).
+ *   until ||r|| <= tol ||b|| (the TRUE residual).  After an inner solve
+ *   that converged, the next one starts from the replaced residual but keeps
+ *   the search direction (residual replacement, as in reliable-update
+ *   Krylov solvers), so the refinement steps do not restart the iteration.
  *   b, x, tol    as in cg_solve
  *   maxit        >= 0: inner iterations allowed in total
- *   inner_tol    in (0, 1)
+ *   inner_tol    in (0, 1); 1e-2 was fastest on the 160^3 FEM system
  *   max_outer    >= 1: refinement steps allowed
  * Returns CG_OK, CG_NOT_CONVERGED (maxit or max_outer reached, x = last
  * iterate), CG_ERR_BREAKDOWN (an inner solve broke down before any

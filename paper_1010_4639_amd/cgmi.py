@@ -295,7 +295,7 @@ class Solver:
             raise CgError(st, cg_last_error(self.h))
         return x, d
 
-    def solve_mixed(self, b, x0=None, tol=1e-10, maxit=None, inner_tol=1e-4, max_outer=50, check=True):
+    def solve_mixed(self, b, x0=None, tol=1e-10, maxit=None, inner_tol=1e-2, max_outer=50, check=True):
         """FP64 refinement around FP32 inner CG (handle created with mixed=True)."""
         import torch
         x = torch.zeros_like(b) if x0 is None else x0.clone()

@@ -1,7 +1,7 @@
 """Time-to-tolerance of FP64 CG vs mixed-precision refinement on one system.
 
     python -m paper_1010_4639_amd.compare_mixed [--workload fem160] [--formats csr]
-        [--tol 1e-10] [--inner-tol 1e-4] [--reps 2]
+        [--tol 1e-10] [--inner-tol 1e-2] [--reps 2]
 
 For each format: the FP64 solve (cg_solve) and the mixed solve
 (cg_solve_mixed: FP32 product and search directions inside FP64 iterative
@@ -23,7 +23,7 @@ def main(argv=None):
     ap.add_argument("--workload", default="fem160")
     ap.add_argument("--formats", default="csr")
     ap.add_argument("--tol", type=float, default=1e-10)
-    ap.add_argument("--inner-tol", type=float, default=1e-4)
+    ap.add_argument("--inner-tol", type=float, default=1e-2)
     ap.add_argument("--maxit", type=int, default=200000)
     ap.add_argument("--reps", type=int, default=2)
     ap.add_argument("--cpu-iters", type=int, default=30)

@@ -380,6 +380,14 @@ void fill_stats(const Plan &p, cg_plan_stats *s)
     s->plan_bytes = p.device_bytes();
 }
 
+// experiments: CGMI_MIXED_RESTART=1 restarts every inner solve from p = r
+// instead of keeping the previous inner solve's next direction
+bool restart_inner()
+{
+    const char *e = std::getenv("CGMI_MIXED_RESTART");
+    return e && std::atoi(e) != 0;
+}
+
 int scatter_entries_override()
 {
     const char *e = std::getenv("CGMI_SCATTER_ENTRIES");
@@ -847,6 +855,7 @@ int cg_solve_mixed(cg_handle *h, const double *b, double *x, double tol, int32_t
     const double nb = out.nb;
     double relres = std::sqrt(out.rho) / nb;
     int total = 0, outer = 0, code = CG_NOT_CONVERGED;
+    bool keep_p = false; // the previous inner solve converged: its next direction carries over
     while (true) {
         if (relres <= tol) {
             code = CG_OK;
@@ -855,7 +864,7 @@ int cg_solve_mixed(cg_handle *h, const double *b, double *x, double tol, int32_t
         if (outer >= max_outer || total >= maxit)
             break;
         // inner solve of (D^-1/2 A D^-1/2) c = D^-1/2 r in FP32 storage
-        launch_mx_init(h->dm, h->rout, h->r, h->p32, h->p, h->rho, h->bb, s);
+        launch_mx_init(h->dm, h->rout, h->r, h->p32, h->p, h->rho, h->bb, s, keep_p && !restart_inner());
         launch_init_state(h->dm, h->st_in, h->bb, h->rho, inner_tol, maxit - total, s);
         int32_t status = kRun;
         if ((st = run_until_stop(h, h->gexec32, h->st_in, &status)) != CG_OK)
@@ -865,6 +874,7 @@ int cg_solve_mixed(cg_handle *h, const double *b, double *x, double tol, int32_t
             return done(st);
         total += in.iters;
         ++outer;
+        keep_p = in.status == kConverged && in.iters > 0;
         if (in.status == kBreakdown && in.iters == 0) {
             h->err = "inner FP32 solve broke down before any step";
             code = CG_ERR_BREAKDOWN;

@@ -127,9 +127,10 @@ void launch_update_xp(const DevMatrix &m, double *x, double *p, const double *r,
 // mixed precision: the same update with p stored in FP32
 void launch_update_xp32(const DevMatrix &m, double *x, float *p, const double *r, DevState *st,
                         const double *rho_part, hipStream_t s);
-// mixed precision: rh = D^-1/2 r_out, p = fl32(rh), c = 0, partials of rh'rh
+// mixed precision: rh = D^-1/2 r_out, p = fl32(rh) (unless keep_p: the
+// direction of the previous inner solve carries over), c = 0, partials of rh'rh
 void launch_mx_init(const DevMatrix &m, const double *r_out, double *rh, float *p, double *c, double *rho_part,
-                    double *bb_part, hipStream_t s);
+                    double *bb_part, hipStream_t s, bool keep_p);
 // mixed precision: x += D^-1/2 c
 void launch_mx_apply(const DevMatrix &m, double *x, const double *c, hipStream_t s);
 // st->rho = sum(rho_part), st->res_true = sqrt(st->rho) / st->nb (one workgroup)

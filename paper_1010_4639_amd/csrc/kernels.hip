@@ -242,6 +242,8 @@ __global__ __launch_bounds__(kBlock) void k_spmv_slices(int nl, int ns, const in
                                                         int first_parked, double *__restrict__ sig_part, DevState *st)
 {
 #pragma clang fp contract(off)
+    // positions per round (values and gathered x stay in their stored type
+    // until the multiply)
     constexpr int U = 8;
     __shared__ double red[kWaves];
     const int wg = xcd_remap(blockIdx.x, gridDim.x);
@@ -272,7 +274,8 @@ __global__ __launch_bounds__(kBlock) void k_spmv_slices(int nl, int ns, const in
         }
         for (int k0 = 0; k0 < lmax; k0 += U) {
             int c[S][U];
-            double v[S][U], xv[S][U];
+            VT v[S][U];
+            PT xv[S][U];
 #pragma unroll
             for (int j = 0; j < S; ++j)
 #pragma unroll
@@ -280,19 +283,19 @@ __global__ __launch_bounds__(kBlock) void k_spmv_slices(int nl, int ns, const in
                     const bool ok = k0 + u < len[j];
                     const int e = e0[j] + (k0 + u) * kSliceRows + lane;
                     c[j][u] = ok ? matrix_load<NT>(col + e) : -1;
-                    v[j][u] = ok ? (double)matrix_load<NT>(val + e) : 0.0;
+                    v[j][u] = ok ? matrix_load<NT>(val + e) : VT(0);
                 }
 #pragma unroll
             for (int j = 0; j < S; ++j)
 #pragma unroll
                 for (int u = 0; u < U; ++u)
-                    xv[j][u] = c[j][u] >= 0 ? (double)x[c[j][u]] : 0.0;
+                    xv[j][u] = c[j][u] >= 0 ? x[c[j][u]] : PT(0);
 #pragma unroll
             for (int j = 0; j < S; ++j)
 #pragma unroll
                 for (int u = 0; u < U; ++u)
                     if (c[j][u] >= 0)
-                        a[j] = a[j] + v[j][u] * xv[j][u];
+                        a[j] = a[j] + (double)v[j][u] * (double)xv[j][u];
         }
 #pragma unroll
         for (int j = 0; j < S; ++j)
@@ -817,10 +820,12 @@ __global__ __launch_bounds__(kBlock) void k_update_xp(int n, int chunk, double *
     const double rho_new = partials_sum(part, n_rho, red);
     const double alpha = st->alpha;
     const double beta = rho_new / st->rho;
-    const bool conv = sqrt(rho_new) <= st->tol_nb; // last step: x only
+    // last step: x only -- except for the FP32 directions of the mixed inner
+    // solve, whose next direction carries over to the next refinement step
+    const bool conv = sqrt(rho_new) <= st->tol_nb && sizeof(PT) == 8;
     if (blockIdx.x == 0 && t == 0) {
         st->rho_next = rho_new;
-        st->conv_next = conv ? 1 : 0;
+        st->conv_next = sqrt(rho_new) <= st->tol_nb ? 1 : 0;
     }
 #pragma unroll
     for (int u = 0; u < kPre; ++u) {
@@ -845,7 +850,8 @@ __global__ __launch_bounds__(kBlock) void k_update_xp(int n, int chunk, double *
 __global__ __launch_bounds__(kBlock) void k_mx_init(int n, int chunk, const double *__restrict__ r_out,
                                                     const double *__restrict__ s, double *__restrict__ rh,
                                                     float *__restrict__ p, double *__restrict__ c,
-                                                    double *__restrict__ rho_part, double *__restrict__ bb_part)
+                                                    double *__restrict__ rho_part, double *__restrict__ bb_part,
+                                                    int keep_p)
 {
     __shared__ double red[kWaves];
     const int blk = xcd_remap(blockIdx.x, gridDim.x);
@@ -854,7 +860,8 @@ __global__ __launch_bounds__(kBlock) void k_mx_init(int n, int chunk, const doub
     for (int i = i0 + threadIdx.x; i < i1; i += kBlock) {
         const double v = s[i] * r_out[i];
         rh[i] = v;
-        p[i] = (float)v;
+        if (!keep_p)
+            p[i] = (float)v;
         c[i] = 0.0;
         a = fma(v, v, a);
     }
@@ -1265,10 +1272,10 @@ void launch_update_xp32(const DevMatrix &m, double *x, float *p, const double *r
 }
 
 void launch_mx_init(const DevMatrix &m, const double *r_out, double *rh, float *p, double *c, double *rho_part,
-                    double *bb_part, hipStream_t s)
+                    double *bb_part, hipStream_t s, bool keep_p)
 {
     hipLaunchKernelGGL(k_mx_init, dim3(m.vec_blocks), dim3(kBlock), 0, s, m.n, m.vec_chunk, r_out, m.dscale, rh,
-                       p, c, rho_part, bb_part);
+                       p, c, rho_part, bb_part, keep_p ? 1 : 0);
 }
 
 void launch_mx_apply(const DevMatrix &m, double *x, const double *c, hipStream_t s)
