@@ -593,25 +593,11 @@ __global__ __launch_bounds__(kBlock) void k_scatter_slices(
             v[m] = ok ? (double)matrix_load<NT>(sval + q) : 0.0;
         }
         const double xo = mine ? (double)x[bk.line0 + t] : 0.0;
-        int tg[SU], lo[SU], hi[SU];
-        const uint16_t *sg = seg + bk.slot0 + bk.id;
-#pragma unroll
-        for (int u = 0; u < SU; ++u) {
-            const int s = t + u * kBlock;
-            const bool ok = s < bk.nslots;
-            tg[u] = ok ? slot_target[bk.slot0 + s] : -1;
-            lo[u] = ok ? sg[s] : 0;
-            hi[u] = ok ? sg[s + 1] : 0;
-        }
         // ---- gathers
         double xg[E];
 #pragma unroll
         for (int m = 0; m < E; ++m)
             xg[m] = c[m] >= 0 ? (double)x[c[m]] : 0.0;
-        double xt[SU];
-#pragma unroll
-        for (int u = 0; u < SU; ++u)
-            xt[u] = tg[u] >= 0 ? (double)x[tg[u]] : 0.0;
         // ---- own row in registers; mirror products (not the diagonal) to LDS
         double own = 0.0;
 #pragma unroll
@@ -622,6 +608,23 @@ __global__ __launch_bounds__(kBlock) void k_scatter_slices(
                     sp[m * nl + t] = v[m] * xo;
             }
         __syncthreads();
+        // ---- slot descriptors, loaded only now: held across the first phase
+        //      they cost 22 VGPRs (91 instead of 69, 5 instead of 7 waves per
+        //      SIMD), more than their latency here (45.5 instead of 47.5 us)
+        int tg[SU], lo[SU], hi[SU];
+        const uint16_t *sg = seg + bk.slot0 + bk.id;
+#pragma unroll
+        for (int u = 0; u < SU; ++u) {
+            const int s = t + u * kBlock;
+            const bool ok = s < bk.nslots;
+            tg[u] = ok ? slot_target[bk.slot0 + s] : -1;
+            lo[u] = ok ? sg[s] : 0;
+            hi[u] = ok ? sg[s + 1] : 0;
+        }
+        double xt[SU];
+#pragma unroll
+        for (int u = 0; u < SU; ++u)
+            xt[u] = tg[u] >= 0 ? (double)x[tg[u]] : 0.0;
         // ---- slot sums
         const bool first_colour = bk.pad == 0;
 #pragma unroll
