@@ -62,6 +62,20 @@ def test_mixed_row_blocks(monkeypatch, fmt):
     check_vs_fp64(fmt, arrs, s.b, xg, info)
 
 
+@pytest.mark.parametrize("restart", ["0", "1"])
+@pytest.mark.parametrize("fmt", [CSR, SYM, CSC])
+def test_mixed_loose_inner_tolerance(monkeypatch, fmt, restart):
+    # inner tolerance 1e-2: several refinement steps, each continuing with the
+    # previous inner solve's direction (restart = 0, the default) or starting
+    # over from p = r (restart = 1); both must meet the FP64 bar
+    monkeypatch.setenv("CGMI_MIXED_RESTART", restart)
+    s = fem_cached("fem32x32x30")
+    arrs = formats_of(s.rowptr, s.col, s.val)[fmt]
+    xg, info = run_mixed(fmt, arrs, s.b, inner_tol=1e-2, label=f"fem32x32x30 inner 1e-2 restart={restart}")
+    assert info["outer"] >= 3
+    check_vs_fp64(fmt, arrs, s.b, xg, info)
+
+
 @pytest.mark.parametrize("fmt", [CSR, SYM])
 def test_mixed_high_contrast(fmt):
     # iron contrast 1e-4: kappa * u_fp32 would exceed 1 without the diagonal scaling
