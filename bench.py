@@ -187,7 +187,9 @@ def main():
                                 spmv_us=round(spmv[name]["us"], 3), spmv_GBps=round(spmv[name]["GBps"], 1),
                                 spmv_cold_us=round(spmv[name]["cold_us"], 3),
                                 spmv_cold_GBps=round(spmv[name]["bytes"] / spmv[name]["cold_us"] / 1e3, 1),
-                                spmv_colors=spmv[name]["colors"])
+                                spmv_colors=spmv[name]["colors"],
+                                sliced=solvers[name].stats()["slices"] == 1,
+                                matrix_cache_resident=solvers[name].stats()["cached_loads"] == 1)
     # dominant product kernel: largest share of the step's time
     dom = max(solvers, key=lambda k: spmv[k]["us"] * per_format[k]["iters"])
     sliced = solvers[dom].stats()["slices"] == 1
