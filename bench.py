@@ -1,22 +1,43 @@
 #!/usr/bin/env python3
-"""Benchmark: CG time-to-1e-10 residual and SpMV bandwidth on one MI355X.
+"""Benchmark: CG time-to-1e-10 residual and product bandwidth on one MI355X.
 
-Workload (default fem100): the synthetic P1 / Kuhn-tet stiffness matrix of a
-100^3 interior grid (n = 1 000 000, nnz = 14 761 198, iron contrast 1e-3),
-b = A x_true, x0 = 0, tol 1e-10 relative to ||b||.  One step solves that
-system three times, with A stored as full CSR, as symmetric CSR (upper
-triangle) and as CSC, i.e. one pass of every product variant and of the
-fused CG vector kernels.  Inputs are resident in HBM before timing starts.
+Step (the timed unit): one FP64 conjugate-gradient solve, from x0 = 0 to
+||b - A x|| <= 1e-10 ||b||, of the synthetic P1 / Kuhn-tet stiffness system of
+a 160^3 interior grid (n = 4 096 000, nnz = 60 827 518, iron contrast 1e-4)
+stored as full CSR.  The iteration is the paper's unpreconditioned CG (one
+product Ap, two scalar products and three vector updates per iteration, all
+on the device).  Inputs are resident in HBM before timing starts.
 
-Printed: one JSON line (metric = time-to-solution of the step, lower is
-better) with the per-format breakdown, a roofline entry for the dominant
-kernel (algorithmic bytes / average launch time, timed live with HIP events
-on the launch stream) and the CPU oracle timed on a bounded sample.
+Printed: ONE JSON line.  Besides the step time it carries
+  * roofline: the dominant kernel (the CSR product, ~75 % of the step) as
+    algorithmic bytes / average launch time over back-to-back launches timed
+    with HIP events on the launch stream, against the 8 TB/s HBM peak, and
+    the HBM bytes one launch moves according to the committed counter runs
+    (profiles/traffic_<workload>.json), while the kernel source is unchanged;
+  * cpu_baseline: the CPU oracle's CSR iteration timed on every host core
+    (its OpenMP timing mode; a bounded sample of iterations, median of 3,
+    scaled by the GPU's iteration count) and, beside it, on one core;
+  * extras, each timed on its own (--extras): the symmetric-CSR and CSC
+    solves and products of the same system; mixed precision (FP32 product
+    inside FP64 refinement) against plain FP64 CG and against FP64 CG on the
+    same Jacobi-scaled system, in CSR and symmetric CSR; the paper-sized
+    32x32x30 system in all formats; the batch of 256 uneven systems x 4
+    right-hand sides solved together against a fully measured loop of the
+    1024 single solves; the adjoint (gradient) solve on the 100^3 system.
+
+Other modes (--mode): `counters` runs only the product of one format
+back-to-back plus a 1 GiB device copy, for hardware-counter runs under
+rocprofv3 --pmc; `parse-counters` turns two such runs (FETCH_SIZE, then
+WRITE_SIZE) into profiles/traffic_<workload>.json.
 """
 import argparse
+import csv
+import glob
 import hashlib
 import json
 import os
+import platform
+import statistics
 import sys
 import time
 
@@ -24,8 +45,14 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0   # MI355X HBM3E, AMD public figure
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_fem100.json")
 KERNEL_SRC = os.path.join(ROOT, "paper_1010_4639_amd", "csrc", "kernels.hip")
+# kernels of one product of each format (name prefixes as the profiler prints
+# them; CSR and CSC slices differ in their first template argument)
+PRODUCT_KERNELS = {"csr": ("k_spmv_slices<false", "k_spmv_csr"),
+                   "symcsr": ("k_scatter_",),
+                   "csc": ("k_spmv_slices<true", "k_panel_")}
+EXTRAS = ("formats", "mixed", "small", "batch", "adjoint", "cpu")
+T_START = time.time()
 
 
 def parse():
@@ -33,23 +60,32 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="fem100")
+    ap.add_argument("--mode", default="bench", choices=("bench", "counters", "parse-counters"))
+    ap.add_argument("--workload", default="fem160")
+    ap.add_argument("--format", default="csr", choices=("csr", "symcsr", "csc"))
     ap.add_argument("--tol", type=float, default=1e-10)
-    ap.add_argument("--maxit", type=int, default=50000)
-    ap.add_argument("--batch", type=int, default=None, help="CG iterations per graph launch")
+    ap.add_argument("--maxit", type=int, default=200000)
     ap.add_argument("--spmv-reps", type=int, default=100)
-    ap.add_argument("--cpu-iters", type=int, default=120, help="oracle CG iterations per format (cpu_baseline)")
-    ap.add_argument("--no-cpu", action="store_true")
-    return ap.parse_args()
+    ap.add_argument("--extras", default="all", help="comma list of " + ",".join(EXTRAS) + ", or all / none")
+    ap.add_argument("--budget-s", type=float, default=480.0,
+                    help="skip the remaining extras once this much wall time has passed")
+    ap.add_argument("--inner-tol", type=float, default=1e-2)
+    ap.add_argument("--loop-systems", type=int, default=256, help="batch extra: systems in the loop of single solves")
+    ap.add_argument("--formats", default="csr,symcsr,csc", help="counters mode: formats to run")
+    ap.add_argument("--counter-dirs", default="", help="parse-counters: FETCH_SIZE run dir,WRITE_SIZE run dir")
+    a = ap.parse_args()
+    a.extras = set(EXTRAS) if a.extras == "all" else set() if a.extras == "none" else set(a.extras.split(","))
+    return a
 
 
 def log(msg):
-    print(msg, file=sys.stderr, flush=True)
+    print(f"[bench {time.time() - T_START:6.1f}s] {msg}", file=sys.stderr, flush=True)
 
 
-def spmv_bytes(fmt, n, nnz_stored):
-    """Algorithmic bytes of one product: idx + val per stored entry, ptr, x and y."""
-    return 12 * nnz_stored + 4 * (n + 1) + 16 * n
+def spmv_bytes(n, nnz_stored, value_bytes=8):
+    """Algorithmic bytes of one product: index + value per stored entry, the
+    line pointers, x read and y written once."""
+    return (4 + value_bytes) * nnz_stored + 4 * (n + 1) + (value_bytes + 8) * n
 
 
 def kernel_source_sha():
@@ -57,25 +93,376 @@ def kernel_source_sha():
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def load_traffic(kind):
+def traffic_file(workload):
+    return os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
+
+
+def load_traffic(workload, fmt):
     """HBM bytes per launch from the committed counter runs, or None if the
     kernels changed since they were taken."""
     try:
-        with open(TRAFFIC_FILE) as f:
+        with open(traffic_file(workload)) as f:
             t = json.load(f)
     except (OSError, ValueError):
         return None
     if t.get("kernel_src_sha") != kernel_source_sha():
         return None
-    return t.get("per_launch_bytes", {}).get(kind)
+    return t.get("per_launch_bytes", {}).get(fmt)
+
+
+def host_cpu():
+    model = platform.processor() or "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return model, os.cpu_count(), usable
+
+
+class Timer:
+    """HIP events on the current torch stream (the stream the library's work
+    is launched on: the Solver binds its handle to it)."""
+
+    def __init__(self, torch):
+        self.torch = torch
+        self.stream = torch.cuda.current_stream()
+
+    def per_call_us(self, fn, reps, warm=5):
+        for _ in range(warm):
+            fn()
+        e0 = self.torch.cuda.Event(enable_timing=True)
+        e1 = self.torch.cuda.Event(enable_timing=True)
+        e0.record(self.stream)
+        for _ in range(reps):
+            fn()
+        e1.record(self.stream)
+        e1.synchronize()
+        return e0.elapsed_time(e1) * 1e3 / reps
+
+
+def timed_solve(torch, fn):
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) * 1e3, out
+
+
+def product_figures(torch, timer, S, xs, ys, nbytes, reps, flush):
+    """Back-to-back average and cold (after evicting the caches) product time."""
+    us = timer.per_call_us(lambda: S.spmv(xs, ys), reps)
+    cold = []
+    for _ in range(5):
+        flush()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(timer.stream)
+        S.spmv(xs, ys)
+        e1.record(timer.stream)
+        e1.synchronize()
+        cold.append(e0.elapsed_time(e1) * 1e3)
+    cus = statistics.median(cold)
+    st = S.stats()
+    return dict(us=round(us, 3), GBps=round(nbytes / us / 1e3, 1), cold_us=round(cus, 3),
+                cold_GBps=round(nbytes / cus / 1e3, 1), bytes=nbytes, colors=st["colors"],
+                sliced=st["slices"] == 1, matrix_cache_resident=st["cached_loads"] == 1,
+                device_bytes=st["plan_bytes"])
+
+
+def energy_err(torch, S, x, x_true):
+    """||x - x_true||_A / ||x_true||_A through the handle's FP64 product."""
+    e = x - x_true
+    return float(torch.sqrt((e @ S.spmv(e)) / (x_true @ S.spmv(x_true))))
+
+
+# ---------------------------------------------------------------- extras
+def extra_formats(torch, cgmi, W, s, a, b, timer, xs, ys, flush, res):
+    up, uc, uv = W.upper_triangle(s.rowptr, s.col, s.val)
+    arrs = {"csr": (s.rowptr, s.col, s.val), "symcsr": (up, uc, uv), "csc": (s.rowptr, s.col, s.val)}
+    out = {}
+    for name in ("symcsr", "csc"):
+        if name == a.format:
+            continue
+        t0 = time.perf_counter()
+        with cgmi.Solver(name, *arrs[name]) as S:
+            plan_ms = (time.perf_counter() - t0) * 1e3
+            S.solve(b, tol=a.tol, maxit=a.maxit)   # graph build
+            ms, (x, info) = timed_solve(torch, lambda: S.solve(b, tol=a.tol, maxit=a.maxit))
+            nb = spmv_bytes(s.n, len(arrs[name][1]))
+            out[name] = dict(time_to_tol_ms=round(ms, 3), iters=info["iters"],
+                             us_per_iter=round(1e3 * ms / max(info["iters"], 1), 3),
+                             relres_true=info["relres_true"], create_ms=round(plan_ms, 1),
+                             spmv=product_figures(torch, timer, S, xs, ys, nb, a.spmv_reps, flush))
+        log(f"{name}: {out[name]['iters']} it, {out[name]['time_to_tol_ms']:.1f} ms, product "
+            f"{out[name]['spmv']['us']:.1f} us")
+    res["formats"] = out
+    return arrs
+
+
+def extra_mixed(torch, cgmi, W, s, a, b, arrs, res):
+    import numpy as np
+    dev = b.device
+    xt = torch.from_numpy(s.x_true).to(dev)
+    out = {}
+    for name in ("csr", "symcsr"):
+        p_, i_, v_ = arrs[name]
+        with cgmi.Solver(name, p_, i_, v_, mixed=True) as S:
+            S.solve_mixed(b, tol=a.tol, maxit=a.maxit, inner_tol=a.inner_tol, max_outer=100)
+            times, x, info = [], None, None
+            for _ in range(3):
+                ms, (x, info) = timed_solve(torch, lambda: S.solve_mixed(b, tol=a.tol, maxit=a.maxit,
+                                                                         inner_tol=a.inner_tol, max_outer=100))
+                times.append(ms)
+            mixed = dict(ms=round(statistics.median(times), 3), inner_iters=info["iters"], outer=info["outer"],
+                         relres_true=info["relres_true"], errA_vs_x_true=energy_err(torch, S, x, xt))
+            # FP64 CG on D^-1/2 A D^-1/2 (the scaling of the mixed inner solve), x = D^-1/2 y
+            line = np.repeat(np.arange(s.n), np.diff(p_))
+            dg = np.zeros(s.n)
+            dpos = line == i_
+            dg[line[dpos]] = v_[dpos]
+            sc = 1.0 / np.sqrt(dg)
+            sct = torch.from_numpy(sc).to(dev)
+            with cgmi.Solver(name, p_, i_, v_ * sc[line] * sc[i_]) as S2:
+                bs = sct * b
+                S2.solve(bs, tol=a.tol, maxit=a.maxit)
+                times = []
+                for _ in range(3):
+                    ms, (y, info2) = timed_solve(torch, lambda: S2.solve(bs, tol=a.tol, maxit=a.maxit))
+                    times.append(ms)
+                xs_ = sct * y
+                rt = float(torch.linalg.norm(b - S.spmv(xs_)) / torch.linalg.norm(b))
+                scaled = dict(ms=round(statistics.median(times), 3), iters=info2["iters"], relres_true=rt,
+                              errA_vs_x_true=energy_err(torch, S, xs_, xt))
+        fp64 = (res["step"] if name == a.format else res.get("formats", {}).get(name))
+        entry = dict(mixed=mixed, fp64_scaled=scaled, inner_tol=a.inner_tol,
+                     speedup_vs_scaled_fp64=round(scaled["ms"] / mixed["ms"], 3))
+        if fp64:
+            entry["fp64_ms"] = fp64["time_to_tol_ms"]
+            entry["speedup_vs_fp64"] = round(fp64["time_to_tol_ms"] / mixed["ms"], 2)
+        out[name] = entry
+        log(f"mixed {name}: {mixed['ms']:.1f} ms ({mixed['inner_iters']} inner, {mixed['outer']} outer), "
+            f"scaled FP64 {scaled['ms']:.1f} ms ({scaled['iters']} it)")
+    res["mixed"] = out
+
+
+def extra_small(torch, cgmi, W, a, res):
+    s = W.fem_config("fem32x32x30")
+    up, uc, uv = W.upper_triangle(s.rowptr, s.col, s.val)
+    arrs = {"symcsr": (up, uc, uv), "csr": (s.rowptr, s.col, s.val), "csc": (s.rowptr, s.col, s.val)}
+    b = torch.from_numpy(s.b).to(torch.device("cuda:0"))
+    out = {"workload": "fem32x32x30: n=30720, nnz=437622 (upper 234171), iron contrast 1e-3"}
+    for name, arr in arrs.items():
+        with cgmi.Solver(name, *arr) as S:
+            S.solve(b, tol=a.tol, maxit=a.maxit)
+            times = []
+            for _ in range(5):
+                ms, (x, info) = timed_solve(torch, lambda: S.solve(b, tol=a.tol, maxit=a.maxit))
+                times.append(ms)
+            ms = statistics.median(times)
+            out[name] = dict(time_to_tol_ms=round(ms, 3), iters=info["iters"],
+                             us_per_iter=round(1e3 * ms / max(info["iters"], 1), 3), relres_true=info["relres_true"])
+        log(f"small {name}: {out[name]['iters']} it, {ms:.2f} ms, {out[name]['us_per_iter']:.2f} us/it")
+    res["small"] = out
+
+
+def extra_batch(torch, cgmi, W, a, res):
+    import numpy as np
+    dev = torch.device("cuda:0")
+    t0 = time.time()
+    systems, B, _ = W.fem_batch(256, lo=20, hi=60, nrhs=4, workers=8)
+    so, ptr, col, val = W.block_diagonal(systems)
+    log(f"batch: 256 systems, N={so[-1]}, nnz={ptr[-1]} generated in {time.time() - t0:.1f}s")
+    Bd = torch.from_numpy(np.ascontiguousarray(B)).to(dev)
+    out = dict(workload="256 FEM systems, interior grid edges U{20..60} per axis (seed 4), 4 right-hand sides each",
+               N=int(so[-1]), nnz=int(ptr[-1]))
+    with cgmi.Batch(so, ptr, col, val, nrhs=4) as bt:
+        out["autotune"] = bt.autotune()
+        bt.solve(Bd, tol=a.tol)
+        ms, (X, info, iters, st) = timed_solve(torch, lambda: bt.solve(Bd, tol=a.tol))
+        out["batched_ms"] = round(ms, 3)
+        out["batched_ok"] = int((st == 0).sum())
+        out["batched_max_iters"] = int(iters.max())
+    log(f"batch: one batched solve {ms:.0f} ms, autotune {out['autotune']}")
+    k = min(a.loop_systems, 256)
+    loop_ms, pairs, ok = 0.0, 0, 0
+    for si in range(k):
+        rp, c, v = systems[si]
+        with cgmi.Solver("csr", rp, c, v) as S:
+            r0, r1 = so[si], so[si + 1]
+            for r in range(4):
+                bb = Bd[r0:r1, r].contiguous()
+                if si == 0 and r == 0:
+                    S.solve(bb, tol=a.tol)
+                ms1, (_, inf1) = timed_solve(torch, lambda: S.solve(bb, tol=a.tol))
+                loop_ms += ms1
+                pairs += 1
+                ok += inf1["status"] == 0
+    out["loop_pairs_timed"] = pairs
+    out["loop_ok"] = ok
+    out["loop_ms"] = round(loop_ms, 3)
+    if k == 256:
+        out["speedup_vs_loop"] = round(loop_ms / out["batched_ms"], 3)
+    log(f"batch: loop of {pairs} single solves {loop_ms:.0f} ms")
+    res["batch"] = out
+
+
+def extra_adjoint(torch, cgmi, W, a, res):
+    import numpy as np
+
+    from paper_1010_4639_amd import adjoint
+    dev = torch.device("cuda:0")
+    t0 = time.time()
+    s = W.fem_config("fem100")
+    coords, tets, dof, nu_cell = W.fem_mesh(s)
+    nu = nu_cell * np.random.default_rng(101).uniform(0.8, 1.25, size=nu_cell.size)
+    xo = torch.from_numpy(W.observation(s)).to(dev)
+    b = torch.from_numpy(s.b).to(dev)
+    log(f"adjoint: fem100 mesh, {nu.size} elements, generated in {time.time() - t0:.1f}s")
+    FS = adjoint.FemSolve(coords, tets, dof, s.n)
+    fwd, bwd = [], []
+    g = x = None
+    for r in range(3):
+        nu_t = torch.from_numpy(nu).to(dev).requires_grad_(True)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        x = FS(nu_t, b, tol=a.tol)
+        L = ((x - xo) ** 2).sum()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        L.backward()
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        if r > 0:
+            fwd.append((t2 - t1) * 1e3)
+            bwd.append((t3 - t2) * 1e3)
+        g = nu_t.grad
+    xs = x.detach()
+    lhs, rhs = float(torch.from_numpy(nu).to(dev) @ g), -2.0 * float((xs - xo) @ xs)
+    res["adjoint"] = dict(workload=f"fem100: n={s.n}, {nu.size} per-element nu, L=||x-x_obs||^2, tol {a.tol:g}",
+                          forward_ms=round(statistics.median(fwd), 3), backward_ms=round(statistics.median(bwd), 3),
+                          identity_rel_diff=abs(lhs - rhs) / abs(rhs))
+    FS.close()
+    log(f"adjoint: forward {res['adjoint']['forward_ms']:.1f} ms, backward {res['adjoint']['backward_ms']:.1f} ms")
+
+
+def cpu_baseline(s, fmt, gpu_iters, target_ms=6000.0):
+    """The oracle's CSR iteration on every host core (OpenMP timing mode) and
+    on one core, each on a bounded sample of iterations, scaled by the GPU's
+    iteration count (the time to tolerance the oracle would need)."""
+    import oracle
+    model, ncpu, usable = host_cpu()
+    arrs = (s.rowptr, s.col, s.val)
+    _, probe = oracle.cg_csr_omp(*arrs, s.b, tol=0.0, maxit=10)
+    per = probe["ms_loop"] / max(probe["iters"], 1)
+    m = int(max(20, min(2000, target_ms / max(per, 1e-3))))
+    runs = []
+    for _ in range(3):
+        _, oi = oracle.cg_csr_omp(*arrs, s.b, tol=0.0, maxit=m)
+        runs.append(oi["ms_loop"] / max(oi["iters"], 1))
+    ms_it = statistics.median(runs)
+    _, ser, _ = oracle.cg(oracle.FMT_CSR, *arrs, s.b, tol=0.0, maxit=20)
+    ser_it = ser["ms_loop"] / max(ser["iters"], 1)
+    log(f"cpu: oracle {ms_it:.2f} ms/iteration on {probe['threads']} threads, {ser_it:.2f} on one core")
+    return dict(value=round(ms_it * gpu_iters, 1), unit="ms", cores=probe["threads"], kind="oracle",
+                sample=(f"oracle CSR CG, OpenMP timing mode (static loops, exactly rounded dots), {m} iterations x 3 "
+                        f"runs on {probe['threads']} threads, median {ms_it:.3f} ms/iteration, scaled by the GPU's "
+                        f"{gpu_iters} iterations; host: {model}, nproc {ncpu}, usable {usable}"),
+                one_core=dict(value=round(ser_it * gpu_iters, 1), ms_per_iter=round(ser_it, 3),
+                              sample=f"serial oracle orc_cg (the correctness reference), 20 iterations"),
+                format=fmt)
+
+
+# ----------------------------------------------------------------- modes
+def counters_mode(a):
+    """Products only, for hardware-counter runs: `reps` back-to-back launches
+    of each format, then one 1 GiB device-to-device copy (calibration)."""
+    import torch
+
+    from paper_1010_4639_amd import cgmi
+    from paper_1010_4639_amd import workload as W
+    dev = torch.device("cuda:0")
+    s = W.fem_config(a.workload, with_rhs=False, keep_geometry=False)
+    up, uc, uv = W.upper_triangle(s.rowptr, s.col, s.val)
+    arrs = {"csr": (s.rowptr, s.col, s.val), "symcsr": (up, uc, uv), "csc": (s.rowptr, s.col, s.val)}
+    x = torch.from_numpy(W.uniform_vector(s.n, seed=5)).to(dev)
+    y = torch.empty_like(x)
+    out = {"workload": a.workload, "n": s.n, "reps": a.spmv_reps, "order": []}
+    for name in a.formats.split(","):
+        with cgmi.Solver(name, *arrs[name]) as S:
+            S.spmv(x, y)
+            torch.cuda.synchronize()
+            log(f"counters: {name} x {a.spmv_reps}")
+            for _ in range(a.spmv_reps):
+                S.spmv(x, y)
+            torch.cuda.synchronize()
+            out["order"].append(name)
+    nel = (1 << 30) // 8
+    src = torch.ones(nel, dtype=torch.float64, device=dev)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    out["copy_bytes_each_way"] = nel * 8
+    print(json.dumps(out), flush=True)
+
+
+def parse_counters(a):
+    """Per-launch HBM bytes of each format's product from a FETCH_SIZE run and
+    a WRITE_SIZE run of `--mode counters` (rocprofv3 counter_collection.csv),
+    each scaled by what the counter reads for the 1 GiB copy of the same run."""
+    dirs = a.counter_dirs.split(",")
+    per = {}
+    calib = {}
+    for d, ctr in zip(dirs, ("FETCH_SIZE", "WRITE_SIZE")):
+        files = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
+        rows = []
+        for f in files:
+            with open(f) as fh:
+                rows += [r for r in csv.DictReader(fh) if r.get("Counter_Name") == ctr]
+        rows.sort(key=lambda r: int(r["Dispatch_Id"]))
+        copy = [float(r["Counter_Value"]) for r in rows if "copy" in r["Kernel_Name"].lower()
+                or "elementwise" in r["Kernel_Name"].lower()]
+        calib[ctr] = dict(copy_kib=copy[-1] if copy else None)
+        byk = {}
+        for r in rows:
+            byk.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
+        calib[ctr]["kernels"] = {k: dict(launches=len(v), mean_kib=statistics.mean(v)) for k, v in byk.items()}
+    nb = (1 << 30)
+    f_scale = nb / (calib["FETCH_SIZE"]["copy_kib"] * 1024)
+    w_scale = nb / (calib["WRITE_SIZE"]["copy_kib"] * 1024)
+    for fmt in ("csr", "symcsr", "csc"):
+        ks = PRODUCT_KERNELS[fmt]
+        fb = sum(v["mean_kib"] for k, v in calib["FETCH_SIZE"]["kernels"].items() if any(x in k for x in ks))
+        wb = sum(v["mean_kib"] for k, v in calib["WRITE_SIZE"]["kernels"].items() if any(x in k for x in ks))
+        per[fmt] = dict(fetch_bytes=round(fb * 1024 * f_scale), write_bytes=round(wb * 1024 * w_scale))
+        per[fmt]["total"] = per[fmt]["fetch_bytes"] + per[fmt]["write_bytes"]
+    out = dict(kernel_src_sha=kernel_source_sha(), workload=a.workload,
+               calibration=dict(copy_bytes_each_way=nb, fetch_scale=f_scale, write_scale=w_scale),
+               per_launch_bytes={k: v["total"] for k, v in per.items()}, detail=per,
+               command=f"rocprofv3 --pmc FETCH_SIZE -d <run1> -- python bench.py --mode counters --workload "
+                       f"{a.workload} --spmv-reps {a.spmv_reps}; the same with WRITE_SIZE -d <run2>; "
+                       f"python bench.py --mode parse-counters --workload {a.workload} --counter-dirs <run1>,<run2>")
+    with open(traffic_file(a.workload), "w") as f:
+        json.dump(out, f, indent=1)
+    print(json.dumps(out), flush=True)
 
 
 def main():
-    args = parse()
-    if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); this build has no multi-GPU path",
-              file=sys.stderr)
+    a = parse()
+    if a.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}): this build has no multi-GPU path; "
+              f"the value for one GPU is what it measures", file=sys.stderr)
         sys.exit(2)
+    if a.mode == "parse-counters":
+        return parse_counters(a)
+    if a.mode == "counters":
+        return counters_mode(a)
     import numpy as np
     import torch
 
@@ -86,146 +473,108 @@ def main():
     cgmi.load()
     dev = torch.device("cuda:0")
     t0 = time.time()
-    s = W.fem_config(args.workload)
-    up, uc, uv = W.upper_triangle(s.rowptr, s.col, s.val)
-    log(f"[bench] generated {args.workload}: n={s.n} nnz={s.nnz} nnz_upper={len(uc)} in {time.time() - t0:.1f}s")
-    formats = {
-        "csr": (cgmi.CG_FMT_CSR, (s.rowptr, s.col, s.val), s.nnz),
-        "symcsr": (cgmi.CG_FMT_SYM_CSR, (up, uc, uv), len(uc)),
-        "csc": (cgmi.CG_FMT_CSC, (s.rowptr, s.col, s.val), s.nnz),
-    }
-    solvers = {}
-    for name, (fmt, arrs, _) in formats.items():
-        t1 = time.time()
-        solvers[name] = cgmi.Solver(fmt, *arrs, batch=args.batch)
-        log(f"[bench] created {name} handle in {time.time() - t1:.1f}s: {solvers[name].stats()}")
+    s = W.fem_config(a.workload, keep_geometry=False)
+    log(f"generated {a.workload}: n={s.n} nnz={s.nnz} in {time.time() - t0:.1f}s")
+    if a.format == "symcsr":
+        arrs = W.upper_triangle(s.rowptr, s.col, s.val)
+    else:
+        arrs = (s.rowptr, s.col, s.val)
+    t1 = time.perf_counter()
+    S = cgmi.Solver(a.format, *arrs)
+    create_ms = (time.perf_counter() - t1) * 1e3
+    log(f"created {a.format} handle in {create_ms:.0f} ms: {S.stats()}")
     b = torch.from_numpy(s.b).to(dev)
     x0 = torch.zeros_like(b)
 
     def step():
-        out = {}
-        for name, S in solvers.items():
-            x, info = S.solve(b, x0, tol=args.tol, maxit=args.maxit)
-            if info["status"] != cgmi.CG_OK:
-                raise RuntimeError(f"{name}: solve failed {info}")
-            out[name] = info
-        return out
+        x, info = S.solve(b, x0, tol=a.tol, maxit=a.maxit)
+        if info["status"] != cgmi.CG_OK:
+            raise RuntimeError(f"solve failed: {info}")
+        return info
 
-    for w in range(args.warmup):
+    for w in range(a.warmup):
         info = step()
-        log(f"[bench] warmup {w}: " + ", ".join(f"{k} {v['iters']} it {v['ms']:.1f} ms" for k, v in info.items()))
+        log(f"warmup {w}: {info['iters']} it, {info['ms']:.1f} ms")
     torch.cuda.synchronize()
-    per = {k: [] for k in solvers}
+    infos = []
     t_start = time.perf_counter()
-    for k in range(args.steps):
-        info = step()
-        for name, v in info.items():
-            per[name].append(v)
-        log(f"[bench] step {k}: " + ", ".join(f"{n} {v['iters']} it {v['ms']:.1f} ms" for n, v in info.items()))
+    for k in range(a.steps):
+        infos.append(step())
+        log(f"step {k}: {infos[-1]['iters']} it, {infos[-1]['ms']:.1f} ms")
     torch.cuda.synchronize()
-    ms_per_step = (time.perf_counter() - t_start) * 1e3 / args.steps
+    ms_per_step = (time.perf_counter() - t_start) * 1e3 / a.steps
+    iters = infos[-1]["iters"]
+    res = {"step": dict(time_to_tol_ms=round(ms_per_step, 3), iters=iters,
+                        us_per_iter=round(1e3 * ms_per_step / iters, 3), relres_true=infos[-1]["relres_true"],
+                        create_ms=round(create_ms, 1), device_bytes=S.stats()["plan_bytes"])}
 
-    # SpMV: average launch duration with HIP events on the launch stream
-    stream = torch.cuda.current_stream()
+    # the dominant kernel: the product, back to back and cold
+    timer = Timer(torch)
     xs = torch.from_numpy(W.uniform_vector(s.n, seed=99)).to(dev)
     ys = torch.empty_like(xs)
-    spmv = {}
-    for name, S in solvers.items():
-        for _ in range(10):
-            S.spmv(xs, ys)
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        for _ in range(args.spmv_reps):
-            S.spmv(xs, ys)
-        e1.record(stream)
-        e1.synchronize()
-        us = e0.elapsed_time(e1) * 1e3 / args.spmv_reps
-        byts = spmv_bytes(name, s.n, formats[name][2])
-        spmv[name] = dict(us=us, bytes=byts, GBps=byts / us / 1e3, colors=S.stats()["colors"])
-        log(f"[bench] spmv {name}: {us:.1f} us/launch, {byts / 1e6:.1f} MB algorithmic, "
-            f"{byts / us / 1e3:.0f} GB/s")
-    # cold products: a 1 GiB read evicts the matrix from the caches (L2, and
-    # the 256 MB Infinity Cache) before each single timed launch, leaving
-    # clean lines behind (a write would leave dirty ones to be written back
-    # during the timed launch); median of 5
     scratch = torch.ones(1 << 27, dtype=torch.float64, device=dev)
     flushed = torch.empty(1, dtype=torch.float64, device=dev)
-    torch.sum(scratch, dim=0, keepdim=True, out=flushed)
-    for name, S in solvers.items():
-        cold = []
-        for i in range(5):
-            torch.sum(scratch, dim=0, keepdim=True, out=flushed)
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e0.record(stream)
-            S.spmv(xs, ys)
-            e1.record(stream)
-            e1.synchronize()
-            cold.append(e0.elapsed_time(e1) * 1e3)
-        spmv[name]["cold_us"] = float(np.median(cold))
-        log(f"[bench] spmv {name} cold: {spmv[name]['cold_us']:.1f} us/launch, "
-            f"{spmv[name]['bytes'] / spmv[name]['cold_us'] / 1e3:.0f} GB/s")
-    del scratch, flushed
-    # plain device copy of 1 GiB for the practical bandwidth ceiling
-    a = torch.empty(1 << 27, dtype=torch.float64, device=dev)
-    c = torch.empty_like(a)
-    c.copy_(a)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    for _ in range(10):
-        c.copy_(a)
-    e1.record(stream)
-    e1.synchronize()
-    copy_gbps = 2 * a.numel() * 8 * 10 / (e0.elapsed_time(e1) * 1e-3) / 1e9
-    del a, c
 
-    per_format = {}
-    for name in solvers:
-        its = [v["iters"] for v in per[name]]
-        ms = float(np.mean([v["ms"] for v in per[name]]))
-        per_format[name] = dict(time_to_tol_ms=round(ms, 3), iters=its[-1], us_per_iter=round(1e3 * ms / its[-1], 3),
-                                relres_true=per[name][-1]["relres_true"],
-                                spmv_us=round(spmv[name]["us"], 3), spmv_GBps=round(spmv[name]["GBps"], 1),
-                                spmv_cold_us=round(spmv[name]["cold_us"], 3),
-                                spmv_cold_GBps=round(spmv[name]["bytes"] / spmv[name]["cold_us"] / 1e3, 1),
-                                spmv_colors=spmv[name]["colors"],
-                                sliced=solvers[name].stats()["slices"] == 1,
-                                matrix_cache_resident=solvers[name].stats()["cached_loads"] == 1)
-    # dominant product kernel: largest share of the step's time
-    dom = max(solvers, key=lambda k: spmv[k]["us"] * per_format[k]["iters"])
-    sliced = solvers[dom].stats()["slices"] == 1
-    kernel_name = {"csr": "k_spmv_slices (CSR product, 64-row slices)" if sliced else
-                          "k_spmv_csr_rows (CSR product, row blocks)",
-                   "symcsr": ("k_scatter_slices" if sliced else "k_scatter_sums") +
-                             " + k_scatter_gather (symmetric-CSR product)",
-                   "csc": ("k_spmv_slices" if sliced else "k_panel_rows") +
-                          " + k_panel_gather (CSC product on column panels)"}[dom]
-    traffic = load_traffic(dom)
-    roofline = dict(bound="hbm", achieved=round(spmv[dom]["GBps"], 1), peak=HBM_PEAK_GBPS, unit="GB/s",
-                    frac=round(spmv[dom]["GBps"] / HBM_PEAK_GBPS, 4), traffic=traffic, kernel=kernel_name,
-                    bytes_per_launch=spmv[dom]["bytes"], avg_us=round(spmv[dom]["us"], 3))
+    def flush():
+        # a 1 GiB read evicts L2 and the 256 MB Infinity Cache, leaving clean lines
+        torch.sum(scratch, dim=0, keepdim=True, out=flushed)
+
+    nbytes = spmv_bytes(s.n, len(arrs[1]))
+    prod = product_figures(torch, timer, S, xs, ys, nbytes, a.spmv_reps, flush)
+    res["spmv"] = prod
+    log(f"product {a.format}: {prod['us']:.1f} us back to back ({prod['GBps']:.0f} GB/s), cold {prod['cold_us']:.1f} us")
+    # plain device copy of 1 GiB: the practical bandwidth ceiling
+    c = torch.empty_like(scratch)
+    copy_us = timer.per_call_us(lambda: c.copy_(scratch), 10, warm=2)
+    copy_gbps = 2 * scratch.numel() * 8 / copy_us / 1e3
+    del c
+    kernel = {"csr": "k_spmv_slices (CSR product, 64-row slices)" if prod["sliced"] else "k_spmv_csr_rows",
+              "symcsr": "symmetric-CSR product (scatter kernel + row pass)",
+              "csc": "CSC product on column panels (slot kernel + row pass)"}[a.format]
+    roofline = dict(bound="hbm", achieved=prod["GBps"], peak=HBM_PEAK_GBPS, unit="GB/s",
+                    frac=round(prod["GBps"] / HBM_PEAK_GBPS, 4), traffic=load_traffic(a.workload, a.format),
+                    kernel=kernel, bytes_per_launch=nbytes, avg_us=prod["us"],
+                    cold_frac=round(prod["cold_GBps"] / HBM_PEAK_GBPS, 4),
+                    matrix_cache_resident=prod["matrix_cache_resident"],
+                    frac_of_copy=round(prod["GBps"] / copy_gbps, 4))
+
+    def room(name):
+        if name not in a.extras:
+            return False
+        if time.time() - T_START > a.budget_s:
+            res.setdefault("skipped", []).append(name)
+            log(f"skipping {name}: {time.time() - T_START:.0f} s spent")
+            return False
+        return True
 
     cpu = None
-    if not args.no_cpu:
-        import oracle
-        cpu_ms = 0.0
-        sample = []
-        for name, (fmt, arrs, _) in formats.items():
-            _, oinfo, _ = oracle.cg(fmt, *arrs, s.b, tol=0.0, maxit=args.cpu_iters)
-            ms_it = oinfo["ms_loop"] / max(oinfo["iters"], 1)
-            cpu_ms += ms_it * per_format[name]["iters"]
-            sample.append(f"{name}: {oinfo['iters']} it at {ms_it:.2f} ms/it")
-            log(f"[bench] oracle {name}: {ms_it:.2f} ms/iteration")
-        cpu = dict(value=round(cpu_ms, 1), unit="ms", cores=1, kind="oracle",
-                   sample=f"{args.cpu_iters} oracle CG iterations per format on the same system (serial C, "
-                          f"-O2), scaled by the GPU's iteration counts; " + "; ".join(sample))
+    all_arrs = None
+    if room("formats"):
+        all_arrs = extra_formats(torch, cgmi, W, s, a, b, timer, xs, ys, flush, res)
+    del scratch, flushed
+    S.close()
+    if room("mixed"):
+        if all_arrs is None:
+            up, uc, uv = W.upper_triangle(s.rowptr, s.col, s.val)
+            all_arrs = {"csr": (s.rowptr, s.col, s.val), "symcsr": (up, uc, uv)}
+        extra_mixed(torch, cgmi, W, s, a, b, all_arrs, res)
+    if room("cpu"):
+        cpu = cpu_baseline(s, a.format, iters)
+    del all_arrs
+    if room("small"):
+        extra_small(torch, cgmi, W, a, res)
+    if room("adjoint"):
+        extra_adjoint(torch, cgmi, W, a, res)
+    if room("batch"):
+        extra_batch(torch, cgmi, W, a, res)
 
-    res = {
-        "metric": "CG time-to-1e-10 residual (CSR + symmetric-CSR + CSC solves of one system)",
+    out = {
+        "metric": "CG time-to-1e-10 residual",
         "value": round(ms_per_step, 3),
         "unit": "ms",
         "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
+        "steps": a.steps,
+        "warmup": a.warmup,
         "ms_per_step": round(ms_per_step, 3),
         "higher_is_better": False,
         "scaling": "weak",
@@ -233,19 +582,19 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {
-            "workload": f"{args.workload}: 3D P1 Kuhn-tet FEM stiffness, {s.nx}x{s.ny}x{s.nz} interior grid, "
-                        f"n={s.n}, nnz={s.nnz} (upper {len(uc)}), iron box {s.iron_fraction:.3f} of cells, "
-                        f"x0=0, tol={args.tol:g}, formats csr+symcsr+csc",
+            "workload": f"{a.workload}: 3D P1 Kuhn-tet FEM stiffness, {s.nx}x{s.ny}x{s.nz} interior grid, "
+                        f"n={s.n}, nnz={s.nnz}, iron box {s.iron_fraction:.3f} of cells, one FP64 CG solve "
+                        f"stored as {a.format}, x0=0, tol={a.tol:g}",
+            "format": a.format,
             "parallelism": "single GPU",
         },
         "roofline": roofline,
         "cpu_baseline": cpu,
-        "per_format": per_format,
         "stream_copy_GBps": round(copy_gbps, 1),
+        **res,
+        "elapsed_s": round(time.time() - T_START, 1),
     }
-    for S in solvers.values():
-        S.close()
-    print(json.dumps(res), flush=True)
+    print(json.dumps(out), flush=True)
 
 
 if __name__ == "__main__":

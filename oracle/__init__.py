@@ -6,7 +6,9 @@ imports nothing from the GPU library.
 
 * ``cg_oracle.c`` (built into ``liborc.so``): plain serial FP64 SpMV for CSR,
   symmetric CSR (upper) and CSC, the format conversions, structure
-  validation and the CG iteration of section III of the paper.
+  validation and the CG iteration of section III of the paper; plus a timing
+  mode of the CSR iteration over OpenMP threads (``cg_csr_omp``), used only
+  for the CPU baseline of the benchmark.
 * ``exact.py``: the same SpMV and CG in exact rational arithmetic for tiny
   inputs.
 * ``fem.py``: the finite-element operator A(nu) = sum_e nu_e K_e, the
@@ -56,8 +58,6 @@ def load(path=None):
     lib.orc_dot.restype = ctypes.c_double
     lib.orc_dot_plain.argtypes = [i64, _P, _P]
     lib.orc_dot_plain.restype = ctypes.c_double
-    lib.orc_nrm2.argtypes = [i64, _P]
-    lib.orc_nrm2.restype = ctypes.c_double
     lib.orc_transpose.argtypes = [i64, _P, _P, _P, _P, _P, _P]
     lib.orc_transpose.restype = ctypes.c_int
     lib.orc_csr_upper.argtypes = [i64, _P, _P, _P, _P, _P, _P]
@@ -69,6 +69,9 @@ def load(path=None):
     lib.orc_cg.argtypes = [ctypes.c_int, i64, _P, _P, _P, _P, _P, ctypes.c_double, i32,
                            ctypes.POINTER(OrcInfo), _P, _P, _P, i32, _P, i32, i32, ctypes.c_int]
     lib.orc_cg.restype = ctypes.c_int
+    lib.orc_cg_csr_omp.argtypes = [i64, _P, _P, _P, _P, _P, ctypes.c_double, i32, ctypes.POINTER(OrcInfo),
+                                   ctypes.POINTER(i32)]
+    lib.orc_cg_csr_omp.restype = ctypes.c_int
     if path is None:
         _lib = lib
     return lib
@@ -170,3 +173,20 @@ def cg(fmt, ptr, idx, val, b, x0=None, tol=1e-10, maxit=None, history=0, x_strid
         hist = dict(alpha=None if ah is None else ah[:k], beta=None if bh is None else bh[:k],
                     res=None if rh is None else rh[:k], x=xh)
     return x, d, hist
+
+
+def cg_csr_omp(ptr, col, val, b, x0=None, tol=1e-10, maxit=None, lib=None):
+    """TIMING MODE of the CSR iteration on all OpenMP threads (not the
+    correctness reference, which is ``cg``).  Returns (x, info dict with
+    'threads')."""
+    lib = lib or load()
+    ptr, col, val, b = _i32(ptr), _i32(col), _f64(val), _f64(b)
+    n = ptr.size - 1
+    x = np.zeros(n) if x0 is None else _f64(x0).copy()
+    if maxit is None:
+        maxit = max(n, 1)
+    info = OrcInfo()
+    nt = ctypes.c_int32(0)
+    lib.orc_cg_csr_omp(n, _p(ptr), _p(col), _p(val), _p(b), _p(x), tol, maxit, ctypes.byref(info), ctypes.byref(nt))
+    return x, dict(iters=info.iters, status=info.status, relres=info.relres, ms_loop=info.ms_loop,
+                   threads=nt.value)

@@ -143,11 +143,6 @@ double orc_dot_plain(int64_t n, const double *a, const double *b)
     return s;
 }
 
-double orc_nrm2(int64_t n, const double *a)
-{
-    return sqrt(orc_dot(n, a, a));
-}
-
 /* --------------------------------------------------------- conversions */
 
 /* Stable counting-sort transpose: (ptr, idx, val) by lines -> by the other
@@ -414,5 +409,137 @@ int orc_cg(int fmt, int64_t n, const int32_t *ptr, const int32_t *idx, const dou
         r[i] = b[i] - q[i];
     info->relres_true = sqrt(dot(n, r, r)) / nb;
     free(r); free(p); free(q);
+    return status;
+}
+
+/* ------------------------------------------------------- timing mode */
+
+/*
+ * TIMING MODE ONLY -- not the correctness reference (orc_cg is).  The CSR
+ * iteration of orc_cg with every loop split into static, contiguous chunks
+ * over the OpenMP threads (OMP_NUM_THREADS, default all host cores), so that
+ * the CPU baseline is the same algorithm on the whole host rather than one
+ * core.  The row sums are the serial ones (one row, one running sum); each
+ * thread forms the exactly rounded scalar product of its chunk as a Dot2 pair
+ * (sum, error), and the pairs are combined in thread order with TwoSum, so
+ * r'r and p'Ap keep the exactness of orc_dot up to the final rounding of the
+ * combined pair.  Only CSR: the symmetric and CSC products scatter into other
+ * rows and have no race-free static split.  *threads receives the count used.
+ */
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+static double omp_dot2(int64_t n, const double *a, const double *b, double *ps, double *pc, int nt)
+{
+#pragma omp parallel num_threads(nt)
+    {
+        int t = 0;
+#ifdef _OPENMP
+        t = omp_get_thread_num();
+#endif
+        int64_t i0 = n * t / nt, i1 = n * (t + 1) / nt;
+        double hi = 0.0, lo = 0.0;
+        for (int64_t i = i0; i < i1; ++i) {
+            const double prod = a[i] * b[i];
+            const double prod_err = fma(a[i], b[i], -prod);
+            const double sum = hi + prod;
+            const double bv = sum - hi;
+            const double sum_err = (hi - (sum - bv)) + (prod - bv);
+            hi = sum;
+            lo += sum_err + prod_err;
+        }
+        ps[t] = hi;
+        pc[t] = lo;
+    }
+    double hi = 0.0, lo = 0.0;
+    for (int t = 0; t < nt; ++t) {
+        const double sum = hi + ps[t];
+        const double bv = sum - hi;
+        lo += ((hi - (sum - bv)) + (ps[t] - bv)) + pc[t];
+        hi = sum;
+    }
+    return hi + lo;
+}
+
+int orc_cg_csr_omp(int64_t n, const int32_t *ptr, const int32_t *col, const double *val, const double *b,
+                   double *x, double tol, int32_t maxit, orc_info *info, int32_t *threads)
+{
+    int nt = 1;
+#ifdef _OPENMP
+    nt = omp_get_max_threads();
+#endif
+    if (threads)
+        *threads = nt;
+    memset(info, 0, sizeof(*info));
+    if (n <= 0 || maxit < 0 || !(tol >= 0.0)) {
+        info->status = n == 0 ? ORC_OK : ORC_ERR_ARG;
+        return info->status;
+    }
+    double *r = (double *)malloc(sizeof(double) * (size_t)n);
+    double *p = (double *)malloc(sizeof(double) * (size_t)n);
+    double *q = (double *)malloc(sizeof(double) * (size_t)n);
+    double *ps = (double *)malloc(sizeof(double) * (size_t)nt);
+    double *pc = (double *)malloc(sizeof(double) * (size_t)nt);
+    if (!r || !p || !q || !ps || !pc) {
+        free(r); free(p); free(q); free(ps); free(pc);
+        info->status = ORC_ERR_NOMEM;
+        return ORC_ERR_NOMEM;
+    }
+    const double nb = sqrt(omp_dot2(n, b, b, ps, pc, nt));
+    double t0 = now_ms();
+#pragma omp parallel for schedule(static) num_threads(nt)
+    for (int64_t i = 0; i < n; ++i) {
+        double ax = 0.0;
+        for (int64_t e = ptr[i]; e < ptr[i + 1]; ++e)
+            ax += val[e] * x[col[e]];
+        r[i] = b[i] - ax;
+        p[i] = r[i];
+    }
+    double rho = omp_dot2(n, r, r, ps, pc, nt);
+    int status = ORC_NOT_CONVERGED;
+    int32_t k = 0;
+    if (sqrt(rho) <= tol * nb) {
+        status = ORC_OK;
+    } else {
+        for (k = 1; k <= maxit; ++k) {
+#pragma omp parallel for schedule(static) num_threads(nt)
+            for (int64_t i = 0; i < n; ++i) {
+                double s = 0.0;
+                for (int64_t e = ptr[i]; e < ptr[i + 1]; ++e)
+                    s += val[e] * p[col[e]];
+                q[i] = s;
+            }
+            const double sigma = omp_dot2(n, p, q, ps, pc, nt);
+            if (!(sigma > 0.0) || !isfinite(sigma)) {
+                status = ORC_ERR_BREAKDOWN;
+                --k;
+                break;
+            }
+            const double alpha = rho / sigma;
+#pragma omp parallel for schedule(static) num_threads(nt)
+            for (int64_t i = 0; i < n; ++i) {
+                x[i] = x[i] + alpha * p[i];
+                r[i] = r[i] - alpha * q[i];
+            }
+            const double rho_new = omp_dot2(n, r, r, ps, pc, nt);
+            const double beta = rho_new / rho;
+            rho = rho_new;
+            if (sqrt(rho) <= tol * nb) {
+                status = ORC_OK;
+                break;
+            }
+#pragma omp parallel for schedule(static) num_threads(nt)
+            for (int64_t i = 0; i < n; ++i)
+                p[i] = r[i] + beta * p[i];
+        }
+        if (k > maxit)
+            k = maxit;
+    }
+    info->ms_loop = now_ms() - t0;
+    info->iters = k;
+    info->status = status;
+    info->relres = nb > 0.0 ? sqrt(rho) / nb : 0.0;
+    free(r); free(p); free(q); free(ps); free(pc);
     return status;
 }

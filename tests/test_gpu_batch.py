@@ -2,7 +2,9 @@
 sequence) vs the oracle run on every (system, right-hand side) pair alone.
 
 Per pair: same status; true residual (oracle product) <= 2 tol; energy-norm
-difference to the oracle's solution <= 1e-8; iteration count within 5 %.
+difference to the oracle's solution <= 1e-8, 2-norm difference <= max(1e-8,
+10 x the oracle's own reduction-order spread) (tests/parity.py); iteration
+count within 5 %.
 The products of every system are checked row by row against the oracle's.
 Every product schedule (row blocks through LDS; 8 or 16 lanes per row; one
 lane per row over 64-row slices) is run, selected with CGMI_BATCH_LANES.
@@ -13,6 +15,7 @@ import pytest
 import oracle
 from paper_1010_4639_amd import cgmi
 from paper_1010_4639_amd import workload as W
+from tests import parity
 from tests.gpu_util import say, spmv_bound, to_dev
 from tests.test_gpu_cg import a_norm
 
@@ -55,6 +58,9 @@ def test_batch_matches_single_oracle_solves(nrhs, lanes, monkeypatch):
             assert rt <= 2e-10, (s, r, rt)
             ea = a_norm(0, arrs, xg - xo) / a_norm(0, arrs, xo)
             assert ea <= 1e-8, (s, r, ea)
+            e2 = np.linalg.norm(xg - xo) / np.linalg.norm(xo)
+            spread2, _, _ = parity.oracle_spread(0, arrs, b, xo, 1e-10, maxit=20000)
+            assert e2 <= parity.x_bar(spread2), (s, r, e2, spread2)
             # the stopping step moves with rounding (the paper's speed-up table
             # gives one matrix 323-328 iterations in three arithmetics); here
             # each schedule also sums p'Ap and r'r over its own workgroup split,
