@@ -58,6 +58,10 @@ def load(path=None):
     lib.orc_dot.restype = ctypes.c_double
     lib.orc_dot_plain.argtypes = [i64, _P, _P]
     lib.orc_dot_plain.restype = ctypes.c_double
+    lib.orc_dot_pairwise.argtypes = [i64, _P, _P]
+    lib.orc_dot_pairwise.restype = ctypes.c_double
+    lib.orc_dot_fused.argtypes = [i64, _P, _P]
+    lib.orc_dot_fused.restype = ctypes.c_double
     lib.orc_transpose.argtypes = [i64, _P, _P, _P, _P, _P, _P]
     lib.orc_transpose.restype = ctypes.c_int
     lib.orc_csr_upper.argtypes = [i64, _P, _P, _P, _P, _P, _P]
@@ -67,7 +71,7 @@ def load(path=None):
     lib.orc_validate.argtypes = [ctypes.c_int, i64, _P, _P, _P, ctypes.c_int, ctypes.c_uint32]
     lib.orc_validate.restype = ctypes.c_int
     lib.orc_cg.argtypes = [ctypes.c_int, i64, _P, _P, _P, _P, _P, ctypes.c_double, i32,
-                           ctypes.POINTER(OrcInfo), _P, _P, _P, i32, _P, i32, i32, ctypes.c_int]
+                           ctypes.POINTER(OrcInfo), _P, _P, _P, i32, _P, i32, i32, i32, ctypes.c_int]
     lib.orc_cg.restype = ctypes.c_int
     lib.orc_cg_csr_omp.argtypes = [i64, _P, _P, _P, _P, _P, ctypes.c_double, i32, ctypes.POINTER(OrcInfo),
                                    ctypes.POINTER(i32)]
@@ -99,11 +103,19 @@ def spmv(fmt, ptr, idx, val, x, lib=None):
     return y
 
 
-def dot(a, b, lib=None, plain=False):
-    """a'b: the exact value rounded once (default) or the plain left-to-right loop."""
+DOT_MODES = {"exact": 0, "plain": 1, "pairwise": 2, "fused": 3}
+
+
+def dot(a, b, lib=None, plain=False, mode=None):
+    """a'b: the exact value rounded once (default), the plain left-to-right
+    loop (plain=True or mode="plain"), pairwise summation (mode="pairwise")
+    or left-to-right fused multiply-adds (mode="fused")."""
     lib = lib or load()
     a, b = _f64(a), _f64(b)
-    return (lib.orc_dot_plain if plain else lib.orc_dot)(a.size, _p(a), _p(b))
+    mode = mode or ("plain" if plain else "exact")
+    fn = {"exact": lib.orc_dot, "plain": lib.orc_dot_plain, "pairwise": lib.orc_dot_pairwise,
+          "fused": lib.orc_dot_fused}[mode]
+    return fn(a.size, _p(a), _p(b))
 
 
 def transpose(ptr, idx, val, lib=None):
@@ -148,9 +160,15 @@ def validate(fmt, ptr, idx, val, base=0, flags=0, n=None, lib=None):
 
 
 def cg(fmt, ptr, idx, val, b, x0=None, tol=1e-10, maxit=None, history=0, x_stride=0, x_cap=0, lib=None,
-       plain_dots=False):
+       plain_dots=False, dots=None, x_first=None):
     """Run the oracle CG; returns (x, info dict, history dict or None).
-    plain_dots selects the literal left-to-right scalar products."""
+    dots selects the arithmetic: "exact" scalar products (default, the
+    reference), "plain" (the literal left-to-right loop; also
+    plain_dots=True), "pairwise", or "fused" (fused multiply-adds in the
+    scalar products and the three vector updates).
+    x_stride / x_cap / x_first: snapshots of x after iterations x_first
+    (default x_stride), x_first + x_stride, ... (x_cap of them) in hist["x"]."""
+    dot_mode = DOT_MODES[dots or ("plain" if plain_dots else "exact")]
     lib = lib or load()
     ptr, idx, val, b = _i32(ptr), _i32(idx), _f64(val), _f64(b)
     n = ptr.size - 1
@@ -164,7 +182,8 @@ def cg(fmt, ptr, idx, val, b, x0=None, tol=1e-10, maxit=None, history=0, x_strid
     if x_stride and x_cap:
         xh = np.zeros((x_cap, n))
     lib.orc_cg(fmt, n, _p(ptr), _p(idx), _p(val), _p(b), _p(x), tol, maxit, ctypes.byref(info),
-               _p(ah), _p(bh), _p(rh), history, _p(xh), x_stride, x_cap, 1 if plain_dots else 0)
+               _p(ah), _p(bh), _p(rh), history, _p(xh), x_stride, x_cap,
+               x_stride if x_first is None else x_first, dot_mode)
     d = dict(iters=info.iters, status=info.status, relres=info.relres, relres_true=info.relres_true,
              ms_loop=info.ms_loop)
     hist = None

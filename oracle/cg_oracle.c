@@ -26,6 +26,7 @@
  */
 #include <math.h>
 #include <stdint.h>
+#include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
 #include <time.h>
@@ -140,6 +141,35 @@ double orc_dot_plain(int64_t n, const double *a, const double *b)
     double s = 0.0;
     for (int64_t i = 0; i < n; ++i)
         s += a[i] * b[i];
+    return s;
+}
+
+/* Pairwise (recursive halving) summation of the products: the two halves
+ * [0, h) and [h, n), h = n / 2, summed apart and added; runs of at most 8
+ * terms left to right.  The order of blocked and tree reductions on parallel
+ * hardware; error <= gamma(ceil(log2 n) + 8) sum |a_i b_i|.  Kept, like the
+ * plain loop, to measure how far an unspecified summation order moves the
+ * iteration (dot_mode 2 of orc_cg). */
+double orc_dot_pairwise(int64_t n, const double *a, const double *b)
+{
+    if (n <= 8) {
+        double s = 0.0;
+        for (int64_t i = 0; i < n; ++i)
+            s += a[i] * b[i];
+        return s;
+    }
+    const int64_t h = n / 2;
+    return orc_dot_pairwise(h, a, b) + orc_dot_pairwise(n - h, a + h, b + h);
+}
+
+/* Left-to-right accumulation with a fused multiply-add per term (one
+ * rounding per term): the scalar product of FMA hardware.  Error <= gamma_n
+ * sum |a_i b_i| like the plain loop (dot_mode 3 of orc_cg). */
+double orc_dot_fused(int64_t n, const double *a, const double *b)
+{
+    double s = 0.0;
+    for (int64_t i = 0; i < n; ++i)
+        s = fma(a[i], b[i], s);
     return s;
 }
 
@@ -310,17 +340,26 @@ static double now_ms(void)
  * Conjugate gradient on a 0-based matrix in the given format.
  *   x      in: x0, out: the last iterate (untouched on ORC_ERR_ARG / NONFINITE)
  *   hist_* optional (NULL = off): alpha_k, beta_k and ||r_k|| per iteration
- *          (hist_cap entries), and x after every x_stride-th iteration into
- *          x_hist (x_cap snapshots of n values).
+ *          (hist_cap entries), and x after iterations x_first,
+ *          x_first + x_stride, ... into x_hist (x_cap snapshots of n values).
  *   dot_mode 0: scalar products by orc_dot (exact value, rounded once);
- *            1: the plain left-to-right loop.
+ *            1: the plain left-to-right loop; 2: pairwise summation;
+ *            3: fused multiply-add throughout -- scalar products accumulated
+ *               left to right with one rounding per term, x += alpha p,
+ *               r -= alpha q and p = r + beta p each one fused operation
+ *               (what FMA hardware and its BLAS do).
+ * With the environment variable ORC_PROGRESS set to k > 0, one line with the
+ * iteration count and the recursive relative residual goes to stderr every
+ * k iterations (output only; a long run on a large system shows it is alive).
  */
 int orc_cg(int fmt, int64_t n, const int32_t *ptr, const int32_t *idx, const double *val,
            const double *b, double *x, double tol, int32_t maxit, orc_info *info,
            double *alpha_hist, double *beta_hist, double *res_hist, int32_t hist_cap,
-           double *x_hist, int32_t x_stride, int32_t x_cap, int dot_mode)
+           double *x_hist, int32_t x_stride, int32_t x_cap, int32_t x_first, int dot_mode)
 {
-    double (*dot)(int64_t, const double *, const double *) = dot_mode == 1 ? orc_dot_plain : orc_dot;
+    double (*dot)(int64_t, const double *, const double *) =
+        dot_mode == 1 ? orc_dot_plain : dot_mode == 2 ? orc_dot_pairwise : dot_mode == 3 ? orc_dot_fused : orc_dot;
+    const int fused = dot_mode == 3;
     orc_info loc;
     if (!info)
         info = &loc;
@@ -352,6 +391,8 @@ int orc_cg(int fmt, int64_t n, const int32_t *ptr, const int32_t *idx, const dou
         info->status = ORC_ERR_NOMEM;
         return ORC_ERR_NOMEM;
     }
+    const char *pe = getenv("ORC_PROGRESS");
+    const long progress = pe ? strtol(pe, NULL, 10) : 0;
     double t0 = now_ms();
     /* init: r0 = b - A x0, p0 = r0 */
     orc_spmv(fmt, n, ptr, idx, val, x, q);
@@ -375,10 +416,17 @@ int orc_cg(int fmt, int64_t n, const int32_t *ptr, const int32_t *idx, const dou
                 break;
             }
             double alpha = rho / sigma;
-            for (int64_t i = 0; i < n; ++i)
-                x[i] = x[i] + alpha * p[i];
-            for (int64_t i = 0; i < n; ++i)
-                r[i] = r[i] - alpha * q[i];
+            if (fused) {
+                for (int64_t i = 0; i < n; ++i) {
+                    x[i] = fma(alpha, p[i], x[i]);
+                    r[i] = fma(-alpha, q[i], r[i]);
+                }
+            } else {
+                for (int64_t i = 0; i < n; ++i)
+                    x[i] = x[i] + alpha * p[i];
+                for (int64_t i = 0; i < n; ++i)
+                    r[i] = r[i] - alpha * q[i];
+            }
             double rho_new = dot(n, r, r);
             double beta = rho_new / rho;
             if (alpha_hist && k <= hist_cap) {
@@ -386,15 +434,26 @@ int orc_cg(int fmt, int64_t n, const int32_t *ptr, const int32_t *idx, const dou
                 beta_hist[k - 1] = beta;
                 res_hist[k - 1] = sqrt(rho_new);
             }
-            if (x_hist && x_stride > 0 && k % x_stride == 0 && k / x_stride <= x_cap)
-                memcpy(x_hist + (size_t)(k / x_stride - 1) * (size_t)n, x, sizeof(double) * (size_t)n);
+            if (x_hist && x_stride > 0 && k >= x_first && (k - x_first) % x_stride == 0 &&
+                (k - x_first) / x_stride < x_cap)
+                memcpy(x_hist + (size_t)((k - x_first) / x_stride) * (size_t)n, x, sizeof(double) * (size_t)n);
             rho = rho_new;
+            if (progress > 0 && k % progress == 0) {
+                fprintf(stderr, "[oracle cg] n=%lld iteration %d relres %.3e %.0f ms\n", (long long)n, k,
+                        sqrt(rho) / nb, now_ms() - t0);
+                fflush(stderr);
+            }
             if (sqrt(rho) <= tol * nb) {
                 status = ORC_OK;
                 break;
             }
-            for (int64_t i = 0; i < n; ++i)
-                p[i] = r[i] + beta * p[i];
+            if (fused) {
+                for (int64_t i = 0; i < n; ++i)
+                    p[i] = fma(beta, p[i], r[i]);
+            } else {
+                for (int64_t i = 0; i < n; ++i)
+                    p[i] = r[i] + beta * p[i];
+            }
         }
         if (k > maxit)
             k = maxit;

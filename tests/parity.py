@@ -2,13 +2,25 @@
 
 CG on an ill-conditioned system stops ~kappa * tol away from the exact
 solution, so where it stops depends on rounding: two valid FP64 evaluations
-of the same iteration do not land on the same x.  The yardstick is the
-oracle's own spread -- its iteration with exactly rounded scalar products
-(the reference) against the same iteration with the plain left-to-right
-products (the paper leaves the summation order to a library routine): both
-are correct FP64 runs of the algorithm.  The GPU's solution must lie within
+of the same iteration do not land on the same x.  The 2-norm yardstick is
+the oracle's own spread, the larger of two distances:
 
-    ||x_gpu - x_oracle||_2 / ||x_oracle||_2  <=  max(1e-8, 10 * spread_2)
+* evaluation spread -- its iteration with exactly rounded scalar products
+  (the reference) against the same iteration with plain left-to-right,
+  pairwise-summed, or fused multiply-add arithmetic (the paper leaves the
+  scalar products and vector updates to a library routine): all are
+  correct FP64 runs of the algorithm;
+* stopping-step spread -- the oracle's own iterate after as many iterations
+  as the GPU needed, against its solution.  CG's residual is not monotone:
+  near the tolerance it can dip below it, rise and fall again, while x keeps
+  moving (its energy-norm error falls at every step).  On a 504-row FEM
+  system the oracle stops at step 301; a run whose residual at step 301 is
+  a little higher stops at 311, 3.9e-8 away in the 2-norm -- where an FP64
+  run with a library's blocked scalar products lands too.
+
+The GPU's solution must lie within
+
+    ||x_gpu - x_oracle||_2 / ||x_oracle||_2  <=  max(1e-8, 4 * spread_2)
 
 and, in the norm CG minimises, ||x_gpu - x_oracle||_A / ||x_oracle||_A <= 1e-8.
 On well-conditioned systems the spread is far below 1e-8 and the bar is the
@@ -23,8 +35,9 @@ import numpy as np
 
 import oracle
 
+ALT_DOTS = ("plain", "pairwise", "fused")  # the alternative evaluations of the iteration
 X_TOL = 1e-8          # relative solution difference at tol 1e-10 (2-norm floor, energy norm)
-SPREAD_FACTOR = 10.0  # allowed multiple of the oracle's own reduction-order spread
+SPREAD_FACTOR = 4.0   # allowed multiple of the oracle's own reduction-order spread
 
 _SPREAD = {}
 
@@ -38,20 +51,67 @@ def a_norm(fmt, arrs, v):
 
 
 def oracle_spread(fmt, arrs, b, x_ref, tol=1e-10, x0=None, maxit=200000):
-    """Relative 2-norm and energy-norm distance between the oracle's solution
-    x_ref (exact scalar products) and the oracle run with plain products."""
+    """Largest relative 2-norm and energy-norm distance between the oracle's
+    solution x_ref (exact scalar products) and the oracle runs with the
+    alternative arithmetic of ALT_DOTS; and the iteration counts of those
+    runs."""
     n = len(arrs[0]) - 1
     k = _key(b, n) + ("" if x0 is None else _key(x0, n)) + f":{tol}"
     if k not in _SPREAD:
-        xp, info, _ = oracle.cg(fmt, *arrs, b, x0=x0, tol=tol, maxit=maxit, plain_dots=True)
-        d = xp - x_ref
-        _SPREAD[k] = (float(np.linalg.norm(d) / np.linalg.norm(x_ref)),
-                      a_norm(fmt, arrs, d) / a_norm(fmt, arrs, x_ref), info["iters"])
+        s2 = sA = 0.0
+        its = []
+        for mode in ALT_DOTS:
+            xp, info, _ = oracle.cg(fmt, *arrs, b, x0=x0, tol=tol, maxit=maxit, dots=mode)
+            d = xp - x_ref
+            s2 = max(s2, float(np.linalg.norm(d) / np.linalg.norm(x_ref)))
+            sA = max(sA, a_norm(fmt, arrs, d) / a_norm(fmt, arrs, x_ref))
+            its.append(info["iters"])
+        _SPREAD[k] = (s2, sA, its)
     return _SPREAD[k]
 
 
-def x_bar(spread2):
-    return max(X_TOL, SPREAD_FACTOR * spread2)
+def step_spread(fmt, arrs, b, x_ref, k_ref, k_other, x0=None):
+    """Relative 2-norm distance between the oracle's iterate after k_other
+    iterations (no stopping test) and its solution x_ref after k_ref: the
+    same bits up to step min(k_ref, k_other)."""
+    if k_other == k_ref or k_other <= 0:
+        return 0.0
+    n = len(arrs[0]) - 1
+    k = _key(b, n) + ("" if x0 is None else _key(x0, n)) + f":step{k_other}"
+    if k not in _SPREAD:
+        xk, _, _ = oracle.cg(fmt, *arrs, b, x0=x0, tol=0.0, maxit=k_other)
+        _SPREAD[k] = float(np.linalg.norm(xk - x_ref) / np.linalg.norm(x_ref))
+    return _SPREAD[k]
+
+
+def stored_step_spread(ref, k_other):
+    """Stopping-step spread from a stored reference's table of
+    ||x_oracle(j) - x_oracle|| / ||x_oracle|| (every `step_stride` iterations
+    around its stop): the larger of the two tabulated steps around k_other;
+    None if k_other lies outside the table."""
+    tab = ref.get("step_table")
+    if not tab:
+        return None
+    js = np.array(tab["iters"])
+    ds = np.array(tab["dist2"])
+    if k_other == ref["iters"]:
+        return 0.0
+    if k_other < js[0] or k_other > js[-1]:
+        return None
+    lo = np.searchsorted(js, k_other, side="right") - 1
+    hi = min(lo + 1, js.size - 1)
+    return float(max(ds[lo], ds[hi]))
+
+
+def stored_spread(ref):
+    """The spread of a stored reference (tests/golden/make_oracle_reference.py):
+    the larger distance over its alternative evaluations."""
+    alts = [ref[k] for k in ("plain_dots", "pairwise_dots", "fused_dots") if k in ref]
+    return (max(a["spread2"] for a in alts), max(a["spreadA"] for a in alts), [a["iters"] for a in alts])
+
+
+def x_bar(spread2, step2=0.0):
+    return max(X_TOL, SPREAD_FACTOR * max(spread2, step2))
 
 
 def record(**kw):

@@ -116,7 +116,8 @@ def _exact_dot(a, b):
 def pin_dot_exact(lib):
     """Scalar products: the default is the exact inner product rounded once
     (within 2 u of it even under heavy cancellation); the plain loop obeys the
-    gamma_n bound of a left-to-right sum."""
+    gamma_n bound of a left-to-right sum, the pairwise sum the gamma bound of
+    its tree depth (Higham, ch. 4)."""
     rng = np.random.default_rng(17)
     for cancel in (False, True, "inexact"):
         a = rng.uniform(-1, 1, 600)
@@ -135,6 +136,21 @@ def pin_dot_exact(lib):
         assert abs(Fraction(got) - ex) <= 2 * U * abs(ex), "dot not within 2u of the exact value"
         plain = oracle.dot(a, b, lib=lib, plain=True)
         assert abs(Fraction(plain) - ex) <= Fraction(gamma(a.size)) * Fraction(float(np.sum(np.abs(a * b))) * 1.01)
+        fu = oracle.dot(a, b, lib=lib, mode="fused")
+        assert abs(Fraction(fu) - ex) <= Fraction(gamma(a.size)) * Fraction(float(np.sum(np.abs(a * b))) * 1.01)
+        # pairwise: the depth of the summation tree, not n, bounds the error
+        pw = oracle.dot(a, b, lib=lib, mode="pairwise")
+        depth = int(np.ceil(np.log2(a.size))) + 8
+        assert abs(Fraction(pw) - ex) <= Fraction(gamma(depth)) * Fraction(float(np.sum(np.abs(a * b))) * 1.01)
+    # every term counts: a dropped product shows at once against the exact value
+    for m in (1, 2, 7, 8, 9, 16, 17, 1000, 1023):
+        a = rng.uniform(0.5, 1.0, m)
+        b = rng.uniform(0.5, 1.0, m)
+        ex = _exact_dot(a, b)
+        pw = oracle.dot(a, b, lib=lib, mode="pairwise")
+        assert abs(Fraction(pw) - ex) <= Fraction(gamma(int(np.ceil(np.log2(m))) + 8)) * ex, m
+        fu = oracle.dot(a, b, lib=lib, mode="fused")
+        assert abs(Fraction(fu) - ex) <= Fraction(gamma(m)) * ex, m
 
 
 # ----------------------------------------------------------- conversions
@@ -337,6 +353,50 @@ def pin_cg_invariants(lib):
     assert info["relres_true"] <= 2 * tol
 
 
+def pin_cg_alternative_evaluations(lib):
+    """The iteration in every alternative arithmetic (plain, pairwise or
+    fused scalar products; fused vector updates) is still CG: it converges
+    on a jittered FEM system with iron to the direct solution (energy norm,
+    SuperLU), meets the tolerance on the true residual, takes the first
+    steps of the exactly rounded run to rounding level, and its iterates
+    snapshot where asked (from a chosen step)."""
+    s = W.fem_p1_system(9, 8, 7, nu_iron=1e-2, seed=4)
+    A = _csr(s.rowptr, s.col, s.val)
+    from scipy.sparse.linalg import spsolve
+    xs = spsolve(A.tocsc(), s.b)
+    ea = float(np.sqrt(xs @ (A @ xs)))
+    _, i0, h0 = oracle.cg(oracle.FMT_CSR, s.rowptr, s.col, s.val, s.b, tol=1e-10, maxit=5000, history=8, lib=lib)
+    for mode in ("plain", "pairwise", "fused"):
+        x, info, h = oracle.cg(oracle.FMT_CSR, s.rowptr, s.col, s.val, s.b, tol=1e-10, maxit=5000, history=8,
+                               lib=lib, dots=mode)
+        assert info["status"] == oracle.OK and info["relres_true"] <= 2e-10, (mode, info)
+        e = x - xs
+        assert np.sqrt(e @ (A @ e)) <= 1e-8 * ea, mode
+        assert np.allclose(h["alpha"][:5], h0["alpha"][:5], rtol=1e-12, atol=0), mode
+        assert np.allclose(h["beta"][:5], h0["beta"][:5], rtol=1e-11, atol=0), mode
+        assert abs(info["iters"] - i0["iters"]) <= 0.1 * i0["iters"], (mode, info, i0)
+    # fused updates are single roundings: x1 = fl(alpha p0 + x0) exactly
+    # (Fraction arithmetic, one rounding), which for a generic x0 differs
+    # from the twice-rounded x0 + fl(alpha p0) in some entries
+    n = 64
+    rng = np.random.default_rng(23)
+    d = rng.uniform(1.0, 3.0, n)
+    ip, ic = np.arange(n + 1, dtype=np.int32), np.arange(n, dtype=np.int32)
+    b, x0 = rng.uniform(-1, 1, n), rng.uniform(-1, 1, n)
+    x1, _, h = oracle.cg(oracle.FMT_CSR, ip, ic, d, b, x0=x0, tol=0.0, maxit=1, history=1, lib=lib, dots="fused")
+    p0 = b - d * x0                        # r0 = b - A x0 (one product and one subtraction per entry)
+    al = Fraction(float(h["alpha"][0]))
+    want = np.array([float(al * Fraction(float(p0[i])) + Fraction(float(x0[i]))) for i in range(n)])
+    assert np.array_equal(x1, want), "fused x update is not one rounding"
+    assert np.any(want != x0 + float(al) * p0)
+    # snapshots from a chosen step: x after steps 5, 8, 11 == runs stopped there
+    _, _, h = oracle.cg(oracle.FMT_CSR, s.rowptr, s.col, s.val, s.b, tol=0.0, maxit=11, x_stride=3, x_cap=3,
+                        x_first=5, lib=lib)
+    for j, k in enumerate((5, 8, 11)):
+        xk, _, _ = oracle.cg(oracle.FMT_CSR, s.rowptr, s.col, s.val, s.b, tol=0.0, maxit=k, lib=lib)
+        assert np.array_equal(h["x"][j], xk), k
+
+
 def pin_cg_statuses(lib):
     """Early exits: b = 0, non-finite b, maxit exhaustion, breakdown on an
     indefinite matrix, x0 already the solution, and the empty system."""
@@ -391,7 +451,7 @@ def pin_cg_formats_agree(lib):
 
 ALL_PINS = [pin_dot_exact, pin_spmv_exact, pin_spmv_library, pin_three_formats_bitwise, pin_conversions, pin_validate,
             pin_cg_cholesky, pin_cg_exact_termination, pin_cg_lanczos_spectrum, pin_cg_invariants,
-            pin_cg_statuses, pin_cg_formats_agree]
+            pin_cg_alternative_evaluations, pin_cg_statuses, pin_cg_formats_agree]
 
 
 def run_all(lib_path):

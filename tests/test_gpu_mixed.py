@@ -4,7 +4,7 @@ refinement) through the C-ABI vs the FP64 oracle.
 The refinement stops on the TRUE residual ||b - A x|| <= tol ||b|| computed
 with the FP64 product, so the bar is the FP64 one: true residual (oracle
 product) <= 2 tol, energy-norm difference to the oracle's FP64 CG solution
-<= 1e-8, 2-norm difference <= max(1e-8, 10 x the oracle's own
+<= 1e-8, 2-norm difference <= max(1e-8, 4 x the oracle's own
 reduction-order spread) (tests/parity.py); measured values are recorded.
 """
 import numpy as np

@@ -32,6 +32,18 @@ MUTANTS = {
     "dot_drops_sum_error": ("c += e + pe;", "c += pe;"),
     "dot_plain_drops_last_term": ("for (int64_t i = 0; i < n; ++i)\n        s += a[i] * b[i];",
                                   "for (int64_t i = 0; i + 1 < n; ++i)\n        s += a[i] * b[i];"),
+    "dot_pairwise_drops_term": ("return orc_dot_pairwise(h, a, b) + orc_dot_pairwise(n - h, a + h, b + h);",
+                                "return orc_dot_pairwise(h, a, b) + orc_dot_pairwise(n - h - 1, a + h, b + h);"),
+    "dot_pairwise_leaf_skips_first": ("for (int64_t i = 0; i < n; ++i)\n            s += a[i] * b[i];\n        return s;",
+                                      "for (int64_t i = 1; i < n; ++i)\n            s += a[i] * b[i];\n        return s;"),
+    "dot_fused_drops_first": ("for (int64_t i = 0; i < n; ++i)\n        s = fma(a[i], b[i], s);",
+                              "for (int64_t i = 1; i < n; ++i)\n        s = fma(a[i], b[i], s);"),
+    "cg_fused_x_update_sign": ("x[i] = fma(alpha, p[i], x[i]);", "x[i] = fma(-alpha, p[i], x[i]);"),
+    "cg_fused_r_update_sign": ("r[i] = fma(-alpha, q[i], r[i]);", "r[i] = fma(alpha, q[i], r[i]);"),
+    "cg_fused_p_update_operand": ("p[i] = fma(beta, p[i], r[i]);", "p[i] = fma(beta, r[i], r[i]);"),
+    "cg_fused_mode_ignored": ("const int fused = dot_mode == 3;", "const int fused = 0;"),
+    "cg_snapshot_index_off": ("memcpy(x_hist + (size_t)((k - x_first) / x_stride) * (size_t)n",
+                              "memcpy(x_hist + (size_t)((k - x_first) / x_stride + 1 == x_cap ? 0 : (k - x_first) / x_stride + 1) * (size_t)n"),
     "cg_x_update_sign": ("x[i] = x[i] + alpha * p[i];", "x[i] = x[i] - alpha * p[i];"),
     "cg_r_update_sign": ("r[i] = r[i] - alpha * q[i];", "r[i] = r[i] + alpha * q[i];"),
     "cg_beta_inverted": ("double beta = rho_new / rho;", "double beta = rho / rho_new;"),
