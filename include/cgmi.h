@@ -101,13 +101,24 @@ typedef struct {
     int32_t cached_loads;    /* 1 = the sliced product reads the matrix with ordinary loads, so that
                                 it stays in the Infinity Cache between iterations (small enough);
                                 0 = non-temporal loads */
-    int32_t reserved;
+    int32_t compact;         /* symmetric CSR: 1 = compact blocks grown on the graph of A (each block
+                                stores its own rows, parks the rest); 0 = coloured line ranges */
     int64_t slots;           /* scatter formats: total (block, target) write slots */
     int64_t plan_bytes;      /* device bytes of the plan beyond ptr / idx / vals */
+    int64_t parked;          /* scatter formats: slot sums parked and added by the row pass */
+    int64_t device_bytes;    /* every device byte the handle holds (matrix, plan, work vectors) */
 } cg_plan_stats;
 
 /*
  * cg_create -- copy A to the device and plan its product.
+ * The paper's problem (section I: A sparse, symmetric positive definite,
+ * known) in the storage of section III: full CSR, or the symmetric storage
+ * of one triangle plus the diagonal (given as the paper keeps it with
+ * CG_LOWER, 1-based with index_base 1 -- section III reads its matrices from
+ * files in full or symmetric CSR); CSC as the abstract names it.  The plan
+ * replaces the paper's atomic updates of the transpose product (section III,
+ * SCSC kernel) by an atomic-free one (compact blocks or coloured line ranges
+ * for symmetric CSR, two-colour column panels for CSC).
  *   out         receives the handle (NULL on error; nothing is leaked)
  *   format      CG_FMT_*
  *   n           order of A (n >= 0; n == 0 is an empty system)
@@ -136,6 +147,11 @@ int cg_set_batch(cg_handle *h, int32_t iters_per_launch);
 
 /*
  * cg_solve -- CG from x0 to ||r||_2 <= tol ||b||_2 or maxit products.
+ * The iteration of section III (alpha = r'r / p'Ap, x += alpha p,
+ * r -= alpha Ap, beta = r'r / r_old'r_old, p = r + beta p), with the one
+ * product Ap per iteration of that section and every scalar kept on the
+ * device -- the paper moves only the scalars between host and GPU; here the
+ * host reads a status word once per launched group of iterations.
  *   b     device, n float64 (read only)
  *   x     device, n float64: in x0, out the solution / last iterate; a
  *         buffer distinct from b (CG_ERR_ARG otherwise).
@@ -218,8 +234,11 @@ void cg_batch_destroy(cg_batch *h);
  * failed cg_batch_create.  Never NULL. */
 const char *cg_batch_last_error(const cg_batch *h);
 
-/* y = A x (device pointers, n float64 each, x and y must not overlap).
- * Asynchronous on the handle's stream. */
+/* y = A x (device pointers, n float64 each, x and y must not overlap):
+ * the sparse matrix-vector product of section III in the handle's storage
+ * (CSR: one sum per row; symmetric: the stored triangle by rows plus its
+ * mirror by columns; CSC: column scatter).  Asynchronous on the handle's
+ * stream. */
 int cg_spmv(cg_handle *h, const double *x, double *y);
 
 /*
@@ -296,7 +315,9 @@ const char *cg_fem_last_error(const cg_fem *f);
 int cg_get_stats(const cg_handle *h, cg_plan_stats *stats);
 
 /* Frees every device and host resource of the handle (NULL is a no-op).
- * Waits for the handle's outstanding work first. */
+ * Waits for the handle's outstanding work first.  (Lifetime management has
+ * no counterpart in the paper, whose program holds one matrix from file read
+ * to solution -- section III.) */
 void cg_destroy(cg_handle *h);
 
 /* Static text for a status code. */
@@ -326,12 +347,35 @@ int cg_analyze(int format, int64_t n, const int32_t *ptr, const int32_t *idx, co
  *   slot_flags                           [slots] uint8: bit0 first writer of
  *                                        that row, bit1 last writer
  *   slot_count                           [slots] int32: products summed into it
- * Returns CG_ERR_ARG for CG_FMT_CSR and CG_FMT_CSC (see cg_analyze_panels).
+ * Returns CG_ERR_ARG for CG_FMT_CSR and CG_FMT_CSC (see cg_analyze_panels)
+ * and for a symmetric matrix planned in compact blocks (cg_analyze_compact).
  */
 int cg_analyze_export(int format, int64_t n, const int32_t *ptr, const int32_t *idx, int index_base,
                       int32_t *blk_color, int32_t *blk_line0, int32_t *blk_line1, int32_t *blk_entry0,
                       int32_t *blk_entry1, int64_t *blk_slot0, int32_t *slot_target, uint8_t *slot_flags,
                       int32_t *slot_count);
+
+/*
+ * Host-only export of the compact-block plan of CG_FMT_SYM_CSR (chosen when
+ * every stored row has at most 8 entries; cg_plan_stats.compact == 1).
+ * Blocks are grown on the graph of A (breadth first from the lowest free
+ * row, at most 256 rows each); a block stores y for its own rows and parks
+ * its sums for the other rows its mirrored products reach (the transpose
+ * half of the symmetric product, section III of the paper), so no two
+ * blocks write one location.  Sizes from cg_analyze: n, scatter_blocks,
+ * slots.
+ *   block_of     [n] int32: block of each row
+ *   blk_slot0    [scatter_blocks+1] int64: slots of block b are
+ *                [blk_slot0[b], blk_slot0[b+1])
+ *   blk_lines    [scatter_blocks] int32: its own rows = its first slots
+ *   slot_target  [slots] int32: row of y each slot adds to
+ *   slot_count   [slots] int32: mirrored products summed into the slot
+ * Any output may be NULL.  Returns CG_ERR_ARG if the plan of these arrays is
+ * not compact (other formats, or a row longer than 8 entries).  Same errors
+ * as cg_analyze otherwise.
+ */
+int cg_analyze_compact(int64_t n, const int32_t *ptr, const int32_t *idx, int index_base, int32_t *block_of,
+                       int64_t *blk_slot0, int32_t *blk_lines, int32_t *slot_target, int32_t *slot_count);
 
 /*
  * Host-only export of the CSC plan ("column panels"), so it can be checked

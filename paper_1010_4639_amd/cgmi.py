@@ -30,7 +30,7 @@ EXPORTS = ("cg_create", "cg_set_stream", "cg_set_batch", "cg_solve", "cg_solve_m
            "cg_batch_create", "cg_batch_set_stream", "cg_batch_spmm", "cg_batch_autotune", "cg_batch_solve",
            "cg_batch_destroy", "cg_batch_last_error", "cg_set_values", "cg_pattern_grad", "cg_fem_create",
            "cg_fem_set_stream", "cg_fem_pattern", "cg_fem_assemble", "cg_fem_nu_grad", "cg_fem_destroy",
-           "cg_fem_last_error", "cg_analyze_panels")
+           "cg_fem_last_error", "cg_analyze_panels", "cg_analyze_compact")
 
 
 class cg_info(ctypes.Structure):
@@ -48,8 +48,8 @@ class cg_plan_stats(ctypes.Structure):
                 ("vec_blocks", ctypes.c_int32), ("colors", ctypes.c_int32),
                 ("scatter_blocks", ctypes.c_int32), ("max_block_entries", ctypes.c_int32),
                 ("slices", ctypes.c_int32),
-                ("cached_loads", ctypes.c_int32), ("reserved", ctypes.c_int32), ("slots", ctypes.c_int64),
-                ("plan_bytes", ctypes.c_int64)]
+                ("cached_loads", ctypes.c_int32), ("compact", ctypes.c_int32), ("slots", ctypes.c_int64),
+                ("plan_bytes", ctypes.c_int64), ("parked", ctypes.c_int64), ("device_bytes", ctypes.c_int64)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
@@ -106,6 +106,7 @@ def load():
     lib.cg_batch_last_error.argtypes = [_VP]
     lib.cg_batch_last_error.restype = ctypes.c_char_p
     lib.cg_analyze_panels.argtypes = [i64, _VP, _VP, ctypes.c_int] + [_VP] * 7
+    lib.cg_analyze_compact.argtypes = [i64, _VP, _VP, ctypes.c_int] + [_VP] * 5
     lib.cg_set_values.argtypes = [_VP, _VP]
     lib.cg_pattern_grad.argtypes = [_VP, _VP, _VP, _VP]
     lib.cg_fem_create.argtypes = [ctypes.POINTER(_VP), i64, _VP, i64, _VP, _VP, i64]
@@ -119,9 +120,10 @@ def load():
     lib.cg_fem_last_error.restype = ctypes.c_char_p
     for nm in ("cg_batch_create", "cg_batch_set_stream", "cg_batch_spmm", "cg_batch_autotune", "cg_batch_solve",
                "cg_set_values", "cg_pattern_grad", "cg_fem_create", "cg_fem_set_stream", "cg_fem_pattern",
-               "cg_fem_assemble", "cg_fem_nu_grad", "cg_analyze_panels"):
+               "cg_fem_assemble", "cg_fem_nu_grad", "cg_analyze_panels", "cg_analyze_compact"):
         getattr(lib, nm).restype = ctypes.c_int
-    for nm in ("cg_create", "cg_set_stream", "cg_set_batch", "cg_solve", "cg_solve_mixed", "cg_spmv", "cg_get_stats",
+    for nm in ("cg_create", "cg_set_stream", "cg_set_batch", "cg_solve", "cg_solve_mixed", "cg_spmv",
+               "cg_get_stats",
                "cg_analyze", "cg_analyze_export"):
         getattr(lib, nm).restype = ctypes.c_int
     _lib = lib
@@ -232,6 +234,27 @@ def cg_analyze_export(fmt, n, ptr, idx, index_base=0):
     st = load().cg_analyze_export(_fmt(fmt), int(n), _np_ptr(ptr), _np_ptr(idx), int(index_base),
                                   *[_np_ptr(out[k]) for k in ("color", "line0", "line1", "entry0", "entry1",
                                                               "slot0", "target", "flags", "count")])
+    out["stats"] = stats
+    return st, out
+
+
+def cg_analyze_compact(n, ptr, idx, index_base=0):
+    """Host-only compact-block plan of a symmetric (upper) matrix; returns
+    (status, dict of numpy arrays)."""
+    lib = load()
+    st, stats = cg_analyze(CG_FMT_SYM_CSR, n, ptr, idx, None, index_base)
+    if st != CG_OK:
+        return st, None
+    nb, ns = stats["scatter_blocks"], stats["slots"]
+    out = dict(block_of=np.zeros(max(n, 1), np.int32), slot0=np.zeros(nb + 1, np.int64),
+               lines=np.zeros(max(nb, 1), np.int32), target=np.zeros(max(ns, 1), np.int32),
+               count=np.zeros(max(ns, 1), np.int32))
+    p = np.ascontiguousarray(ptr, dtype=np.int32)
+    i = np.ascontiguousarray(idx, dtype=np.int32)
+    st = lib.cg_analyze_compact(int(n), _np_ptr(p), _np_ptr(i), int(index_base),
+                                *[_np_ptr(out[k]) for k in ("block_of", "slot0", "lines", "target", "count")])
+    out["block_of"], out["lines"] = out["block_of"][:n], out["lines"][:nb]
+    out["target"], out["count"] = out["target"][:ns], out["count"][:ns]
     out["stats"] = stats
     return st, out
 

@@ -34,6 +34,7 @@ struct cg_handle {
     hipStream_t stream = nullptr;  // caller's stream (null stream by default)
     hipStream_t capture = nullptr; // private stream used only to record the graph
     std::vector<void *> allocs;
+    size_t dev_bytes = 0; // sum of the allocations
     double *r = nullptr, *p = nullptr, *q = nullptr, *xw = nullptr;
     double *sig = nullptr, *sig_spmv = nullptr, *rho = nullptr, *bb = nullptr;
     DevState *st = nullptr;
@@ -83,6 +84,7 @@ int dalloc(cg_handle *h, T **out, size_t count)
     if (e != hipSuccess)
         return hip_fail(h->err, e, "hipMalloc");
     h->allocs.push_back(p);
+    h->dev_bytes += bytes;
     *out = static_cast<T *>(p);
     return CG_OK;
 }
@@ -233,6 +235,53 @@ int upload_all(cg_handle *h, const std::vector<int32_t> &ptr0, const std::vector
         m.scatter_wgs = p.scatter_wgs();
         if (h->mixed && !p.slices && (st = dalloc(h, &m.pn_val32, p.pn_src.size())) != CG_OK)
             return st;
+    } else if (p.sym_compact && n > 0) {
+        // compact blocks (plan.h): per row, its parked sums in ascending
+        // block order for the row pass
+        std::vector<int32_t> rsp((size_t)n + 1, 0), rsi((size_t)p.cp_parked);
+        for (const CompactBlock &b : p.cp_blocks)
+            for (int32_t s = b.nl; s < b.nslots; ++s)
+                rsp[p.slot_target[b.slot0 + s] + 1]++;
+        for (int64_t i = 0; i < n; ++i)
+            rsp[i + 1] += rsp[i];
+        {
+            std::vector<int32_t> next(rsp.begin(), rsp.end() - 1);
+            for (const CompactBlock &b : p.cp_blocks)
+                for (int32_t s = b.nl; s < b.nslots; ++s)
+                    rsi[next[p.slot_target[b.slot0 + s]]++] = b.park0 + (s - b.nl);
+        }
+        CompactBlock *cb;
+        int32_t *tg, *drsp, *drsi, *sidx, *ssrc;
+        uint16_t *sg, *tl;
+        double *part, *sv;
+        const size_t np = std::max<size_t>(p.ss_src.size(), 1);
+        if ((st = upload(h, &cb, p.cp_blocks.data(), p.cp_blocks.size())) != CG_OK ||
+            (st = upload(h, &tg, p.slot_target.data(), p.slot_target.size())) != CG_OK ||
+            (st = upload(h, &sg, p.seg.data(), p.seg.size())) != CG_OK ||
+            (st = upload(h, &tl, p.ss_tl.data(), p.ss_tl.size())) != CG_OK ||
+            (st = dalloc(h, &part, (size_t)p.cp_parked)) != CG_OK ||
+            (st = upload(h, &drsp, rsp.data(), rsp.size())) != CG_OK ||
+            (st = upload(h, &drsi, rsi.data(), rsi.size())) != CG_OK ||
+            (st = upload(h, &sidx, p.ss_idx.data(), p.ss_idx.size())) != CG_OK ||
+            (st = upload(h, &ssrc, p.ss_src.data(), p.ss_src.size())) != CG_OK || (st = dalloc(h, &sv, np)) != CG_OK)
+            return st;
+        m.compact = true;
+        m.cblocks = cb;
+        m.parked = p.cp_parked;
+        m.slot_target = tg;
+        m.seg = sg;
+        m.tl = tl;
+        m.part = part;
+        m.rs_ptr = drsp;
+        m.rs_idx = drsi;
+        m.has_c0 = nullptr;
+        m.ss_idx = sidx;
+        m.ss_src = ssrc;
+        m.ss_val = sv;
+        m.ss_positions = (int64_t)p.ss_src.size();
+        m.scatter_wgs = p.scatter_wgs();
+        if (h->mixed && (st = dalloc(h, &m.ss_val32, np)) != CG_OK)
+            return st;
     } else if (p.format != kCsr && n > 0) {
         // device arrays in colour order: the blocks of one colour, and their
         // write slots, are contiguous
@@ -374,7 +423,9 @@ void fill_stats(const Plan &p, cg_plan_stats *s)
     s->vec_blocks = p.vec_blocks;
     s->colors = p.ncolors;
     s->max_block_entries = p.max_entries;
-    s->slices = p.slices || p.sym_slices ? 1 : 0;
+    s->slices = p.slices || p.sym_slices || p.sym_compact ? 1 : 0;
+    s->compact = p.sym_compact ? 1 : 0;
+    s->parked = p.sym_compact ? p.cp_parked : 0;
     s->cached_loads = p.matrix_cached() ? 1 : 0;
     s->slots = p.panel ? (int64_t)p.pn_slot_target.size() : (int64_t)p.slot_target.size();
     s->plan_bytes = p.device_bytes();
@@ -521,7 +572,7 @@ int refresh_values(cg_handle *h)
         launch_permute(nnz, m.val, m.pn_src, m.pn_val, h->stream);
     if (m.slices)
         launch_permute((int64_t)h->plan.sl_src.size(), m.val, m.sl_src, m.sl_val, h->stream);
-    if (m.sym_slices)
+    if (m.sym_slices || m.compact)
         launch_permute(m.ss_positions, m.val, m.ss_src, m.ss_val, h->stream);
     HIP_TRY(h, hipGetLastError());
     if (h->mixed && m.n > 0) {
@@ -532,7 +583,7 @@ int refresh_values(cg_handle *h)
             launch_permute(nnz, m.val32, m.pn_src, m.pn_val32, h->stream);
         if (m.slices)
             launch_permute((int64_t)h->plan.sl_src.size(), m.val32, m.sl_src, m.sl_val32, h->stream);
-        if (m.sym_slices)
+        if (m.sym_slices || m.compact)
             launch_permute(m.ss_positions, m.val32, m.ss_src, m.ss_val32, h->stream);
         HIP_TRY(h, hipGetLastError());
     }
@@ -598,6 +649,10 @@ int cg_analyze_export(int format, int64_t n, const int32_t *ptr, const int32_t *
         Plan plan;
         if (st == CG_OK)
             st = build_plan(format, n, p0.data(), i0.data(), scatter_entries_override(), plan, err);
+        if (st == CG_OK && plan.sym_compact) {
+            err = "this symmetric matrix is planned in compact blocks (cg_analyze_compact)";
+            st = CG_ERR_ARG;
+        }
         if (st == CG_OK) {
             for (int b = 0; b < plan.nblocks; ++b) {
                 const ScatterBlock &bk = plan.blocks[b];   // block-id order
@@ -613,6 +668,46 @@ int cg_analyze_export(int format, int64_t n, const int32_t *ptr, const int32_t *
             if (slot_target) std::memcpy(slot_target, plan.slot_target.data(), ns * 4);
             if (slot_flags) std::memcpy(slot_flags, plan.slot_flag.data(), ns);
             if (slot_count) std::memcpy(slot_count, plan.slot_count.data(), ns * 4);
+        }
+    } catch (const std::bad_alloc &) {
+        err = "host allocation failed";
+        st = CG_ERR_NOMEM;
+    }
+    g_err = st == CG_OK ? std::string() : err;
+    return st;
+}
+
+int cg_analyze_compact(int64_t n, const int32_t *ptr, const int32_t *idx, int index_base, int32_t *block_of,
+                       int64_t *blk_slot0, int32_t *blk_lines, int32_t *slot_target, int32_t *slot_count)
+{
+    std::vector<int32_t> p0, i0;
+    std::string err;
+    int st;
+    try {
+        st = validate_and_normalise(kSymCsr, n, ptr, idx, nullptr, index_base, 0, p0, i0, err);
+        Plan plan;
+        if (st == CG_OK)
+            st = build_plan(kSymCsr, n, p0.data(), i0.data(), scatter_entries_override(), plan, err);
+        if (st == CG_OK && !plan.sym_compact) {
+            err = "this matrix is not planned in compact blocks";
+            st = CG_ERR_ARG;
+        }
+        if (st == CG_OK) {
+            if (block_of)
+                std::memcpy(block_of, plan.cp_block_of.data(), (size_t)n * 4);
+            for (int b = 0; b < plan.nblocks; ++b) {
+                if (blk_slot0)
+                    blk_slot0[b] = plan.cp_blocks[b].slot0;
+                if (blk_lines)
+                    blk_lines[b] = plan.cp_blocks[b].nl;
+            }
+            if (blk_slot0)
+                blk_slot0[plan.nblocks] = (int64_t)plan.slot_target.size();
+            const size_t ns = plan.slot_target.size();
+            if (slot_target)
+                std::memcpy(slot_target, plan.slot_target.data(), ns * 4);
+            if (slot_count)
+                std::memcpy(slot_count, plan.slot_count.data(), ns * 4);
         }
     } catch (const std::bad_alloc &) {
         err = "host allocation failed";
@@ -943,6 +1038,7 @@ int cg_get_stats(const cg_handle *h, cg_plan_stats *stats)
     if (!h || !stats)
         return CG_ERR_ARG;
     fill_stats(h->plan, stats);
+    stats->device_bytes = (int64_t)h->dev_bytes;
     return CG_OK;
 }
 

@@ -10,10 +10,17 @@
 
 namespace cgmi {
 
-// Iteration state kept in device memory.  Every kernel reads it at entry;
-// a field is only written by one thread (block 0, thread 0) of a kernel in
-// which no other block reads that field, so kernel boundaries are the only
-// synchronisation needed.
+// Iteration state kept in device memory.  Every kernel reads it at entry,
+// and every field is written by one thread only (block 0, thread 0), so
+// kernel boundaries are the synchronisation.  One field is written while
+// other blocks of the same kernel may still read it: `status`, set by the
+// stop decision of iter_gate and by k_update_r on breakdown.  That is safe
+// because every block takes the same decision from fields that kernel does
+// not write (conv_next, k, maxit, and the same p'Ap partials): a block that
+// still reads kRun reaches the same stop and returns without writing
+// anything, exactly as a block that already reads the new status does.  A
+// gate whose decision could differ between blocks would need the status
+// written in a later kernel instead.
 enum DevStatus : int32_t {
     kRun = 0,        // iterating
     kConverged = 1,  // ||r|| <= tol ||b||
@@ -81,6 +88,13 @@ struct DevMatrix {
     double *ss_val = nullptr;              // values at the positions (0 at padding)
     float *ss_val32 = nullptr;             // mixed precision: val32 at the positions
     int64_t ss_positions = 0;
+    // symmetric CSR, compact blocks (plan.h): positions in ss_idx / ss_val,
+    // slots in slot_target / seg, contributions in tl, parked sums in part
+    // with per-row lists rs_ptr / rs_idx (has_c0 unused: every row is stored
+    // by the block that owns its line)
+    bool compact = false;
+    const CompactBlock *cblocks = nullptr;
+    int64_t parked = 0;
     // CSC column panels (nblocks = chunks, scatter_wgs = their workgroups)
     bool panel = false;
     bool pn_gather = false;               // some row has parked sums or no writer
@@ -96,7 +110,10 @@ struct DevMatrix {
     int vec_blocks = 0, vec_chunk = 0;
     int spmv_blocks() const { return format == kCsr || slices ? csr_blocks : scatter_wgs; }
     // the product ends with a row pass (parked slot sums, rows with no writer)
-    bool row_pass() const { return panel ? pn_gather : (format == kSymCsr && ncolors > 1); }
+    bool row_pass() const
+    {
+        return panel ? pn_gather : compact ? parked > 0 : (format == kSymCsr && ncolors > 1);
+    }
 };
 
 // Iteration context: null st = plain product (no gating, p'q partials still

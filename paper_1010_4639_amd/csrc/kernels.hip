@@ -30,6 +30,20 @@ __device__ __forceinline__ T matrix_load(const T *p)
         return *p;
 }
 
+// Two-element vectors for the paired loads of the sliced layout (native
+// vector types, which the non-temporal load builtin accepts).
+typedef int int2v __attribute__((ext_vector_type(2)));
+template <class T>
+struct Vec2;
+template <>
+struct Vec2<double> {
+    typedef double type __attribute__((ext_vector_type(2)));
+};
+template <>
+struct Vec2<float> {
+    typedef float type __attribute__((ext_vector_type(2)));
+};
+
 // Start of an iteration (before its product): stop when the current residual
 // meets the tolerance (decided and published by the previous x/p update, or by
 // the initialisation) or maxit products are done.  Every workgroup reads the
@@ -279,11 +293,27 @@ __global__ __launch_bounds__(kBlock) void k_spmv_slices(int nl, int ns, const in
 #pragma unroll
             for (int j = 0; j < S; ++j)
 #pragma unroll
-                for (int u = 0; u < U; ++u) {
-                    const bool ok = k0 + u < len[j];
-                    const int e = e0[j] + (k0 + u) * kSliceRows + lane;
-                    c[j][u] = ok ? matrix_load<NT>(col + e) : -1;
-                    v[j][u] = ok ? matrix_load<NT>(val + e) : VT(0);
+                for (int u = 0; u < U; u += 2) {
+                    // entries k, k + 1 side by side (one 8- / 16-byte load per
+                    // lane), or the single last entry of an odd-width slice
+                    const int k = k0 + u;
+                    const int e = e0[j] + (k >> 1) * (2 * kSliceRows) + 2 * lane;
+                    if (k + 1 < len[j]) {
+                        const int2v cc = matrix_load<NT>(reinterpret_cast<const int2v *>(col + e));
+                        const typename Vec2<VT>::type vv = matrix_load<NT>(
+                            reinterpret_cast<const typename Vec2<VT>::type *>(val + e));
+                        c[j][u] = cc.x;
+                        c[j][u + 1] = cc.y;
+                        v[j][u] = vv.x;
+                        v[j][u + 1] = vv.y;
+                    } else {
+                        const bool ok = k < len[j];
+                        const int e1 = e0[j] + k * kSliceRows + lane;
+                        c[j][u] = ok ? matrix_load<NT>(col + e1) : -1;
+                        v[j][u] = ok ? matrix_load<NT>(val + e1) : VT(0);
+                        c[j][u + 1] = -1;
+                        v[j][u + 1] = VT(0);
+                    }
                 }
 #pragma unroll
             for (int j = 0; j < S; ++j)
@@ -648,6 +678,109 @@ __global__ __launch_bounds__(kBlock) void k_scatter_slices(
         sig_part[wg] = sig;
 }
 
+// Compact blocks of the symmetric format (plan.h): thread t holds own line
+// t of the block (its row index from the block's first slots), loads that
+// line's entries (two per load, coalesced over t), sums the stored row in
+// registers left to right from rounded products, and parks the mirror
+// products a_e x_t in LDS.  After one barrier each slot sums its
+// contributions in the plan's order: own-line slots add them to their row
+// and store y (the block owns those rows; nobody else stores them), the other
+// slots park their sum for the row pass.  Fused epilogue: x'y as
+// sum_slots x_target * sum.
+template <int SU, bool NT, class VT, class PT>
+__global__ __launch_bounds__(kBlock) void k_scatter_compact(
+    const int32_t *__restrict__ sidx, const VT *__restrict__ sval, const CompactBlock *__restrict__ blocks,
+    int nblocks, const int32_t *__restrict__ slot_target, const uint16_t *__restrict__ seg,
+    const uint16_t *__restrict__ tl, const PT *__restrict__ x, double *__restrict__ y, double *__restrict__ part,
+    double *__restrict__ sig_part, DevState *st)
+{
+#pragma clang fp contract(off)
+    constexpr int E = kStreamPerThread;
+    __shared__ double sp[kMaxScatterEntries];
+    __shared__ uint16_t tv[kMaxScatterEntries];
+    __shared__ double red[kWaves];
+    const int wg = xcd_remap(blockIdx.x, gridDim.x);
+    if (st != nullptr && !iter_gate(st))
+        return;
+    const int t = threadIdx.x;
+    const int b0 = (int)((int64_t)wg * nblocks / gridDim.x);
+    const int b1 = (int)((int64_t)(wg + 1) * nblocks / gridDim.x);
+    double sig = 0.0;
+    for (int b = b0; b < b1; ++b) {
+        const CompactBlock bk = blocks[b];
+        const int nl = bk.nl, L = bk.len;
+        const bool mine = t < nl;
+        // ---- independent loads
+        for (int i = t; i < bk.ntl; i += kBlock)
+            tv[i] = tl[bk.tl0 + i];
+        const int line = mine ? matrix_load<NT>(slot_target + bk.slot0 + t) : -1;
+        int c[E];
+        double v[E];
+#pragma unroll
+        for (int m = 0; m < E; m += 2) {
+            // entries m, m + 1 side by side (one 8- / 16-byte load), or the
+            // single last entry of an odd width
+            if (mine && m + 1 < L) {
+                const int q = bk.pos0 + m * nl + 2 * t;
+                const int2v cc = matrix_load<NT>(reinterpret_cast<const int2v *>(sidx + q));
+                const typename Vec2<VT>::type vv =
+                    matrix_load<NT>(reinterpret_cast<const typename Vec2<VT>::type *>(sval + q));
+                c[m] = cc.x;
+                c[m + 1] = cc.y;
+                v[m] = (double)vv.x;
+                v[m + 1] = (double)vv.y;
+            } else {
+                const bool ok = mine && m < L;
+                const int q = bk.pos0 + m * nl + t;
+                c[m] = ok ? matrix_load<NT>(sidx + q) : -1;
+                v[m] = ok ? (double)matrix_load<NT>(sval + q) : 0.0;
+                c[m + 1] = -1;
+                v[m + 1] = 0.0;
+            }
+        }
+        const double xo = mine ? (double)x[line] : 0.0;
+        // ---- gathers
+        double xg[E];
+#pragma unroll
+        for (int m = 0; m < E; ++m)
+            xg[m] = c[m] >= 0 ? (double)x[c[m]] : 0.0;
+        // ---- own row in registers; mirror products (not the diagonal) to LDS
+        double own = 0.0;
+#pragma unroll
+        for (int m = 0; m < E; ++m)
+            if (c[m] >= 0) {
+                own = own + v[m] * xg[m];
+                if (c[m] != line)
+                    sp[m * nl + t] = v[m] * xo;
+            }
+        __syncthreads();
+        // ---- slot sums: own lines store y, the others park
+        const uint16_t *sg = seg + bk.seg0;
+#pragma unroll
+        for (int u = 0; u < SU; ++u) {
+            const int s = t + u * kBlock;
+            if (s >= bk.nslots)
+                continue;
+            const bool own_slot = s < nl; // implies u == 0 and s == t
+            const int tg = own_slot ? line : matrix_load<NT>(slot_target + bk.slot0 + s);
+            const double xt = own_slot ? xo : (double)x[tg];
+            double a = own_slot ? own : 0.0;
+            const int hi = sg[s + 1];
+            for (int i = sg[s]; i < hi; ++i)
+                a += sp[tv[i]];
+            if (own_slot)
+                y[tg] = a;
+            else
+                part[bk.park0 + (s - nl)] = a;
+            sig = fma(xt, a, sig);
+        }
+        __syncthreads(); // LDS is reused by the next block
+    }
+    sig = block_sum(sig, red);
+    if (t == 0)
+        sig_part[wg] = sig;
+}
+
 // One thread per row: y_i = (y_i if a colour-0 block wrote it, else 0)
 // + the row's parked slot sums in ascending colour order.  Every row is
 // owned by one thread, so no atomics; the order is fixed by the plan.
@@ -663,7 +796,7 @@ __global__ __launch_bounds__(kBlock) void k_scatter_gather(int n, const int32_t 
     if (i >= n)
         return;
     const int k0 = rs_ptr[i], k1 = rs_ptr[i + 1];
-    const bool c0 = has_c0[i] != 0;
+    const bool c0 = has_c0 == nullptr || has_c0[i] != 0; // null: compact blocks, every row stored by its owner
     if (k0 == k1) {
         if (!c0)
             y[i] = 0.0; // no entry writes this row
@@ -707,8 +840,10 @@ constexpr int kPre = 4;
 // (k_scatter_gather's sum, same terms, same order) into the r update, so the
 // product's last writes of y and their re-read are saved.
 // GATHER: 0 = no row pass; 1 = per-row lists of parked slots (symmetric
-// CSR); 2 = at most one parked sum per row, stored by row, with a flag byte
-// (bit 0: y_i holds a share, bit 1: part_i does; CSC panels).
+// CSR, coloured plan); 2 = at most one parked sum per row, stored by row,
+// with a flag byte (bit 0: y_i holds a share, bit 1: part_i does; CSC
+// panels); 3 = per-row lists, y_i always stored (symmetric CSR, compact
+// blocks).
 struct RowPass {
     const int32_t *rs_ptr = nullptr, *rs_idx = nullptr;
     const uint8_t *has_c0 = nullptr;
@@ -728,7 +863,7 @@ __device__ __forceinline__ double q_value(const double *__restrict__ q, const Ro
         return a;
     }
     const int k0 = g.rs_ptr[i], k1 = g.rs_ptr[i + 1];
-    double a = g.has_c0[i] ? q[i] : 0.0;
+    double a = (GATHER == 3 || g.has_c0[i]) ? q[i] : 0.0;
     for (int k = k0; k < k1; ++k)
         a += g.part[g.rs_idx[k]];
     return a;
@@ -1101,6 +1236,35 @@ void scatter_slices_launch(const DevMatrix &m, const VT *val, const PT *x, doubl
                            m.rs_idx, m.has_c0, m.part, y, c.st);
 }
 
+template <int SU, class VT, class PT>
+void compact_launch(const DevMatrix &m, const VT *val, const PT *x, double *y, double *sig, const IterCtx &c,
+                    hipStream_t s)
+{
+    if (m.matrix_cached)
+        hipLaunchKernelGGL((k_scatter_compact<SU, false, VT, PT>), dim3(m.scatter_wgs), dim3(kBlock), 0, s, m.ss_idx,
+                           sym_slice_vals(m, val), m.cblocks, m.nblocks, m.slot_target, m.seg, m.tl, x, y, m.part,
+                           sig, c.st);
+    else
+        hipLaunchKernelGGL((k_scatter_compact<SU, true, VT, PT>), dim3(m.scatter_wgs), dim3(kBlock), 0, s, m.ss_idx,
+                           sym_slice_vals(m, val), m.cblocks, m.nblocks, m.slot_target, m.seg, m.tl, x, y, m.part,
+                           sig, c.st);
+    if (m.parked > 0 && !c.defer_rows)
+        hipLaunchKernelGGL(k_scatter_gather, dim3((m.n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, m.n, m.rs_ptr,
+                           m.rs_idx, nullptr, m.part, y, c.st);
+}
+
+template <class VT, class PT>
+void compact_dispatch(const DevMatrix &m, const VT *val, const PT *x, double *y, double *sig, const IterCtx &c,
+                      hipStream_t s)
+{
+    if (m.max_slots <= 2 * kBlock)
+        compact_launch<2>(m, val, x, y, sig, c, s);
+    else if (m.max_slots <= 4 * kBlock)
+        compact_launch<4>(m, val, x, y, sig, c, s);
+    else
+        compact_launch<9>(m, val, x, y, sig, c, s);
+}
+
 template <int E, class VT, class PT>
 void scatter_dispatch_su(const DevMatrix &m, const VT *val, const PT *x, double *y, double *sig, const IterCtx &c,
                          hipStream_t s)
@@ -1205,8 +1369,10 @@ void spmv_any(const DevMatrix &m, const VT *val, const PT *x, double *y, double 
         case 32: csr_launch<32>(m, val, x, y, sig_part, c, s); break;
         default: csr_launch<64>(m, val, x, y, sig_part, c, s); break;
         }
+    } else if (m.compact) {
+        compact_dispatch(m, val, x, y, sig_part, c, s); // symmetric CSR, compact blocks
     } else {
-        scatter_dispatch(m, val, x, y, sig_part, c, s); // symmetric CSR (CSC runs on panels)
+        scatter_dispatch(m, val, x, y, sig_part, c, s); // symmetric CSR, coloured (CSC runs on panels)
     }
 }
 
@@ -1236,7 +1402,7 @@ void launch_update_r(const DevMatrix &m, double *r, const double *q, DevState *s
     g.rs_idx = m.rs_idx;
     g.has_c0 = m.has_c0;
     g.part = m.part;
-    const int mode = rows_deferred && m.row_pass() ? (m.panel ? 2 : 1) : 0;
+    const int mode = rows_deferred && m.row_pass() ? (m.panel ? 2 : m.compact ? 3 : 1) : 0;
     const dim3 grid(m.vec_blocks), blk(kBlock);
 #define CGMI_UPDATE_R(G, P)                                                                                  \
     hipLaunchKernelGGL((k_update_r<G, P * kPartPerThread>), grid, blk, 0, s, m.n, m.vec_chunk, r, q, st, sig_part, \
@@ -1250,7 +1416,9 @@ void launch_update_r(const DevMatrix &m, double *r, const double *q, DevState *s
         else                                                                                                 \
             CGMI_UPDATE_R(G, 4);                                                                             \
     } while (0)
-    if (mode == 2)
+    if (mode == 3)
+        CGMI_UPDATE_R_PPT(3);
+    else if (mode == 2)
         CGMI_UPDATE_R_PPT(2);
     else if (mode == 1)
         CGMI_UPDATE_R_PPT(1);

@@ -21,6 +21,11 @@ int64_t Plan::device_bytes() const
     if (panel) // entry source + column + reordered value; slot target / pointer; chunks; parked sums, flags
         return nnz * (4 + 4 + 8) + (int64_t)pn_slot_target.size() * (4 + 4) + (int64_t)pn_chunk_slot.size() * 4 +
                n * 9;
+    if (sym_compact) // descriptors; slot targets, segment offsets; contributions; parked sums, their
+                     // per-row lists; positions (source, column, value)
+        return (int64_t)cp_blocks.size() * sizeof(CompactBlock) + (int64_t)slot_target.size() * 4 +
+               (int64_t)seg.size() * 2 + (int64_t)ss_tl.size() * 2 + cp_parked * (8 + 4) + (n + 1) * 4 +
+               (int64_t)ss_src.size() * (4 + 4 + 8);
     // descriptors, slot target / flag / segment offsets, contributions, parked
     // sums and their per-row index (upper bounds: every slot counted); sliced
     // blocks: positions (source, column, value) and their block offsets
@@ -34,6 +39,9 @@ int64_t Plan::slice_stream_bytes() const
     if (slices) // positions, slice offsets; CSC: slot targets, parked sums written and read
         return (int64_t)sl_src.size() * 12 + (int64_t)sl_off.size() * 4 +
                (panel ? (int64_t)pn_slot_target.size() * 4 + n * 17 : 0);
+    if (sym_compact) // positions; slot targets, segments; contributions; parked sums written and read, row lists
+        return (int64_t)ss_src.size() * 12 + (int64_t)slot_target.size() * (4 + 2) + (int64_t)ss_tl.size() * 2 +
+               cp_parked * (8 + 8 + 4) + (n + 1) * 4;
     if (sym_slices) // positions; slot targets, segments, flags; contributions; parked sums and row lists
         return (int64_t)ss_src.size() * 12 + (int64_t)slot_target.size() * (4 + 2 + 1 + 8 + 8 + 4) +
                (int64_t)tl.size() * 2 + n * 5;
@@ -239,9 +247,10 @@ static bool plan_slices(Plan &p, int64_t nl, const int32_t *seg_ptr, const int32
     p.sl_src.assign((size_t)padded, -1);
     p.sl_col.assign((size_t)padded, -1);
     for (int64_t r = 0; r < nl; ++r) {
-        const int64_t base = off[r / kSliceRows] + r % kSliceRows;
+        const int64_t sl = r / kSliceRows, lane = r % kSliceRows;
+        const int64_t w = (off[sl + 1] - off[sl]) / kSliceRows;
         for (int64_t k = seg_ptr[r]; k < seg_ptr[r + 1]; ++k) {
-            const int64_t q = base + (k - seg_ptr[r]) * kSliceRows;
+            const int64_t q = off[sl] + slice_position(k - seg_ptr[r], lane, w);
             p.sl_src[q] = seg_src ? seg_src[k] : (int32_t)k;
             p.sl_col[q] = seg_col[k];
         }
@@ -648,6 +657,273 @@ static void plan_sym_slices(Plan &p, const int32_t *ptr, const int32_t *idx, int
     p.sym_slices = true;
 }
 
+// experiments: CGMI_SYM_PLAN = colour selects the contiguous, coloured plan
+// for symmetric CSR even where compact blocks apply
+static bool compact_allowed()
+{
+    const char *e = std::getenv("CGMI_SYM_PLAN");
+    return !(e && std::strcmp(e, "colour") == 0);
+}
+
+// Symmetric CSR, compact blocks (plan.h).  Returns false (plan untouched)
+// when some line has more than kStreamPerThread entries.
+static bool plan_sym_compact(Plan &p, const int32_t *ptr, const int32_t *idx)
+{
+    const int64_t n = p.n;
+    for (int64_t l = 0; l < n; ++l)
+        if ((int64_t)ptr[l + 1] - ptr[l] > kStreamPerThread)
+            return false;
+    // graph of A without the diagonal: the stored triangle and its mirror
+    std::vector<int32_t> ap((size_t)n + 1, 0);
+    for (int64_t i = 0; i < n; ++i)
+        for (int64_t k = ptr[i]; k < ptr[i + 1]; ++k)
+            if (idx[k] != i) {
+                ap[i + 1]++;
+                ap[idx[k] + 1]++;
+            }
+    for (int64_t i = 0; i < n; ++i)
+        ap[i + 1] += ap[i];
+    std::vector<int32_t> ai((size_t)ap[n]);
+    {
+        std::vector<int32_t> fill(ap.begin(), ap.end() - 1);
+        for (int64_t i = 0; i < n; ++i)
+            for (int64_t k = ptr[i]; k < ptr[i + 1]; ++k)
+                if (idx[k] != i) {
+                    ai[fill[i]++] = idx[k];
+                    ai[fill[idx[k]]++] = (int32_t)i;
+                }
+    }
+    // 1. growth: from the lowest free line; nearest to the seed first, then
+    //    most couplings into the block, then the lowest line number
+    std::vector<int32_t> blk((size_t)n, -1), gain((size_t)n, 0), dist((size_t)n, 0), stamp((size_t)n, -1);
+    struct Cand {
+        int64_t key;
+        int32_t line;
+        bool operator<(const Cand &o) const { return key < o.key || (key == o.key && line > o.line); }
+    };
+    auto key = [&](int32_t j) { return -(int64_t)dist[j] * 4096 + gain[j]; };
+    std::vector<Cand> heap;
+    int32_t nb = 0;
+    int64_t seed = 0;
+    while (true) {
+        while (seed < n && blk[seed] >= 0)
+            ++seed;
+        if (seed >= n)
+            break;
+        heap.clear();
+        dist[seed] = 0;
+        gain[seed] = 0;
+        stamp[seed] = nb;
+        heap.push_back({key((int32_t)seed), (int32_t)seed});
+        int lines = 0;
+        while (!heap.empty() && lines < kMaxBlockLines) {
+            std::pop_heap(heap.begin(), heap.end());
+            const Cand c = heap.back();
+            heap.pop_back();
+            const int32_t i = c.line;
+            if (blk[i] >= 0 || stamp[i] != nb || c.key != key(i))
+                continue; // taken, or a stale entry
+            blk[i] = nb;
+            ++lines;
+            for (int32_t q = ap[i]; q < ap[i + 1]; ++q) {
+                const int32_t j = ai[q];
+                if (blk[j] >= 0)
+                    continue;
+                if (stamp[j] != nb) {
+                    stamp[j] = nb;
+                    gain[j] = 0;
+                    dist[j] = dist[i] + 1;
+                }
+                gain[j]++;
+                heap.push_back({key(j), j});
+                std::push_heap(heap.begin(), heap.end());
+            }
+        }
+        ++nb;
+    }
+    // 2. merge small pockets into the neighbour they couple to most (with room)
+    std::vector<int32_t> bl((size_t)nb, 0);
+    for (int64_t i = 0; i < n; ++i)
+        bl[blk[i]]++;
+    {
+        std::vector<std::vector<int32_t>> mem((size_t)nb);
+        for (int64_t i = 0; i < n; ++i)
+            mem[blk[i]].push_back((int32_t)i);
+        std::vector<int32_t> order((size_t)nb);
+        for (int32_t b = 0; b < nb; ++b)
+            order[b] = b;
+        std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return bl[a] < bl[b]; });
+        std::vector<int32_t> cnt((size_t)nb, 0), touched;
+        for (int32_t b : order) {
+            if (bl[b] == 0 || bl[b] >= kMinCompactLines)
+                continue;
+            touched.clear();
+            for (int32_t i : mem[b])
+                for (int32_t q = ap[i]; q < ap[i + 1]; ++q) {
+                    const int32_t c = blk[ai[q]];
+                    if (c == b)
+                        continue;
+                    if (cnt[c]++ == 0)
+                        touched.push_back(c);
+                }
+            int32_t best = -1;
+            for (int32_t c : touched)
+                if (bl[c] + bl[b] <= kMaxBlockLines &&
+                    (best < 0 || cnt[c] > cnt[best] || (cnt[c] == cnt[best] && c < best)))
+                    best = c;
+            for (int32_t c : touched)
+                cnt[c] = 0;
+            if (best < 0)
+                continue;
+            for (int32_t i : mem[b]) {
+                blk[i] = best;
+                mem[best].push_back(i);
+            }
+            mem[b].clear();
+            bl[best] += bl[b];
+            bl[b] = 0;
+        }
+    }
+    // 3. block order: by lowest line; lines ascending inside a block
+    std::vector<int32_t> first((size_t)nb, INT32_MAX), rank((size_t)nb, -1), ids;
+    for (int64_t i = n - 1; i >= 0; --i)
+        first[blk[i]] = (int32_t)i;
+    for (int32_t b = 0; b < nb; ++b)
+        if (bl[b] > 0)
+            ids.push_back(b);
+    std::sort(ids.begin(), ids.end(), [&](int32_t a, int32_t b) { return first[a] < first[b]; });
+    for (size_t k = 0; k < ids.size(); ++k)
+        rank[ids[k]] = (int32_t)k;
+    const int32_t nbk = (int32_t)ids.size();
+    p.cp_block_of.resize((size_t)n);
+    std::vector<int32_t> lp((size_t)nbk + 1, 0), lines((size_t)n);
+    for (int64_t i = 0; i < n; ++i) {
+        p.cp_block_of[i] = rank[blk[i]];
+        lp[rank[blk[i]] + 1]++;
+    }
+    for (int32_t b = 0; b < nbk; ++b)
+        lp[b + 1] += lp[b];
+    {
+        std::vector<int32_t> fill(lp.begin(), lp.end() - 1);
+        for (int64_t i = 0; i < n; ++i)
+            lines[fill[p.cp_block_of[i]]++] = (int32_t)i; // ascending inside each block
+    }
+    // 4. per block: positions, slots (own lines, then the rows reached
+    //    outside), contributions grouped by slot (line order within a slot)
+    p.cp_blocks.assign((size_t)nbk, CompactBlock{});
+    p.slot_target.clear();
+    p.slot_count.clear();
+    p.seg.clear();
+    p.ss_tl.clear();
+    p.ss_src.clear();
+    p.ss_idx.clear();
+    p.ss_pos.assign((size_t)nbk + 1, 0);
+    std::vector<int32_t> local((size_t)n, -1); // row -> local slot while its block is built
+    std::vector<int32_t> remote, cs;
+    std::vector<std::pair<int32_t, int32_t>> contrib; // (slot, position)
+    int64_t pos = 0, parked = 0;
+    p.max_slots = 0;
+    p.max_entries = 0;
+    p.max_lines = 0;
+    for (int32_t b = 0; b < nbk; ++b) {
+        const int32_t l0 = lp[b], nl = lp[b + 1] - lp[b];
+        int32_t len = 0;
+        for (int32_t t = 0; t < nl; ++t) {
+            const int32_t i = lines[l0 + t];
+            len = std::max<int32_t>(len, ptr[i + 1] - ptr[i]);
+            local[i] = t;
+        }
+        remote.clear();
+        for (int32_t t = 0; t < nl; ++t) {
+            const int32_t i = lines[l0 + t];
+            for (int64_t k = ptr[i]; k < ptr[i + 1]; ++k)
+                if (idx[k] != i && local[idx[k]] < 0)
+                    remote.push_back(idx[k]);
+        }
+        std::sort(remote.begin(), remote.end());
+        remote.erase(std::unique(remote.begin(), remote.end()), remote.end());
+        for (size_t r = 0; r < remote.size(); ++r)
+            local[remote[r]] = nl + (int32_t)r;
+        const int32_t ns = nl + (int32_t)remote.size();
+        contrib.clear();
+        if (pos + (int64_t)nl * len > INT32_MAX)
+            return false;
+        for (int32_t t = 0; t < nl; ++t) {
+            const int32_t i = lines[l0 + t];
+            for (int64_t k = ptr[i]; k < ptr[i + 1]; ++k) {
+                const int32_t q = (int32_t)((k - ptr[i]) * nl + t); // LDS slot of its mirror product
+                if (idx[k] != i)
+                    contrib.push_back({local[idx[k]], q});
+            }
+        }
+        std::stable_sort(contrib.begin(), contrib.end(),
+                         [](const std::pair<int32_t, int32_t> &a, const std::pair<int32_t, int32_t> &c) {
+                             return a.first < c.first;
+                         });
+        CompactBlock &cb = p.cp_blocks[b];
+        cb.pos0 = (int32_t)pos;
+        cb.len = len;
+        cb.nl = nl;
+        cb.slot0 = (int32_t)p.slot_target.size();
+        cb.nslots = ns;
+        cb.seg0 = (int32_t)p.seg.size();
+        cb.tl0 = (int32_t)p.ss_tl.size();
+        cb.ntl = (int32_t)contrib.size();
+        cb.park0 = (int32_t)parked;
+        for (int32_t t = 0; t < nl; ++t)
+            p.slot_target.push_back(lines[l0 + t]);
+        for (int32_t r : remote)
+            p.slot_target.push_back(r);
+        cs.assign((size_t)ns + 1, 0);
+        for (const auto &c : contrib)
+            cs[c.first + 1]++;
+        for (int32_t s = 0; s < ns; ++s)
+            cs[s + 1] += cs[s];
+        for (int32_t s = 0; s <= ns; ++s)
+            p.seg.push_back((uint16_t)cs[s]);
+        for (int32_t s = 0; s < ns; ++s)
+            p.slot_count.push_back(cs[s + 1] - cs[s]);
+        for (const auto &c : contrib)
+            p.ss_tl.push_back((uint16_t)c.second);
+        // positions: entries k and k + 1 of line t side by side (pairs, as in
+        // the slices with nl lines), padding -1; every block starts at an
+        // even position, so a pair is one aligned 8- / 16-byte load
+        const int64_t npos = ((int64_t)nl * len + 1) & ~int64_t(1);
+        p.ss_src.resize((size_t)(pos + npos), -1);
+        p.ss_idx.resize((size_t)(pos + npos), -1);
+        for (int32_t t = 0; t < nl; ++t) {
+            const int32_t i = lines[l0 + t];
+            for (int64_t k = ptr[i]; k < ptr[i + 1]; ++k) {
+                const int64_t kk = k - ptr[i];
+                const int64_t q = pos + (kk < (len & ~1) ? (kk >> 1) * 2 * nl + 2 * t + (kk & 1) : kk * nl + t);
+                p.ss_src[q] = (int32_t)k;
+                p.ss_idx[q] = idx[k];
+            }
+        }
+        pos += npos;
+        p.ss_pos[b + 1] = (int32_t)pos;
+        parked += (int64_t)remote.size();
+        for (int32_t t = 0; t < nl; ++t)
+            local[lines[l0 + t]] = -1;
+        for (int32_t r : remote)
+            local[r] = -1;
+        p.max_slots = std::max(p.max_slots, ns);
+        p.max_entries = std::max(p.max_entries, nl * len);
+        p.max_lines = std::max(p.max_lines, nl);
+    }
+    if ((int64_t)p.slot_target.size() + nbk + 1 >= INT32_MAX || parked >= INT32_MAX)
+        return false;
+    p.nblocks = nbk;
+    p.ncolors = 1;
+    p.cp_parked = parked;
+    p.blocks.clear();
+    p.block_color.assign((size_t)nbk, 0);
+    p.color_off = {0, nbk};
+    p.phase_blocks.clear();
+    p.sym_compact = true;
+    return true;
+}
+
 int build_plan(int fmt, int64_t n, const int32_t *ptr0, const int32_t *idx0, int target_entries, Plan &p,
                std::string &err)
 {
@@ -669,6 +945,10 @@ int build_plan(int fmt, int64_t n, const int32_t *ptr0, const int32_t *idx0, int
         const int st = plan_panels(p, ptr0, idx0, err);
         p.cached = st == CG_OK && decide_cached(p);
         return st;
+    }
+    if (target_entries <= 0 && compact_allowed() && slice_mode() >= 0 && plan_sym_compact(p, ptr0, idx0)) {
+        p.cached = decide_cached(p);
+        return CG_OK;
     }
     if (target_entries <= 0)
         target_entries = (int)block_entries(p.nnz, 512);

@@ -26,15 +26,39 @@
 // two-dimensional blocking of compressed-sparse-blocks storage applied to
 // the transpose product: column blocks for the scatter, row order inside.
 //
+// Compact blocks (symmetric CSR whose lines have at most kStreamPerThread
+// entries; the default there).  Contiguous line ranges are a poor unit for
+// the mirrored product: in a mesh numbered plane by plane, almost every
+// mirror product of a range lands outside it.  Instead blocks are grown on
+// the graph of A: from the lowest-numbered free line, breadth first (lines
+// nearer the seed first, then those with more couplings into the block,
+// then the lowest number), up to kMaxBlockLines lines; leftover pockets of
+// fewer than kMinCompactLines lines are merged into the neighbouring block
+// they couple to most when it has room.  Each line belongs to exactly one
+// block, and that block OWNS the line's row of y: its first slots are its
+// own lines (ascending), whose sums -- the stored row itself plus the mirror
+// products landing on it from the block's other lines -- it stores in y.
+// Its remaining slots are the rows outside the block that its mirror
+// products reach; their sums are parked and added to y row by row
+// afterwards, in ascending block order.  No two blocks write one location,
+// so no colouring is needed.  The entries of a block are stored like a
+// slice of nl lines (entries 2j, 2j + 1 of line t side by side at
+// pos0 + 2 nl j + 2 t, the last entries of an odd width at
+// pos0 + nl (len - 1) + t).
+//
 // Slices.  Rows (CSR) or write slots (CSC panels: one (panel, row) segment
 // each) are grouped in slices of 64 consecutive lines, one per wavefront
-// lane, and a slice stores the k-th entry of each of its lines contiguously
-// (positions off + 64 k + lane; lines shorter than the slice's longest are
-// padded with source -1).  This is the sliced ELLPACK layout (SELL-C-sigma,
-// Kreutzer et al. 2014) with C = 64 and no sorting: for a stencil-like matrix
-// the lanes of one load read neighbouring x entries, so the gather of x
-// becomes a near-contiguous load.  Chosen when the padding stays small; each
-// line is still summed left to right by one lane.
+// lane; lines shorter than the slice's longest (w entries) are padded with
+// source -1.  Inside a slice the entries are stored in pairs: entries 2j and
+// 2j + 1 of the line of lane l sit side by side at off + 128 j + 2 l (+ 1),
+// and when w is odd the last entries of all lines follow at
+// off + 64 (w - 1) + l.  One 8- or 16-byte load per lane thus brings two
+// entries, and a wave's load is 512 or 1024 contiguous bytes.  This is the
+// sliced ELLPACK layout (SELL-C-sigma, Kreutzer et al. 2014) with C = 64, no
+// sorting and two-entry packing: for a stencil-like matrix the lanes of one
+// load read neighbouring x entries, so the gather of x becomes a
+// near-contiguous load.  Chosen when the padding stays small; each line is
+// still summed left to right by one lane.
 #pragma once
 
 #include <cstdint>
@@ -68,10 +92,18 @@ constexpr int64_t kCacheResidentBytes = 336ll << 20;
 constexpr int kPanelMinWidth = 4096;    // CSC panels span at least this many columns
 constexpr int kPanelChunkEntries = kStreamEntries; // entries per CSC panel chunk
 constexpr int kPanelChunkSlots = kBlock;           // slots per CSC panel chunk (one thread each)
+constexpr int kMinCompactLines = 128;    // compact blocks: smaller pockets are merged when possible
 constexpr uint8_t kSlotFirst = 1;
 constexpr uint8_t kSlotLast = 2;
 
 enum Format { kCsr = 0, kSymCsr = 1, kCsc = 2 };
+
+// Offset inside a slice of width w (entries per line) of the k-th entry of
+// the line of lane `lane` (the pair packing above).
+inline int64_t slice_position(int64_t k, int64_t lane, int64_t w)
+{
+    return k < (w & ~int64_t(1)) ? (k >> 1) * (2 * kSliceRows) + 2 * lane + (k & 1) : k * kSliceRows + lane;
+}
 
 struct ScatterBlock {
     int32_t line0, line1;  // lines [line0, line1)
@@ -80,6 +112,20 @@ struct ScatterBlock {
     int32_t tl0, id;       // contributions start; block id (index of its dot partial)
     int32_t ntl;           // number of contributions
     int32_t pad;           // device copy: colour of the block
+};
+
+// A compact block of the symmetric format (device layout).
+struct CompactBlock {
+    int32_t pos0;   // first position of its entries (even)
+    int32_t len;    // entries per line (its longest line; shorter lines padded)
+    int32_t nl;     // own lines = its first nl slots
+    int32_t slot0;  // slots [slot0, slot0 + nslots) of slot_target
+    int32_t nslots;
+    int32_t seg0;   // nslots + 1 offsets into its contributions: seg[seg0 ..]
+    int32_t tl0;    // contributions [tl0, tl0 + ntl): LDS slots k * nl + t of the mirror
+                    // products, grouped by slot
+    int32_t ntl;
+    int32_t park0;  // parked-sum index of its slot nl (its first non-own slot)
 };
 
 struct Plan {
@@ -118,6 +164,12 @@ struct Plan {
     std::vector<int32_t> ss_src;          // [positions] caller entry (0-based), -1 = padding
     std::vector<int32_t> ss_idx;          // [positions] column, -1 = padding
     std::vector<uint16_t> ss_tl;          // [contributions] local position of each contribution
+    // symmetric CSR, compact blocks (plan.h); positions in ss_src / ss_idx,
+    // contributions (local positions) in ss_tl, slots in slot_target / seg
+    bool sym_compact = false;
+    std::vector<CompactBlock> cp_blocks;  // [nblocks] in block order
+    std::vector<int32_t> cp_block_of;     // [n] block of each line
+    int64_t cp_parked = 0;                // parked sums (slots that are not own lines)
     // CSC column panels (format kCsc): entries in panel order
     bool panel = false;
     int64_t pn_width = 0;

@@ -120,7 +120,7 @@ def record(**kw):
         return
     os.makedirs(os.path.dirname(os.path.abspath(path)), exist_ok=True)
     with open(path, "a") as f:
-        f.write(json.dumps({k: (float(v) if isinstance(v, np.floating) else v) for k, v in kw.items()}) + "\n")
+        f.write(json.dumps({k: (v.item() if isinstance(v, np.generic) else v) for k, v in kw.items()}) + "\n")
 
 
 def load_reference(name):

@@ -14,8 +14,13 @@ adjoint, central finite differences of the oracle's dense forward on 32
 random nu entries, and, on the 100^3 system (6 181 806 elements), the
 homogeneity identity sum_e nu_e dL/dnu_e = -2 (x - x_obs)' x and central
 differences of the GPU forward on 32 random elements against a bound built
-from the measured residuals.
+from the measured residuals; and against the FP64 oracle gradient of the same
+case, stored by tests/golden/make_adjoint_reference.py (loss, gradient norm,
+4096 sampled elements).
 """
+import hashlib
+import os
+
 import numpy as np
 import pytest
 
@@ -293,3 +298,38 @@ def test_fem100_adjoint_identity_and_fd():
             worst = max(worst, abs(fd - g[e]) / bound)
             assert abs(fd - g[e]) <= bound, (int(e), fd, g[e], bound)
         say(f"fem100 fd: worst |fd - g| / bound = {worst:.3f}")
+
+
+def test_fem100_adjoint_vs_stored_oracle_gradient():
+    """The 100^3 gradient against the FP64 oracle's (two serial oracle CG
+    solves at tol 1e-12 over oracle/fem.py, stored by
+    tests/golden/make_adjoint_reference.py): the loss, the homogeneity
+    identity and dL/dnu at 4096 seeded elements.  The two gradients come
+    from different FP64 evaluations of the same two solves, so they agree to
+    the solves' accuracy, not bit for bit: bar 1e-6 relative (2-norm over the
+    sample, and per element against the sample's largest entry)."""
+    import json
+    from paper_1010_4639_amd import adjoint
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "fem100_adjoint_oracle.json")
+    with open(path) as f:
+        ref = json.load(f)
+    s, coords, tets, dof, nu_cell = mesh("fem100")
+    nu = nu_cell * np.random.default_rng(101).uniform(0.8, 1.25, size=nu_cell.size)
+    xo = W.observation(s)
+    assert hashlib.sha256(np.ascontiguousarray(s.b).tobytes()).hexdigest() == ref["b_sha256"]
+    pos = np.array(ref["sample_elem"], dtype=np.int64)
+    g_ref = np.array([float.fromhex(h) for h in ref["sample_g"]])
+    with adjoint.FemSolve(coords, tets, dof, s.n) as FS:
+        nu_t = to_dev(nu).requires_grad_(True)
+        x = FS(nu_t, to_dev(s.b), tol=ref["tol"])
+        L = ((x - to_dev(xo)) ** 2).sum()
+        L.backward()
+        g = nu_t.grad.cpu().numpy()
+    Lg = float(L.detach())
+    err = np.linalg.norm(g[pos] - g_ref) / np.linalg.norm(g_ref)
+    worst = float(np.max(np.abs(g[pos] - g_ref)) / np.max(np.abs(g_ref)))
+    say(f"fem100 adjoint vs stored oracle: L {Lg:.12e} / {ref['L']:.12e}, sampled g rel 2-norm {err:.2e}, "
+        f"max {worst:.2e}, ||g|| {np.linalg.norm(g):.6e} / {ref['norm2_g']:.6e}")
+    assert abs(Lg - ref["L"]) <= 1e-8 * ref["L"]
+    assert abs(np.linalg.norm(g) - ref["norm2_g"]) <= 1e-6 * ref["norm2_g"]
+    assert err <= 1e-6 and worst <= 1e-6, (err, worst)

@@ -4,8 +4,9 @@ refinement) through the C-ABI vs the FP64 oracle.
 The refinement stops on the TRUE residual ||b - A x|| <= tol ||b|| computed
 with the FP64 product, so the bar is the FP64 one: true residual (oracle
 product) <= 2 tol, energy-norm difference to the oracle's FP64 CG solution
-<= 1e-8, 2-norm difference <= max(1e-8, 4 x the oracle's own
-reduction-order spread) (tests/parity.py); measured values are recorded.
+<= 1e-8, and a 2-norm error against the exact solution no larger than the
+FP64 oracle's own (within 4x); the 2-norm difference to the oracle's
+solution is recorded per result.
 """
 import numpy as np
 import pytest
@@ -30,7 +31,14 @@ def run_mixed(fmt, arrs, b, tol=1e-10, inner_tol=1e-4, label=""):
     return x.cpu().numpy(), info
 
 
-def check_vs_fp64(fmt, arrs, b, xg, info, tol=1e-10, label=""):
+def check_vs_fp64(fmt, arrs, b, xg, info, x_true, tol=1e-10, label=""):
+    """The refinement is another algorithm than the oracle's CG: it stops on
+    the true residual, after whole inner solves, usually well below tol, so
+    its x does not sit where the oracle's FP64 CG stops (~kappa tol away from
+    the solution).  Asserted: the energy-norm difference to the oracle's
+    solution (<= 1e-8, the FP64 bar), and the 2-norm error against the exact
+    solution x_true no larger than the FP64 oracle's own (within 4x, floor
+    1e-8).  The 2-norm difference to the oracle's solution is recorded."""
     assert info["status"] == cgmi.CG_OK, info
     rt = true_relres(fmt, *arrs, b, xg)
     assert rt <= 2 * tol and abs(rt - info["relres_true"]) <= 1e-2 * rt
@@ -39,13 +47,15 @@ def check_vs_fp64(fmt, arrs, b, xg, info, tol=1e-10, label=""):
     d = xg - xo
     err_a = a_norm(fmt, arrs, d) / a_norm(fmt, arrs, xo)
     err = np.linalg.norm(d) / np.linalg.norm(xo)
-    spread2, _, _ = parity.oracle_spread(fmt, arrs, b, xo, tol)
-    bar = parity.x_bar(spread2)
-    say(f"   vs FP64 oracle ({oinfo['iters']} it): 2-norm {err:.3e} (bar {bar:.3e}, oracle spread {spread2:.3e})"
-        f"  A-norm {err_a:.3e}")
-    parity.record(test="mixed " + label, fmt=int(fmt), n=len(arrs[0]) - 1, err2=err, errA=err_a, bar2=bar,
-                  spread2=spread2, inner_iters=info["iters"], outer=info["outer"], relres_true=rt)
-    assert err_a <= parity.X_TOL and err <= bar
+    nt = np.linalg.norm(x_true)
+    e_orc, e_mx = np.linalg.norm(xo - x_true) / nt, np.linalg.norm(xg - x_true) / nt
+    say(f"   vs FP64 oracle ({oinfo['iters']} it): 2-norm {err:.3e}  A-norm {err_a:.3e}; error vs x_true: "
+        f"mixed {e_mx:.3e}, oracle {e_orc:.3e}")
+    parity.record(test="mixed " + label, fmt=int(fmt), n=len(arrs[0]) - 1, err2=err, errA=err_a,
+                  err2_vs_true=e_mx, oracle_err2_vs_true=e_orc, inner_iters=info["iters"], outer=info["outer"],
+                  relres_true=rt)
+    assert err_a <= parity.X_TOL, err_a
+    assert e_mx <= max(parity.X_TOL, 4 * e_orc), (e_mx, e_orc)
 
 
 @pytest.mark.parametrize("fmt", [CSR, SYM, CSC])
@@ -53,7 +63,7 @@ def test_mixed_paper_sized(fmt):
     s = fem_cached("fem32x32x30")
     arrs = formats_of(s.rowptr, s.col, s.val)[fmt]
     xg, info = run_mixed(fmt, arrs, s.b, label="fem32x32x30")
-    check_vs_fp64(fmt, arrs, s.b, xg, info, label="fem32x32x30 inner 1e-4")
+    check_vs_fp64(fmt, arrs, s.b, xg, info, s.x_true, label="fem32x32x30 inner 1e-4")
 
 
 @pytest.mark.parametrize("fmt", [CSR, SYM, CSC])
@@ -64,7 +74,7 @@ def test_mixed_row_blocks(monkeypatch, fmt):
     s = fem_cached("fem32x32x30")
     arrs = formats_of(s.rowptr, s.col, s.val)[fmt]
     xg, info = run_mixed(fmt, arrs, s.b, label="fem32x32x30 row blocks")
-    check_vs_fp64(fmt, arrs, s.b, xg, info, label="fem32x32x30 row blocks")
+    check_vs_fp64(fmt, arrs, s.b, xg, info, s.x_true, label="fem32x32x30 row blocks")
 
 
 @pytest.mark.parametrize("restart", ["0", "1"])
@@ -78,7 +88,7 @@ def test_mixed_loose_inner_tolerance(monkeypatch, fmt, restart):
     arrs = formats_of(s.rowptr, s.col, s.val)[fmt]
     xg, info = run_mixed(fmt, arrs, s.b, inner_tol=1e-2, label=f"fem32x32x30 inner 1e-2 restart={restart}")
     assert info["outer"] >= 3
-    check_vs_fp64(fmt, arrs, s.b, xg, info, label=f"fem32x32x30 inner 1e-2 restart={restart}")
+    check_vs_fp64(fmt, arrs, s.b, xg, info, s.x_true, label=f"fem32x32x30 inner 1e-2 restart={restart}")
 
 
 @pytest.mark.parametrize("fmt", [CSR, SYM])
@@ -87,7 +97,7 @@ def test_mixed_high_contrast(fmt):
     s = W.fem_p1_system(20, 20, 18, nu_iron=1e-4, seed=3)
     arrs = formats_of(s.rowptr, s.col, s.val)[fmt]
     xg, info = run_mixed(fmt, arrs, s.b, label="fem20x20x18 nu=1e-4")
-    check_vs_fp64(fmt, arrs, s.b, xg, info, label="fem20x20x18 nu=1e-4")
+    check_vs_fp64(fmt, arrs, s.b, xg, info, s.x_true, label="fem20x20x18 nu=1e-4")
 
 
 def test_mixed_statuses():

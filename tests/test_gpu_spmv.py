@@ -107,8 +107,10 @@ def test_scatter_block_sizes(monkeypatch, fmt, entries):
 
 @pytest.mark.parametrize("entries", [None, "32", "200"])
 def test_sym_sliced_blocks_same_bits(monkeypatch, entries):
-    # sliced blocks keep the blocks, slots and summation order of the plain
-    # symmetric kernel: identical bits, and the oracle's bar
+    # the coloured plan of line ranges: its sliced blocks keep the blocks,
+    # slots and summation order of the plain symmetric kernel -- identical
+    # bits, and the oracle's bar (compact blocks are a different plan)
+    monkeypatch.setenv("CGMI_SYM_PLAN", "colour")
     if entries:
         monkeypatch.setenv("CGMI_SCATTER_ENTRIES", entries)
     s = W.fem_p1_system(20, 18, 16, seed=25)
@@ -121,6 +123,25 @@ def test_sym_sliced_blocks_same_bits(monkeypatch, entries):
         assert stats["slices"] == (layout == "slices")
         ys[layout], _ = check_spmv(SYM, *up, x, label=f"symcsr {layout} entries={entries}")
     assert np.array_equal(ys["rows"], ys["slices"])
+
+
+@pytest.mark.parametrize("dims", [(20, 18, 16), (7, 5, 3), (1, 1, 1), (33, 2, 2)])
+def test_sym_compact_vs_colour_plan(monkeypatch, dims):
+    # compact blocks (the default for short lines) and coloured line ranges:
+    # both within the oracle's bar, and run to run identical
+    s = W.fem_p1_system(*dims, seed=29, with_rhs=False)
+    up = W.upper_triangle(s.rowptr, s.col, s.val)
+    x = W.uniform_vector(s.n, seed=30)
+    st, stats = cgmi.cg_analyze(SYM, s.n, *up)
+    assert stats["compact"] == 1
+    yc, _ = check_spmv(SYM, *up, x, label=f"symcsr compact {dims}")
+    yc2, _ = check_spmv(SYM, *up, x, label=f"symcsr compact {dims} again")
+    assert np.array_equal(yc, yc2)
+    monkeypatch.setenv("CGMI_SYM_PLAN", "colour")
+    st, stats = cgmi.cg_analyze(SYM, s.n, *up)
+    assert stats["compact"] == 0
+    yk, yo = check_spmv(SYM, *up, x, label=f"symcsr colour {dims}")
+    assert np.linalg.norm(yc - yk) <= 1e-13 * np.linalg.norm(yo)
 
 
 @pytest.mark.parametrize("fmt", [CSR, SYM, CSC])

@@ -209,11 +209,107 @@ def check_scatter_plan(fmt, ptr, idx):
     return P
 
 
-def test_scatter_plan_fem_symcsr():
+def test_scatter_plan_fem_symcsr(monkeypatch):
+    monkeypatch.setenv("CGMI_SYM_PLAN", "colour")   # the coloured plan of contiguous line ranges
     s = W.fem_p1_system(12, 10, 9, seed=3)
     up, uc, _ = W.upper_triangle(s.rowptr, s.col, s.val)
     P = check_scatter_plan(cgmi.CG_FMT_SYM_CSR, up, uc)
-    assert P["stats"]["colors"] <= 8
+    assert P["stats"]["colors"] <= 8 and P["stats"]["compact"] == 0
+
+
+def check_compact_plan(ptr, idx, base=0):
+    """Re-derives the compact-block plan of a symmetric (upper) matrix from
+    its block assignment and compares every slot and count."""
+    n = len(ptr) - 1
+    st, P = cgmi.cg_analyze_compact(n, ptr, idx, base)
+    assert st == 0, cgmi.cg_last_error(None)
+    p0 = np.asarray(ptr, np.int64) - base
+    i0 = np.asarray(idx, np.int64) - base
+    rows = np.repeat(np.arange(n), np.diff(p0))
+    bo = P["block_of"]
+    nb = P["stats"]["scatter_blocks"]
+    assert P["stats"]["compact"] == 1 and P["stats"]["colors"] == 1
+    assert bo.min() == 0 and bo.max() == nb - 1
+    sizes = np.bincount(bo, minlength=nb)
+    assert np.array_equal(sizes, P["lines"]) and sizes.max() <= 256 and sizes.min() >= 1
+    # blocks are numbered by their lowest row
+    firsts = np.array([np.flatnonzero(bo == b)[0] for b in range(nb)])
+    assert np.all(np.diff(firsts) > 0)
+    off = rows != i0
+    mir_src, mir_dst = rows[off], i0[off]          # mirrored product of (i, j) lands on row j
+    own_rows = set()
+    parked = 0
+    for b in range(nb):
+        s0, s1 = P["slot0"][b], P["slot0"][b + 1]
+        tg, cnt = P["target"][s0:s1], P["count"][s0:s1]
+        mine = np.flatnonzero(bo == b)
+        nl = mine.size
+        assert np.array_equal(tg[:nl], mine), "own rows first, ascending"
+        sel = bo[mir_src] == b
+        dst = mir_dst[sel]
+        outside = np.unique(dst[bo[dst] != b])
+        assert np.array_equal(tg[nl:], outside), "parked slots = rows outside reached by its mirrors"
+        want = dict(zip(*np.unique(dst, return_counts=True)))
+        assert all(c == want.get(t, 0) for t, c in zip(tg.tolist(), cnt.tolist()))
+        own_rows |= set(mine.tolist())
+        parked += outside.size
+        # every block is connected in the graph of A
+        adj = {}
+        for a_, c_ in zip(rows[off].tolist(), i0[off].tolist()):
+            if bo[a_] == b and bo[c_] == b:
+                adj.setdefault(a_, []).append(c_)
+                adj.setdefault(c_, []).append(a_)
+        seen, todo = {int(mine[0])}, [int(mine[0])]
+        while todo:
+            for c_ in adj.get(todo.pop(), []):
+                if c_ not in seen:
+                    seen.add(c_)
+                    todo.append(c_)
+        assert seen == set(mine.tolist()), f"block {b} is not connected"
+    assert own_rows == set(range(n))
+    assert parked == P["stats"]["parked"] and P["stats"]["slots"] == n + parked
+    return P
+
+
+def test_compact_plan_fem_symcsr():
+    s = W.fem_p1_system(12, 10, 9, seed=3)
+    up, uc, _ = W.upper_triangle(s.rowptr, s.col, s.val)
+    P = check_compact_plan(up, uc)
+    assert P["stats"]["parked"] <= 1.2 * s.n   # contiguous 256-row ranges park ~2x more here
+
+
+def test_compact_plan_fewer_parked_than_line_ranges(monkeypatch):
+    # a 40^3 grid: compact blocks park under half of what line ranges need
+    s = W.fem_p1_system(40, 40, 40, seed=4, with_rhs=False)
+    up, uc, _ = W.upper_triangle(s.rowptr, s.col, s.val)
+    st, stats = cgmi.cg_analyze(cgmi.CG_FMT_SYM_CSR, s.n, up, uc, None)
+    assert st == 0 and stats["compact"] == 1
+    monkeypatch.setenv("CGMI_SYM_PLAN", "colour")
+    st, P = cgmi.cg_analyze_export(cgmi.CG_FMT_SYM_CSR, s.n, up, uc)
+    assert st == 0
+    colour_parked = int(np.sum(P["color"][np.searchsorted(P["slot0"], np.arange(P["stats"]["slots"]),
+                                                           side="right") - 1] > 0))
+    assert stats["parked"] < 0.5 * colour_parked, (stats["parked"], colour_parked)
+
+
+def test_compact_plan_ragged_and_one_based():
+    # random SPD pattern with rows of at most 8 stored entries, 1-based input
+    ptr, col, val = W.random_spd_sparse(900, density=0.004, seed=5)
+    up, uc, uv = W.upper_triangle(ptr, col, val)
+    assert np.diff(up).max() <= 8
+    P0 = check_compact_plan(up, uc)
+    st, P1 = cgmi.cg_analyze_compact(900, up + 1, uc + 1, 1)
+    assert st == 0
+    for k in ("block_of", "slot0", "target", "count"):
+        assert np.array_equal(P0[k], P1[k])
+
+
+def test_compact_plan_refused_for_long_rows():
+    up, uc = _arrow_upper(50)                      # row 0 has 50 entries: coloured plan
+    st, stats = cgmi.cg_analyze(cgmi.CG_FMT_SYM_CSR, 50, up, uc, None)
+    assert st == 0 and stats["compact"] == 0
+    st, _ = cgmi.cg_analyze_compact(50, up, uc)
+    assert st == cgmi.CG_ERR_ARG
 
 
 def check_panel_plan(ptr, idx, base=0):
@@ -351,7 +447,8 @@ def test_scatter_plan_too_many_colours_is_an_error(monkeypatch):
     assert st == cgmi.CG_ERR_UNSUPPORTED and "colours" in cgmi.cg_last_error(None)
 
 
-def test_one_based_input_same_plan():
+def test_one_based_input_same_plan(monkeypatch):
+    monkeypatch.setenv("CGMI_SYM_PLAN", "colour")
     s = W.fem_p1_system(6, 5, 4, seed=7)
     up, uc, _ = W.upper_triangle(s.rowptr, s.col, s.val)
     st0, P0 = cgmi.cg_analyze_export(cgmi.CG_FMT_SYM_CSR, s.n, up, uc, 0)
