@@ -242,6 +242,28 @@ const char *cg_batch_last_error(const cg_batch *h);
 int cg_spmv(cg_handle *h, const double *x, double *y);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * product as cg_spmv -- same kernels, same bits -- with its scratch (the
+ * workgroups' dot partials and, for symmetric CSR and CSC, the parked sums
+ * of the row pass) in a fixed 32 MiB array in device memory instead of the
+ * handle's buffers.  Calls no hipMalloc / hipFree or other allocating
+ * routine (the first call on a device looks the array's address up once).
+ * Every call on one GPU shares that GPU's array, so calls whose products
+ * overlap on one GPU (other streams, other threads, other handles) race; the
+ * array keeps the last call's contents and needs no clearing (every value a
+ * product reads it writes first).
+ *   h     handle whose device is the current device
+ *   x, y  device pointers, n float64 each, not overlapping
+ * Errors: CG_ERR_ARG if h / x / y is NULL, x == y, the current device is not
+ * the handle's, or the product needs more scratch than the array holds
+ * (8 bytes per dot partial plus 8 per parked sum: n of them for CSC,
+ * cg_plan_stats.parked for symmetric CSR; about 4M rows of CSC);
+ * CG_ERR_HIP.  Asynchronous on the handle's stream.
+ */
+int cg_spmv_static(cg_handle *h, const double *x, double *y);
+
+/*
  * Differentiating the solve.  For x = A^-1 b and a loss L(x), the adjoint
  * lam = A^-1 dL/dx (A symmetric, so a second cg_solve on the same handle)
  * gives dL/db = lam and dL/dA_ij = -lam_i x_j; nothing from the forward

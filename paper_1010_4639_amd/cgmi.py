@@ -30,7 +30,7 @@ EXPORTS = ("cg_create", "cg_set_stream", "cg_set_batch", "cg_solve", "cg_solve_m
            "cg_batch_create", "cg_batch_set_stream", "cg_batch_spmm", "cg_batch_autotune", "cg_batch_solve",
            "cg_batch_destroy", "cg_batch_last_error", "cg_set_values", "cg_pattern_grad", "cg_fem_create",
            "cg_fem_set_stream", "cg_fem_pattern", "cg_fem_assemble", "cg_fem_nu_grad", "cg_fem_destroy",
-           "cg_fem_last_error", "cg_analyze_panels", "cg_analyze_compact")
+           "cg_fem_last_error", "cg_analyze_panels", "cg_analyze_compact", "cg_spmv_static")
 
 
 class cg_info(ctypes.Structure):
@@ -87,6 +87,7 @@ def load():
     lib.cg_solve.argtypes = [_VP, _VP, _VP, dbl, i32, ctypes.POINTER(cg_info)]
     lib.cg_solve_mixed.argtypes = [_VP, _VP, _VP, dbl, i32, dbl, i32, ctypes.POINTER(cg_info)]
     lib.cg_spmv.argtypes = [_VP, _VP, _VP]
+    lib.cg_spmv_static.argtypes = [_VP, _VP, _VP]
     lib.cg_get_stats.argtypes = [_VP, ctypes.POINTER(cg_plan_stats)]
     lib.cg_destroy.argtypes = [_VP]
     lib.cg_destroy.restype = None
@@ -123,7 +124,7 @@ def load():
                "cg_fem_assemble", "cg_fem_nu_grad", "cg_analyze_panels", "cg_analyze_compact"):
         getattr(lib, nm).restype = ctypes.c_int
     for nm in ("cg_create", "cg_set_stream", "cg_set_batch", "cg_solve", "cg_solve_mixed", "cg_spmv",
-               "cg_get_stats",
+               "cg_spmv_static", "cg_get_stats",
                "cg_analyze", "cg_analyze_export"):
         getattr(lib, nm).restype = ctypes.c_int
     _lib = lib
@@ -339,6 +340,19 @@ class Solver:
         xp, yp = _dev(x, self.n, "x"), _dev(y, self.n, "y")
         self._stream()
         st = load().cg_spmv(self.h, xp, yp)
+        if st != CG_OK:
+            raise CgError(st, cg_last_error(self.h))
+        return y
+
+    def spmv_static(self, x, y=None):
+        """y = A x through cg_spmv_static (scratch in the library's static
+        device array; the library allocates nothing)."""
+        import torch
+        if y is None:
+            y = torch.empty_like(x)
+        xp, yp = _dev(x, self.n, "x"), _dev(y, self.n, "y")
+        self._stream()
+        st = load().cg_spmv_static(self.h, xp, yp)
         if st != CG_OK:
             raise CgError(st, cg_last_error(self.h))
         return y

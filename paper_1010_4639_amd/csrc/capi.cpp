@@ -17,6 +17,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -26,6 +27,9 @@
 #include "plan.h"
 
 using namespace cgmi;
+
+// The static scratch array of cg_spmv_static (see static_scratch below).
+static __device__ __align__(256) double scratch[(32u << 20) / sizeof(double)];
 
 struct cg_handle {
     Plan plan;
@@ -231,6 +235,7 @@ int upload_all(cg_handle *h, const std::vector<int32_t> &ptr0, const std::vector
         m.pn_val = pv;
         m.pn_first_parked = fp;
         m.part = part;
+        m.part_doubles = n;
         m.has_c0 = dc0;
         m.scatter_wgs = p.scatter_wgs();
         if (h->mixed && !p.slices && (st = dalloc(h, &m.pn_val32, p.pn_src.size())) != CG_OK)
@@ -268,6 +273,7 @@ int upload_all(cg_handle *h, const std::vector<int32_t> &ptr0, const std::vector
         m.compact = true;
         m.cblocks = cb;
         m.parked = p.cp_parked;
+        m.part_doubles = p.cp_parked;
         m.slot_target = tg;
         m.seg = sg;
         m.tl = tl;
@@ -349,6 +355,7 @@ int upload_all(cg_handle *h, const std::vector<int32_t> &ptr0, const std::vector
         m.blocks = b;
         m.slot_target = tg;
         m.slot_flag = fl;
+        m.part_doubles = (int64_t)otg.size();
         m.seg = sg;
         m.tl = tl;
         m.part = part;
@@ -590,6 +597,39 @@ int refresh_values(cg_handle *h)
     return CG_OK;
 }
 
+// Scratch of cg_spmv_static (dot partials and parked sums of one product):
+// a fixed array in device memory, one copy on every GPU the library runs on,
+// held until the process ends.  Host code never uses the name itself as an
+// address: static_scratch looks up each device's copy once.
+constexpr size_t kStaticScratchDoubles = (32u << 20) / sizeof(double); // 32 MiB
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_ptr[kMaxScratchDevices] = {};
+
+// Device address of the static scratch on the handle's device, which must
+// be the current device.
+int static_scratch(cg_handle *h, double **out)
+{
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess)
+        return hip_fail(h->err, e, "hipGetDevice");
+    if (dev != h->device || dev < 0 || dev >= kMaxScratchDevices) {
+        h->err = "cg_spmv_static: the current device is not the handle's";
+        return CG_ERR_ARG;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_ptr[dev] == nullptr) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess)
+            return hip_fail(h->err, e, "hipGetSymbolAddress(scratch)");
+        g_scratch_ptr[dev] = static_cast<double *>(p);
+    }
+    *out = g_scratch_ptr[dev];
+    return CG_OK;
+}
+
 int status_to_code(int32_t s)
 {
     switch (s) {
@@ -827,6 +867,35 @@ int cg_spmv(cg_handle *h, const double *x, double *y)
         return CG_ERR_ARG;
     }
     launch_spmv(h->dm, x, y, h->sig_spmv, IterCtx{}, h->stream);
+    HIP_TRY(h, hipGetLastError());
+    return CG_OK;
+}
+
+int cg_spmv_static(cg_handle *h, const double *x, double *y)
+{
+    if (!h)
+        return CG_ERR_ARG;
+    if (h->dm.n == 0)
+        return CG_OK;
+    if (!x || !y || x == y) {
+        h->err = "x / y NULL or aliased";
+        return CG_ERR_ARG;
+    }
+    // dot partials first (rounded up to 256 bytes), then the parked sums
+    const int64_t nsig = ((int64_t)std::max(1, h->dm.spmv_blocks()) + 31) / 32 * 32;
+    const int64_t need = nsig + h->dm.part_doubles;
+    if (need > (int64_t)kStaticScratchDoubles) {
+        h->err = "cg_spmv_static: the product needs " + std::to_string(need * 8) + " scratch bytes, more than the " +
+                 std::to_string(kStaticScratchDoubles * 8) + " of the static array (use cg_spmv)";
+        return CG_ERR_ARG;
+    }
+    double *base = nullptr;
+    const int st = static_scratch(h, &base);
+    if (st != CG_OK)
+        return st;
+    IterCtx c;
+    c.part = h->dm.part_doubles > 0 ? base + nsig : nullptr;
+    launch_spmv(h->dm, x, y, base, c, h->stream);
     HIP_TRY(h, hipGetLastError());
     return CG_OK;
 }

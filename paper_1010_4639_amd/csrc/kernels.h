@@ -110,6 +110,7 @@ struct DevMatrix {
     int vec_blocks = 0, vec_chunk = 0;
     int spmv_blocks() const { return format == kCsr || slices ? csr_blocks : scatter_wgs; }
     // the product ends with a row pass (parked slot sums, rows with no writer)
+    int64_t part_doubles = 0;             // entries of `part` (0: no parked sums)
     bool row_pass() const
     {
         return panel ? pn_gather : compact ? parked > 0 : (format == kSymCsr && ncolors > 1);
@@ -125,6 +126,9 @@ struct IterCtx {
     // leave the row pass of a scatter product to the r update (y then holds
     // only the colour-0 rows; the iteration's q is never read elsewhere)
     bool defer_rows = false;
+    // parked sums of a scatter product in this buffer instead of the
+    // handle's (at least DevMatrix::part_doubles entries)
+    double *part = nullptr;
 };
 
 // y = A x; writes spmv_blocks() partials of x'y into sig_part.

@@ -1194,6 +1194,13 @@ __global__ __launch_bounds__(kBlock) void k_pattern_grad(int fmt, int n, const i
     }
 }
 
+// Parked sums of a scatter product: the handle's buffer, or the caller's
+// scratch (IterCtx::part, products launched with a static scratch array).
+inline double *parked_buf(const DevMatrix &m, const IterCtx &c)
+{
+    return c.part != nullptr ? c.part : m.part;
+}
+
 template <int W, class VT, class PT>
 void csr_launch(const DevMatrix &m, const VT *val, const PT *x, double *y, double *sig, const IterCtx &c,
                 hipStream_t s)
@@ -1209,11 +1216,11 @@ void scatter_launch(const DevMatrix &m, const VT *val, const PT *x, double *y, d
     const size_t Ent = (size_t)m.lds_entries, R = (size_t)m.lds_lines;
     const size_t lds = Ent * 8 + R * 8 + (R + 1) * 4 + 2 * Ent * 2;
     hipLaunchKernelGGL((k_scatter_sums<SU, E, VT, PT>), dim3(m.scatter_wgs), dim3(kBlock), lds, s, m.ptr,
-                       m.idx, val, x, y, m.part, sig, m.blocks, m.nblocks, m.slot_target, m.seg, m.tl,
+                       m.idx, val, x, y, parked_buf(m, c), sig, m.blocks, m.nblocks, m.slot_target, m.seg, m.tl,
                        m.lds_entries, m.lds_lines, c.st);
     if (m.ncolors > 1 && !c.defer_rows)
         hipLaunchKernelGGL(k_scatter_gather, dim3((m.n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, m.n, m.rs_ptr,
-                           m.rs_idx, m.has_c0, m.part, y, c.st);
+                           m.rs_idx, m.has_c0, parked_buf(m, c), y, c.st);
 }
 
 inline const double *sym_slice_vals(const DevMatrix &m, const double *) { return m.ss_val; }
@@ -1225,15 +1232,15 @@ void scatter_slices_launch(const DevMatrix &m, const VT *val, const PT *x, doubl
 {
     if (m.matrix_cached)
         hipLaunchKernelGGL((k_scatter_slices<SU, false, VT, PT>), dim3(m.scatter_wgs), dim3(kBlock), 0, s, m.ss_idx,
-                           sym_slice_vals(m, val), m.ss_blk, x, y, m.part, sig, m.blocks, m.nblocks, m.slot_target,
+                           sym_slice_vals(m, val), m.ss_blk, x, y, parked_buf(m, c), sig, m.blocks, m.nblocks, m.slot_target,
                            m.seg, m.tl, c.st);
     else
         hipLaunchKernelGGL((k_scatter_slices<SU, true, VT, PT>), dim3(m.scatter_wgs), dim3(kBlock), 0, s, m.ss_idx,
-                           sym_slice_vals(m, val), m.ss_blk, x, y, m.part, sig, m.blocks, m.nblocks, m.slot_target,
+                           sym_slice_vals(m, val), m.ss_blk, x, y, parked_buf(m, c), sig, m.blocks, m.nblocks, m.slot_target,
                            m.seg, m.tl, c.st);
     if (m.ncolors > 1 && !c.defer_rows)
         hipLaunchKernelGGL(k_scatter_gather, dim3((m.n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, m.n, m.rs_ptr,
-                           m.rs_idx, m.has_c0, m.part, y, c.st);
+                           m.rs_idx, m.has_c0, parked_buf(m, c), y, c.st);
 }
 
 template <int SU, class VT, class PT>
@@ -1242,15 +1249,15 @@ void compact_launch(const DevMatrix &m, const VT *val, const PT *x, double *y, d
 {
     if (m.matrix_cached)
         hipLaunchKernelGGL((k_scatter_compact<SU, false, VT, PT>), dim3(m.scatter_wgs), dim3(kBlock), 0, s, m.ss_idx,
-                           sym_slice_vals(m, val), m.cblocks, m.nblocks, m.slot_target, m.seg, m.tl, x, y, m.part,
+                           sym_slice_vals(m, val), m.cblocks, m.nblocks, m.slot_target, m.seg, m.tl, x, y, parked_buf(m, c),
                            sig, c.st);
     else
         hipLaunchKernelGGL((k_scatter_compact<SU, true, VT, PT>), dim3(m.scatter_wgs), dim3(kBlock), 0, s, m.ss_idx,
-                           sym_slice_vals(m, val), m.cblocks, m.nblocks, m.slot_target, m.seg, m.tl, x, y, m.part,
+                           sym_slice_vals(m, val), m.cblocks, m.nblocks, m.slot_target, m.seg, m.tl, x, y, parked_buf(m, c),
                            sig, c.st);
     if (m.parked > 0 && !c.defer_rows)
         hipLaunchKernelGGL(k_scatter_gather, dim3((m.n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, m.n, m.rs_ptr,
-                           m.rs_idx, nullptr, m.part, y, c.st);
+                           m.rs_idx, nullptr, parked_buf(m, c), y, c.st);
 }
 
 template <class VT, class PT>
@@ -1313,7 +1320,7 @@ void slices_launch_nt(const DevMatrix &m, const VT *val, const PT *x, double *y,
 {
     hipLaunchKernelGGL((k_spmv_slices<PANEL, S, NT, VT, PT>), dim3(m.csr_blocks), dim3(kBlock), 0, s, m.sl_lines,
                        m.nslices, m.sl_off, m.sl_col, val, x, y, PANEL ? m.pn_slot_target : nullptr,
-                       PANEL ? m.part : nullptr, PANEL ? m.pn_first_parked : 0, sig_part, c.st);
+                       PANEL ? parked_buf(m, c) : nullptr, PANEL ? m.pn_first_parked : 0, sig_part, c.st);
 }
 
 template <bool PANEL, int S, class VT, class PT>
@@ -1348,12 +1355,12 @@ void spmv_any(const DevMatrix &m, const VT *val, const PT *x, double *y, double 
     } else if (m.panel && m.nblocks > 0) {
         hipLaunchKernelGGL((k_panel_rows<VT, PT>), dim3(m.scatter_wgs), dim3(kBlock), 0, s, m.nblocks,
                            m.pn_chunk_slot, m.pn_slot_ptr, m.pn_slot_target, m.pn_col, panel_vals(m, val), x, y,
-                           m.part, m.pn_first_parked, sig_part, c.st);
+                           parked_buf(m, c), m.pn_first_parked, sig_part, c.st);
     }
     if (m.panel) {
         if (m.pn_gather && !c.defer_rows)
             hipLaunchKernelGGL(k_panel_gather, dim3((m.n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, m.n,
-                               m.has_c0, m.part, y, c.st);
+                               m.has_c0, parked_buf(m, c), y, c.st);
         return;
     }
     if (m.slices)
@@ -1401,7 +1408,7 @@ void launch_update_r(const DevMatrix &m, double *r, const double *q, DevState *s
     g.rs_ptr = m.rs_ptr;
     g.rs_idx = m.rs_idx;
     g.has_c0 = m.has_c0;
-    g.part = m.part;
+    g.part = m.part; // iterations use the handle's own buffer
     const int mode = rows_deferred && m.row_pass() ? (m.panel ? 2 : m.compact ? 3 : 1) : 0;
     const dim3 grid(m.vec_blocks), blk(kBlock);
 #define CGMI_UPDATE_R(G, P)                                                                                  \
