@@ -257,13 +257,13 @@ int upload_all(cg_handle *h, const std::vector<int32_t> &ptr0, const std::vector
         }
         CompactBlock *cb;
         int32_t *tg, *drsp, *drsi, *sidx, *ssrc;
-        uint16_t *sg, *tl;
+        uint16_t *sg, *rk;
         double *part, *sv;
         const size_t np = std::max<size_t>(p.ss_src.size(), 1);
         if ((st = upload(h, &cb, p.cp_blocks.data(), p.cp_blocks.size())) != CG_OK ||
             (st = upload(h, &tg, p.slot_target.data(), p.slot_target.size())) != CG_OK ||
             (st = upload(h, &sg, p.seg.data(), p.seg.size())) != CG_OK ||
-            (st = upload(h, &tl, p.ss_tl.data(), p.ss_tl.size())) != CG_OK ||
+            (st = upload(h, &rk, p.cp_rank.data(), p.cp_rank.size())) != CG_OK ||
             (st = dalloc(h, &part, (size_t)p.cp_parked)) != CG_OK ||
             (st = upload(h, &drsp, rsp.data(), rsp.size())) != CG_OK ||
             (st = upload(h, &drsi, rsi.data(), rsi.size())) != CG_OK ||
@@ -276,7 +276,7 @@ int upload_all(cg_handle *h, const std::vector<int32_t> &ptr0, const std::vector
         m.part_doubles = p.cp_parked;
         m.slot_target = tg;
         m.seg = sg;
-        m.tl = tl;
+        m.cp_rank = rk;
         m.part = part;
         m.rs_ptr = drsp;
         m.rs_idx = drsi;

@@ -94,6 +94,7 @@ struct DevMatrix {
     // by the block that owns its line)
     bool compact = false;
     const CompactBlock *cblocks = nullptr;
+    const uint16_t *cp_rank = nullptr;    // [8 n] LDS place of each entry's mirror product
     int64_t parked = 0;
     // CSC column panels (nblocks = chunks, scatter_wgs = their workgroups)
     bool panel = false;

@@ -33,6 +33,7 @@ __device__ __forceinline__ T matrix_load(const T *p)
 // Two-element vectors for the paired loads of the sliced layout (native
 // vector types, which the non-temporal load builtin accepts).
 typedef int int2v __attribute__((ext_vector_type(2)));
+typedef unsigned int uint4v __attribute__((ext_vector_type(4)));
 template <class T>
 struct Vec2;
 template <>
@@ -680,40 +681,53 @@ __global__ __launch_bounds__(kBlock) void k_scatter_slices(
 
 // Compact blocks of the symmetric format (plan.h): thread t holds own line
 // t of the block (its row index from the block's first slots), loads that
-// line's entries (two per load, coalesced over t), sums the stored row in
-// registers left to right from rounded products, and parks the mirror
-// products a_e x_t in LDS.  After one barrier each slot sums its
-// contributions in the plan's order: own-line slots add them to their row
-// and store y (the block owns those rows; nobody else stores them), the other
-// slots park their sum for the row pass.  Fused epilogue: x'y as
-// sum_slots x_target * sum.
+// line's entries (two per load, coalesced over t) and the LDS places of
+// their mirror products (one 16-byte load), sums the stored row in registers
+// left to right from rounded products, and puts each mirror product a_e x_t
+// at its place -- the products are grouped there by the slot they add to.
+// The block's slot starts are staged in LDS (16 bytes per thread).  After
+// one barrier each slot sums its contiguous run of products in the plan's
+// order: own-line slots add it to their row's sum and store y (the block
+// owns those rows; nobody else stores them), the other slots park their sum
+// for the row pass.  Fused epilogue: x'y as sum_slots x_target * sum.
 template <int SU, bool NT, class VT, class PT>
 __global__ __launch_bounds__(kBlock) void k_scatter_compact(
     const int32_t *__restrict__ sidx, const VT *__restrict__ sval, const CompactBlock *__restrict__ blocks,
     int nblocks, const int32_t *__restrict__ slot_target, const uint16_t *__restrict__ seg,
-    const uint16_t *__restrict__ tl, const PT *__restrict__ x, double *__restrict__ y, double *__restrict__ part,
+    const uint16_t *__restrict__ rank, const PT *__restrict__ x, double *__restrict__ y, double *__restrict__ part,
     double *__restrict__ sig_part, DevState *st)
 {
 #pragma clang fp contract(off)
     constexpr int E = kStreamPerThread;
+    constexpr int kStarts = ((kBlock + kMaxScatterEntries + 1) + 7) / 8 * 8;
     __shared__ double sp[kMaxScatterEntries];
-    __shared__ uint16_t tv[kMaxScatterEntries];
+    __shared__ __align__(16) uint16_t st16[kStarts];
     __shared__ double red[kWaves];
-    const int wg = xcd_remap(blockIdx.x, gridDim.x);
     if (st != nullptr && !iter_gate(st))
         return;
     const int t = threadIdx.x;
-    const int b0 = (int)((int64_t)wg * nblocks / gridDim.x);
-    const int b1 = (int)((int64_t)(wg + 1) * nblocks / gridDim.x);
+    // blocks of this XCD: one contiguous eighth; its workgroups take them in
+    // turn (workgroup i of the XCD: blocks i, i + G, i + 2G, ...), so the
+    // blocks in flight on an XCD at any time are neighbours, whose x and y
+    // lines meet in that XCD's L2
+    const int nx = min(kXcds, (int)gridDim.x);
+    const int xcd = blockIdx.x % nx, wi = blockIdx.x / nx;
+    const int gx = ((int)gridDim.x - xcd + nx - 1) / nx;
+    const int b1 = (int)((int64_t)(xcd + 1) * nblocks / nx);
     double sig = 0.0;
-    for (int b = b0; b < b1; ++b) {
+    for (int b = (int)((int64_t)xcd * nblocks / nx) + wi; b < b1; b += gx) {
         const CompactBlock bk = blocks[b];
         const int nl = bk.nl, L = bk.len;
         const bool mine = t < nl;
-        // ---- independent loads
-        for (int i = t; i < bk.ntl; i += kBlock)
-            tv[i] = tl[bk.tl0 + i];
+        // ---- independent loads: slot starts -> LDS, own line, LDS places,
+        //      entries, and the rows of the parked slots
+        if (8 * t < bk.nslots + 1)
+            *reinterpret_cast<uint4v *>(st16 + 8 * t) =
+                matrix_load<NT>(reinterpret_cast<const uint4v *>(seg + bk.seg0) + t);
         const int line = mine ? matrix_load<NT>(slot_target + bk.slot0 + t) : -1;
+        uint4v rk = {0xffffffffu, 0xffffffffu, 0xffffffffu, 0xffffffffu};
+        if (mine)
+            rk = matrix_load<NT>(reinterpret_cast<const uint4v *>(rank) + (bk.line0 + t));
         int c[E];
         double v[E];
 #pragma unroll
@@ -738,47 +752,56 @@ __global__ __launch_bounds__(kBlock) void k_scatter_compact(
                 v[m + 1] = 0.0;
             }
         }
-        const double xo = mine ? (double)x[line] : 0.0;
+        int tg[SU];
+#pragma unroll
+        for (int u = 0; u < SU; ++u) {
+            const int s = t + u * kBlock;
+            tg[u] = s < nl ? line : s < bk.nslots ? matrix_load<NT>(slot_target + bk.slot0 + s) : -1;
+        }
         // ---- gathers
+        const double xo = mine ? (double)x[line] : 0.0;
         double xg[E];
 #pragma unroll
         for (int m = 0; m < E; ++m)
             xg[m] = c[m] >= 0 ? (double)x[c[m]] : 0.0;
-        // ---- own row in registers; mirror products (not the diagonal) to LDS
+        double xt[SU];
+#pragma unroll
+        for (int u = 0; u < SU; ++u)
+            xt[u] = t + u * kBlock < nl ? xo : tg[u] >= 0 ? (double)x[tg[u]] : 0.0;
+        // ---- own row in registers; mirror products (not the diagonal) to their places
+        const uint32_t rw[4] = {rk.x, rk.y, rk.z, rk.w};
         double own = 0.0;
 #pragma unroll
         for (int m = 0; m < E; ++m)
             if (c[m] >= 0) {
                 own = own + v[m] * xg[m];
-                if (c[m] != line)
-                    sp[m * nl + t] = v[m] * xo;
+                const uint32_t place = (rw[m >> 1] >> (16 * (m & 1))) & 0xffffu;
+                if (place != 0xffffu)
+                    sp[place] = v[m] * xo;
             }
         __syncthreads();
         // ---- slot sums: own lines store y, the others park
-        const uint16_t *sg = seg + bk.seg0;
 #pragma unroll
         for (int u = 0; u < SU; ++u) {
-            const int s = t + u * kBlock;
-            if (s >= bk.nslots)
+            if (tg[u] < 0)
                 continue;
+            const int s = t + u * kBlock;
             const bool own_slot = s < nl; // implies u == 0 and s == t
-            const int tg = own_slot ? line : matrix_load<NT>(slot_target + bk.slot0 + s);
-            const double xt = own_slot ? xo : (double)x[tg];
             double a = own_slot ? own : 0.0;
-            const int hi = sg[s + 1];
-            for (int i = sg[s]; i < hi; ++i)
-                a += sp[tv[i]];
+            const int hi = st16[s + 1];
+            for (int i = st16[s]; i < hi; ++i)
+                a += sp[i];
             if (own_slot)
-                y[tg] = a;
+                y[tg[u]] = a;
             else
                 part[bk.park0 + (s - nl)] = a;
-            sig = fma(xt, a, sig);
+            sig = fma(xt[u], a, sig);
         }
         __syncthreads(); // LDS is reused by the next block
     }
     sig = block_sum(sig, red);
     if (t == 0)
-        sig_part[wg] = sig;
+        sig_part[blockIdx.x] = sig;
 }
 
 // One thread per row: y_i = (y_i if a colour-0 block wrote it, else 0)
@@ -1249,11 +1272,11 @@ void compact_launch(const DevMatrix &m, const VT *val, const PT *x, double *y, d
 {
     if (m.matrix_cached)
         hipLaunchKernelGGL((k_scatter_compact<SU, false, VT, PT>), dim3(m.scatter_wgs), dim3(kBlock), 0, s, m.ss_idx,
-                           sym_slice_vals(m, val), m.cblocks, m.nblocks, m.slot_target, m.seg, m.tl, x, y, parked_buf(m, c),
+                           sym_slice_vals(m, val), m.cblocks, m.nblocks, m.slot_target, m.seg, m.cp_rank, x, y, parked_buf(m, c),
                            sig, c.st);
     else
         hipLaunchKernelGGL((k_scatter_compact<SU, true, VT, PT>), dim3(m.scatter_wgs), dim3(kBlock), 0, s, m.ss_idx,
-                           sym_slice_vals(m, val), m.cblocks, m.nblocks, m.slot_target, m.seg, m.tl, x, y, parked_buf(m, c),
+                           sym_slice_vals(m, val), m.cblocks, m.nblocks, m.slot_target, m.seg, m.cp_rank, x, y, parked_buf(m, c),
                            sig, c.st);
     if (m.parked > 0 && !c.defer_rows)
         hipLaunchKernelGGL(k_scatter_gather, dim3((m.n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, m.n, m.rs_ptr,

@@ -21,10 +21,10 @@ int64_t Plan::device_bytes() const
     if (panel) // entry source + column + reordered value; slot target / pointer; chunks; parked sums, flags
         return nnz * (4 + 4 + 8) + (int64_t)pn_slot_target.size() * (4 + 4) + (int64_t)pn_chunk_slot.size() * 4 +
                n * 9;
-    if (sym_compact) // descriptors; slot targets, segment offsets; contributions; parked sums, their
-                     // per-row lists; positions (source, column, value)
+    if (sym_compact) // descriptors; slot targets, slot starts; LDS ranks; parked sums, their per-row
+                     // lists; positions (source, column, value)
         return (int64_t)cp_blocks.size() * sizeof(CompactBlock) + (int64_t)slot_target.size() * 4 +
-               (int64_t)seg.size() * 2 + (int64_t)ss_tl.size() * 2 + cp_parked * (8 + 4) + (n + 1) * 4 +
+               (int64_t)seg.size() * 2 + (int64_t)cp_rank.size() * 2 + cp_parked * (8 + 4) + (n + 1) * 4 +
                (int64_t)ss_src.size() * (4 + 4 + 8);
     // descriptors, slot target / flag / segment offsets, contributions, parked
     // sums and their per-row index (upper bounds: every slot counted); sliced
@@ -39,8 +39,8 @@ int64_t Plan::slice_stream_bytes() const
     if (slices) // positions, slice offsets; CSC: slot targets, parked sums written and read
         return (int64_t)sl_src.size() * 12 + (int64_t)sl_off.size() * 4 +
                (panel ? (int64_t)pn_slot_target.size() * 4 + n * 17 : 0);
-    if (sym_compact) // positions; slot targets, segments; contributions; parked sums written and read, row lists
-        return (int64_t)ss_src.size() * 12 + (int64_t)slot_target.size() * (4 + 2) + (int64_t)ss_tl.size() * 2 +
+    if (sym_compact) // positions; slot targets, starts; LDS ranks; parked sums written and read, row lists
+        return (int64_t)ss_src.size() * 12 + (int64_t)slot_target.size() * (4 + 2) + (int64_t)cp_rank.size() * 2 +
                cp_parked * (8 + 8 + 4) + (n + 1) * 4;
     if (sym_slices) // positions; slot targets, segments, flags; contributions; parked sums and row lists
         return (int64_t)ss_src.size() * 12 + (int64_t)slot_target.size() * (4 + 2 + 1 + 8 + 8 + 4) +
@@ -811,6 +811,7 @@ static bool plan_sym_compact(Plan &p, const int32_t *ptr, const int32_t *idx)
     // 4. per block: positions, slots (own lines, then the rows reached
     //    outside), contributions grouped by slot (line order within a slot)
     p.cp_blocks.assign((size_t)nbk, CompactBlock{});
+    p.cp_rank.assign((size_t)n * kStreamPerThread, 0xffff);
     p.slot_target.clear();
     p.slot_count.clear();
     p.seg.clear();
@@ -867,8 +868,7 @@ static bool plan_sym_compact(Plan &p, const int32_t *ptr, const int32_t *idx)
         cb.slot0 = (int32_t)p.slot_target.size();
         cb.nslots = ns;
         cb.seg0 = (int32_t)p.seg.size();
-        cb.tl0 = (int32_t)p.ss_tl.size();
-        cb.ntl = (int32_t)contrib.size();
+        cb.line0 = l0;
         cb.park0 = (int32_t)parked;
         for (int32_t t = 0; t < nl; ++t)
             p.slot_target.push_back(lines[l0 + t]);
@@ -881,10 +881,14 @@ static bool plan_sym_compact(Plan &p, const int32_t *ptr, const int32_t *idx)
             cs[s + 1] += cs[s];
         for (int32_t s = 0; s <= ns; ++s)
             p.seg.push_back((uint16_t)cs[s]);
+        while (p.seg.size() % 8 != 0) // the next block's starts begin 16-byte aligned
+            p.seg.push_back(0);
         for (int32_t s = 0; s < ns; ++s)
             p.slot_count.push_back(cs[s + 1] - cs[s]);
-        for (const auto &c : contrib)
-            p.ss_tl.push_back((uint16_t)c.second);
+        for (size_t r = 0; r < contrib.size(); ++r) { // LDS place = rank in the slot-grouped order
+            const int32_t q = contrib[r].second, t = q % nl, k = q / nl;
+            p.cp_rank[(size_t)(l0 + t) * kStreamPerThread + k] = (uint16_t)r;
+        }
         // positions: entries k and k + 1 of line t side by side (pairs, as in
         // the slices with nl lines), padding -1; every block starts at an
         // even position, so a pair is one aligned 8- / 16-byte load

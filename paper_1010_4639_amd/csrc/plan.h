@@ -114,17 +114,18 @@ struct ScatterBlock {
     int32_t pad;           // device copy: colour of the block
 };
 
-// A compact block of the symmetric format (device layout).
+// A compact block of the symmetric format (device layout).  Its mirror
+// products are placed in LDS grouped by the slot they add to: slot s sums
+// the products at [seg[seg0 + s], seg[seg0 + s + 1]); the place of the
+// product of line t's k-th entry is cp_rank[8 (line0 + t) + k].
 struct CompactBlock {
     int32_t pos0;   // first position of its entries (even)
     int32_t len;    // entries per line (its longest line; shorter lines padded)
     int32_t nl;     // own lines = its first nl slots
     int32_t slot0;  // slots [slot0, slot0 + nslots) of slot_target
     int32_t nslots;
-    int32_t seg0;   // nslots + 1 offsets into its contributions: seg[seg0 ..]
-    int32_t tl0;    // contributions [tl0, tl0 + ntl): LDS slots k * nl + t of the mirror
-                    // products, grouped by slot
-    int32_t ntl;
+    int32_t seg0;   // nslots + 1 slot starts seg[seg0 ..] (seg0 a multiple of 8)
+    int32_t line0;  // its lines' ranks at cp_rank[8 line0 ..]
     int32_t park0;  // parked-sum index of its slot nl (its first non-own slot)
 };
 
@@ -168,6 +169,7 @@ struct Plan {
     // contributions (local positions) in ss_tl, slots in slot_target / seg
     bool sym_compact = false;
     std::vector<CompactBlock> cp_blocks;  // [nblocks] in block order
+    std::vector<uint16_t> cp_rank;        // [8 n] LDS place of each entry's mirror product (0xffff: none)
     std::vector<int32_t> cp_block_of;     // [n] block of each line
     int64_t cp_parked = 0;                // parked sums (slots that are not own lines)
     // CSC column panels (format kCsc): entries in panel order
