@@ -40,6 +40,7 @@ struct cg_handle {
     std::vector<void *> allocs;
     size_t dev_bytes = 0; // sum of the allocations
     double *r = nullptr, *p = nullptr, *q = nullptr, *xw = nullptr;
+    double *bp = nullptr; // b in the device row order (renumbered plans)
     double *sig = nullptr, *sig_spmv = nullptr, *rho = nullptr, *bb = nullptr;
     DevState *st = nullptr;
     DevState *host_st = nullptr; // pinned, 2 entries
@@ -241,36 +242,50 @@ int upload_all(cg_handle *h, const std::vector<int32_t> &ptr0, const std::vector
         if (h->mixed && !p.slices && (st = dalloc(h, &m.pn_val32, p.pn_src.size())) != CG_OK)
             return st;
     } else if (p.sym_compact && n > 0) {
-        // compact blocks (plan.h): per row, its parked sums in ascending
-        // block order for the row pass
+        // compact blocks (plan.h), rows renumbered in block order: row
+        // indices (columns, slot targets) converted to it; per row, its
+        // parked sums in ascending block order for the row pass
+        std::vector<int32_t> inv((size_t)n);
+        for (int64_t k = 0; k < n; ++k)
+            inv[p.cp_perm[k]] = (int32_t)k;
+        std::vector<int32_t> dtg(p.slot_target.size()), didx(p.ss_idx.size());
+        for (size_t q = 0; q < dtg.size(); ++q)
+            dtg[q] = inv[p.slot_target[q]];
+        for (size_t q = 0; q < didx.size(); ++q)
+            didx[q] = p.ss_idx[q] < 0 ? -1 : inv[p.ss_idx[q]];
         std::vector<int32_t> rsp((size_t)n + 1, 0), rsi((size_t)p.cp_parked);
         for (const CompactBlock &b : p.cp_blocks)
             for (int32_t s = b.nl; s < b.nslots; ++s)
-                rsp[p.slot_target[b.slot0 + s] + 1]++;
+                rsp[dtg[b.slot0 + s] + 1]++;
         for (int64_t i = 0; i < n; ++i)
             rsp[i + 1] += rsp[i];
         {
             std::vector<int32_t> next(rsp.begin(), rsp.end() - 1);
             for (const CompactBlock &b : p.cp_blocks)
                 for (int32_t s = b.nl; s < b.nslots; ++s)
-                    rsi[next[p.slot_target[b.slot0 + s]]++] = b.park0 + (s - b.nl);
+                    rsi[next[dtg[b.slot0 + s]]++] = b.park0 + (s - b.nl);
         }
         CompactBlock *cb;
-        int32_t *tg, *drsp, *drsi, *sidx, *ssrc;
+        int32_t *tg, *drsp, *drsi, *sidx, *ssrc, *vp, *vi;
         uint16_t *sg, *rk;
         double *part, *sv;
         const size_t np = std::max<size_t>(p.ss_src.size(), 1);
         if ((st = upload(h, &cb, p.cp_blocks.data(), p.cp_blocks.size())) != CG_OK ||
-            (st = upload(h, &tg, p.slot_target.data(), p.slot_target.size())) != CG_OK ||
+            (st = upload(h, &tg, dtg.data(), dtg.size())) != CG_OK ||
+            (st = upload(h, &vp, p.cp_perm.data(), p.cp_perm.size())) != CG_OK ||
+            (st = upload(h, &vi, inv.data(), inv.size())) != CG_OK ||
+            (st = dalloc(h, &h->bp, (size_t)n)) != CG_OK ||
             (st = upload(h, &sg, p.seg.data(), p.seg.size())) != CG_OK ||
             (st = upload(h, &rk, p.cp_rank.data(), p.cp_rank.size())) != CG_OK ||
             (st = dalloc(h, &part, (size_t)p.cp_parked)) != CG_OK ||
             (st = upload(h, &drsp, rsp.data(), rsp.size())) != CG_OK ||
             (st = upload(h, &drsi, rsi.data(), rsi.size())) != CG_OK ||
-            (st = upload(h, &sidx, p.ss_idx.data(), p.ss_idx.size())) != CG_OK ||
+            (st = upload(h, &sidx, didx.data(), didx.size())) != CG_OK ||
             (st = upload(h, &ssrc, p.ss_src.data(), p.ss_src.size())) != CG_OK || (st = dalloc(h, &sv, np)) != CG_OK)
             return st;
         m.compact = true;
+        m.vperm = vp;
+        m.vinv = vi;
         m.cblocks = cb;
         m.parked = p.cp_parked;
         m.part_doubles = p.cp_parked;
@@ -558,7 +573,12 @@ int mixed_rescale(cg_handle *h)
 {
     hipStream_t s = h->stream;
     HIP_TRY(h, hipMemsetAsync(h->flag, 0, sizeof(int32_t), s));
-    launch_mx_rescale(h->dm, const_cast<double *>(h->dm.dscale), const_cast<float *>(h->dm.val32), h->flag, s);
+    double *sc = const_cast<double *>(h->dm.dscale);
+    if (h->dm.vperm != nullptr) // D^-1/2 by the caller's rows first, then in the device order
+        sc = h->q;
+    launch_mx_rescale(h->dm, sc, const_cast<float *>(h->dm.val32), h->flag, s);
+    if (h->dm.vperm != nullptr)
+        launch_permute(h->dm.n, sc, h->dm.vperm, const_cast<double *>(h->dm.dscale), s);
     HIP_TRY(h, hipGetLastError());
     HIP_TRY(h, hipMemcpyAsync(&h->host_st[0].pad, h->flag, sizeof(int32_t), hipMemcpyDeviceToHost, s));
     HIP_TRY(h, hipStreamSynchronize(s));
@@ -628,6 +648,26 @@ int static_scratch(cg_handle *h, double **out)
     }
     *out = g_scratch_ptr[dev];
     return CG_OK;
+}
+
+// Vectors in and out of the device row order (compact symmetric plans
+// renumber their rows; every other plan keeps the caller's order).
+// into(): src in the caller's order -> dst in the device order; returns the
+// vector the device uses.  out_of(): device order -> caller's order.
+const double *vec_into(cg_handle *h, const double *src, double *dst)
+{
+    if (h->dm.vperm == nullptr)
+        return src;
+    launch_permute(h->dm.n, src, h->dm.vperm, dst, h->stream);
+    return dst;
+}
+
+hipError_t vec_out_of(cg_handle *h, const double *src, double *dst)
+{
+    if (h->dm.vinv == nullptr)
+        return hipMemcpyAsync(dst, src, sizeof(double) * (size_t)h->dm.n, hipMemcpyDeviceToDevice, h->stream);
+    launch_permute(h->dm.n, src, h->dm.vinv, dst, h->stream);
+    return hipGetLastError();
 }
 
 int status_to_code(int32_t s)
@@ -866,7 +906,12 @@ int cg_spmv(cg_handle *h, const double *x, double *y)
         h->err = "x / y NULL or aliased";
         return CG_ERR_ARG;
     }
-    launch_spmv(h->dm, x, y, h->sig_spmv, IterCtx{}, h->stream);
+    if (h->dm.vperm != nullptr) { // through the device row order
+        launch_spmv(h->dm, vec_into(h, x, h->p), h->q, h->sig_spmv, IterCtx{}, h->stream);
+        HIP_TRY(h, vec_out_of(h, h->q, y));
+    } else {
+        launch_spmv(h->dm, x, y, h->sig_spmv, IterCtx{}, h->stream);
+    }
     HIP_TRY(h, hipGetLastError());
     return CG_OK;
 }
@@ -895,7 +940,12 @@ int cg_spmv_static(cg_handle *h, const double *x, double *y)
         return st;
     IterCtx c;
     c.part = h->dm.part_doubles > 0 ? base + nsig : nullptr;
-    launch_spmv(h->dm, x, y, base, c, h->stream);
+    if (h->dm.vperm != nullptr) { // through the device row order (the handle's own vectors, no allocation)
+        launch_spmv(h->dm, vec_into(h, x, h->p), h->q, base, c, h->stream);
+        HIP_TRY(h, vec_out_of(h, h->q, y));
+    } else {
+        launch_spmv(h->dm, x, y, base, c, h->stream);
+    }
     HIP_TRY(h, hipGetLastError());
     return CG_OK;
 }
@@ -929,9 +979,11 @@ int cg_solve(cg_handle *h, const double *b, double *x, double tol, int32_t maxit
     int st = build_graph(h);
     if (st != CG_OK)
         return done(st);
-    // initialisation
-    launch_spmv(h->dm, x, h->q, h->sig_spmv, IterCtx{}, s);
-    launch_init_vec(h->dm, b, x, h->q, h->r, h->p, h->xw, h->rho, h->bb, s);
+    // initialisation (b and x0 in the device row order)
+    const double *bi = vec_into(h, b, h->bp);
+    const double *x0 = vec_into(h, x, h->xw);
+    launch_spmv(h->dm, x0, h->q, h->sig_spmv, IterCtx{}, s);
+    launch_init_vec(h->dm, bi, x0, h->q, h->r, h->p, h->xw, h->rho, h->bb, s);
     launch_init_state(h->dm, h->st, h->bb, h->rho, tol, maxit, s);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess)
@@ -942,11 +994,11 @@ int cg_solve(cg_handle *h, const double *b, double *x, double tol, int32_t maxit
         return done(st);
     // finish: copy x out, true residual of the returned x
     if (status == kConverged || status == kMaxit || status == kBreakdown) {
-        e = hipMemcpyAsync(x, h->xw, sizeof(double) * (size_t)n, hipMemcpyDeviceToDevice, s);
+        e = vec_out_of(h, h->xw, x);
         if (e != hipSuccess)
-            return done(hip_fail(h->err, e, "hipMemcpyAsync"));
+            return done(hip_fail(h->err, e, "copy-out"));
         launch_spmv(h->dm, h->xw, h->q, h->sig_spmv, IterCtx{}, s);
-        launch_true_residual(h->dm, b, h->q, h->bb, h->st, s);
+        launch_true_residual(h->dm, bi, h->q, h->bb, h->st, s);
     } else if (status == kZeroRhs) {
         launch_fill(n, x, 0.0, s);
     }
@@ -1000,9 +1052,11 @@ int cg_solve_mixed(cg_handle *h, const double *b, double *x, double tol, int32_t
     int st = build_graph_generic(h, true);
     if (st != CG_OK)
         return done(st);
-    // outer start: r = b - A x0, ||b||, ||r|| (FP64 product)
-    launch_spmv(h->dm, x, h->q, h->sig_spmv, IterCtx{}, s);
-    launch_init_vec(h->dm, b, x, h->q, h->rout, h->p, h->xw, h->rho, h->bb, s);
+    // outer start: r = b - A x0, ||b||, ||r|| (FP64 product; device row order)
+    const double *bi = vec_into(h, b, h->bp);
+    const double *x0 = vec_into(h, x, h->xw);
+    launch_spmv(h->dm, x0, h->q, h->sig_spmv, IterCtx{}, s);
+    launch_init_vec(h->dm, bi, x0, h->q, h->rout, h->p, h->xw, h->rho, h->bb, s);
     launch_init_state(h->dm, h->st, h->bb, h->rho, tol, maxit, s);
     DevState out;
     if ((st = read_state(h, h->st, &out)) != CG_OK)
@@ -1047,7 +1101,7 @@ int cg_solve_mixed(cg_handle *h, const double *b, double *x, double tol, int32_t
         // x += D^-1/2 c; r = b - A x (FP64 product), true residual norm
         launch_mx_apply(h->dm, h->xw, h->p, s);
         launch_spmv(h->dm, h->xw, h->q, h->sig_spmv, IterCtx{}, s);
-        launch_init_vec(h->dm, b, h->xw, h->q, h->rout, h->p, h->xw, h->rho, h->bb, s);
+        launch_init_vec(h->dm, bi, h->xw, h->q, h->rout, h->p, h->xw, h->rho, h->bb, s);
         launch_outer_norm(h->dm, h->st, h->rho, s);
         if ((st = read_state(h, h->st, &out)) != CG_OK)
             return done(st);
@@ -1058,7 +1112,7 @@ int cg_solve_mixed(cg_handle *h, const double *b, double *x, double tol, int32_t
             break;
         }
     }
-    hipError_t e = hipMemcpyAsync(x, h->xw, sizeof(double) * (size_t)n, hipMemcpyDeviceToDevice, s);
+    hipError_t e = vec_out_of(h, h->xw, x);
     if (e == hipSuccess)
         e = hipStreamSynchronize(s);
     if (e != hipSuccess)

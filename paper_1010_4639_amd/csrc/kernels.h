@@ -92,8 +92,10 @@ struct DevMatrix {
     // slots in slot_target / seg, contributions in tl, parked sums in part
     // with per-row lists rs_ptr / rs_idx (has_c0 unused: every row is stored
     // by the block that owns its line)
-    bool compact = false;
+    bool compact = false;                 // (its rows renumbered in block order: vperm / vinv)
     const CompactBlock *cblocks = nullptr;
+    const int32_t *vperm = nullptr;       // [n] device row k = caller's row vperm[k]
+    const int32_t *vinv = nullptr;        // [n] caller's row i = device row vinv[i]
     const uint16_t *cp_rank = nullptr;    // [8 n] LDS place of each entry's mirror product
     int64_t parked = 0;
     // CSC column panels (nblocks = chunks, scatter_wgs = their workgroups)
@@ -174,7 +176,8 @@ void launch_permute(int64_t nnz, const double *src, const int32_t *perm, double 
 void launch_permute(int64_t nnz, const float *src, const int32_t *perm, float *dst, hipStream_t s);
 // val[k] = src[perm ? perm[k] : k] for k < nnz
 void launch_set_values(int64_t nnz, const double *src, const int32_t *perm, double *val, hipStream_t s);
-// mixed precision: recompute D^-1/2 and the FP32 scaled values from m.val; *bad <- 1 on a bad diagonal
+// mixed precision: recompute D^-1/2 (into sc, the caller's row order) and the FP32 scaled values from
+// m.val; *bad <- 1 on a bad diagonal
 void launch_mx_rescale(const DevMatrix &m, double *sc, float *v32, int32_t *bad, hipStream_t s);
 // out[perm ? perm[k] : k] = dL/d(stored value k) from the adjoint lam and the solution x
 void launch_pattern_grad(const DevMatrix &m, const double *lam, const double *x, const int32_t *perm, double *out,

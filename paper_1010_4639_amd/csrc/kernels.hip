@@ -680,7 +680,7 @@ __global__ __launch_bounds__(kBlock) void k_scatter_slices(
 }
 
 // Compact blocks of the symmetric format (plan.h): thread t holds own line
-// t of the block (its row index from the block's first slots), loads that
+// t of the block (row line0 + t of the block order), loads that
 // line's entries (two per load, coalesced over t) and the LDS places of
 // their mirror products (one 16-byte load), sums the stored row in registers
 // left to right from rounded products, and puts each mirror product a_e x_t
@@ -724,7 +724,7 @@ __global__ __launch_bounds__(kBlock) void k_scatter_compact(
         if (8 * t < bk.nslots + 1)
             *reinterpret_cast<uint4v *>(st16 + 8 * t) =
                 matrix_load<NT>(reinterpret_cast<const uint4v *>(seg + bk.seg0) + t);
-        const int line = mine ? matrix_load<NT>(slot_target + bk.slot0 + t) : -1;
+        const int line = mine ? bk.line0 + t : -1; // rows renumbered in block order
         uint4v rk = {0xffffffffu, 0xffffffffu, 0xffffffffu, 0xffffffffu};
         if (mine)
             rk = matrix_load<NT>(reinterpret_cast<const uint4v *>(rank) + (bk.line0 + t));

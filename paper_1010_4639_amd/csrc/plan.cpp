@@ -826,6 +826,7 @@ static bool plan_sym_compact(Plan &p, const int32_t *ptr, const int32_t *idx)
     p.max_slots = 0;
     p.max_entries = 0;
     p.max_lines = 0;
+    p.cp_perm = lines; // blocks' lines in block order: the device numbering
     for (int32_t b = 0; b < nbk; ++b) {
         const int32_t l0 = lp[b], nl = lp[b + 1] - lp[b];
         int32_t len = 0;

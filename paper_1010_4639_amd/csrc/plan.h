@@ -41,7 +41,13 @@
 // Its remaining slots are the rows outside the block that its mirror
 // products reach; their sums are parked and added to y row by row
 // afterwards, in ascending block order.  No two blocks write one location,
-// so no colouring is needed.  The entries of a block are stored like a
+// so no colouring is needed.  On the device the rows are renumbered block
+// by block (the lines of block b become the consecutive numbers
+// line0 .. line0 + nl - 1, in their original order), so a block's own rows
+// of x and y are contiguous: its y stores and own x loads are whole cache
+// lines, and its gathers stay near them.  The plan itself (and its export)
+// keeps the caller's numbering; cg_solve / cg_spmv move the caller's
+// vectors in and out of the block order.  The entries of a block are stored like a
 // slice of nl lines (entries 2j, 2j + 1 of line t side by side at
 // pos0 + 2 nl j + 2 t, the last entries of an odd width at
 // pos0 + nl (len - 1) + t).
@@ -170,6 +176,7 @@ struct Plan {
     bool sym_compact = false;
     std::vector<CompactBlock> cp_blocks;  // [nblocks] in block order
     std::vector<uint16_t> cp_rank;        // [8 n] LDS place of each entry's mirror product (0xffff: none)
+    std::vector<int32_t> cp_perm;         // [n] block order: device row k is the caller's row cp_perm[k]
     std::vector<int32_t> cp_block_of;     // [n] block of each line
     int64_t cp_parked = 0;                // parked sums (slots that are not own lines)
     // CSC column panels (format kCsc): entries in panel order
