@@ -253,7 +253,9 @@ int upload_all(cg_handle *h, const std::vector<int32_t> &ptr0, const std::vector
             dtg[q] = inv[p.slot_target[q]];
         for (size_t q = 0; q < didx.size(); ++q)
             didx[q] = p.ss_idx[q] < 0 ? -1 : inv[p.ss_idx[q]];
-        std::vector<int32_t> rsp((size_t)n + 1, 0), rsi((size_t)p.cp_parked);
+        // parked sums stored by row: row i's sums (ascending block order) at
+        // part[rsp[i] .. rsp[i + 1]); each parked slot gets its place there
+        std::vector<int32_t> rsp((size_t)n + 1, 0), dest((size_t)p.cp_parked);
         for (const CompactBlock &b : p.cp_blocks)
             for (int32_t s = b.nl; s < b.nslots; ++s)
                 rsp[dtg[b.slot0 + s] + 1]++;
@@ -263,10 +265,10 @@ int upload_all(cg_handle *h, const std::vector<int32_t> &ptr0, const std::vector
             std::vector<int32_t> next(rsp.begin(), rsp.end() - 1);
             for (const CompactBlock &b : p.cp_blocks)
                 for (int32_t s = b.nl; s < b.nslots; ++s)
-                    rsi[next[dtg[b.slot0 + s]]++] = b.park0 + (s - b.nl);
+                    dest[b.park0 + (s - b.nl)] = next[dtg[b.slot0 + s]]++;
         }
         CompactBlock *cb;
-        int32_t *tg, *drsp, *drsi, *sidx, *ssrc, *vp, *vi;
+        int32_t *tg, *drsp, *ddst, *sidx, *ssrc, *vp, *vi;
         uint16_t *sg, *rk;
         double *part, *sv;
         const size_t np = std::max<size_t>(p.ss_src.size(), 1);
@@ -279,7 +281,7 @@ int upload_all(cg_handle *h, const std::vector<int32_t> &ptr0, const std::vector
             (st = upload(h, &rk, p.cp_rank.data(), p.cp_rank.size())) != CG_OK ||
             (st = dalloc(h, &part, (size_t)p.cp_parked)) != CG_OK ||
             (st = upload(h, &drsp, rsp.data(), rsp.size())) != CG_OK ||
-            (st = upload(h, &drsi, rsi.data(), rsi.size())) != CG_OK ||
+            (st = upload(h, &ddst, dest.data(), dest.size())) != CG_OK ||
             (st = upload(h, &sidx, didx.data(), didx.size())) != CG_OK ||
             (st = upload(h, &ssrc, p.ss_src.data(), p.ss_src.size())) != CG_OK || (st = dalloc(h, &sv, np)) != CG_OK)
             return st;
@@ -294,7 +296,8 @@ int upload_all(cg_handle *h, const std::vector<int32_t> &ptr0, const std::vector
         m.cp_rank = rk;
         m.part = part;
         m.rs_ptr = drsp;
-        m.rs_idx = drsi;
+        m.rs_idx = nullptr; // parked sums already by row
+        m.cp_dest = ddst;
         m.has_c0 = nullptr;
         m.ss_idx = sidx;
         m.ss_src = ssrc;

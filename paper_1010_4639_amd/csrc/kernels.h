@@ -75,7 +75,8 @@ struct DevMatrix {
     const ScatterBlock *blocks = nullptr; // in colour order; slot0 / id refer to the colour-ordered arrays
     double *part = nullptr;              // parked slot sums (colours >= 1); CSC panels: by row
     const int32_t *rs_ptr = nullptr;     // per row: its parked slots [rs_ptr[i], rs_ptr[i+1]) of rs_idx
-    const int32_t *rs_idx = nullptr;     //   slot indices, ascending colour (symmetric CSR)
+    const int32_t *rs_idx = nullptr;     //   slot indices, ascending colour (symmetric CSR); null (compact
+                                         //   blocks): the parked sums themselves are stored by row
     const uint8_t *has_c0 = nullptr;     // per row: written by a colour-0 block; CSC panels: bit 1 = part_i
     const int32_t *slot_target = nullptr;
     const uint8_t *slot_flag = nullptr;
@@ -97,6 +98,7 @@ struct DevMatrix {
     const int32_t *vperm = nullptr;       // [n] device row k = caller's row vperm[k]
     const int32_t *vinv = nullptr;        // [n] caller's row i = device row vinv[i]
     const uint16_t *cp_rank = nullptr;    // [8 n] LDS place of each entry's mirror product
+    const int32_t *cp_dest = nullptr;     // [parked] place of each parked sum in the by-row array
     int64_t parked = 0;
     // CSC column panels (nblocks = chunks, scatter_wgs = their workgroups)
     bool panel = false;

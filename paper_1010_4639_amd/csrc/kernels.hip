@@ -689,20 +689,22 @@ __global__ __launch_bounds__(kBlock) void k_scatter_slices(
 // one barrier each slot sums its contiguous run of products in the plan's
 // order: own-line slots add it to their row's sum and store y (the block
 // owns those rows; nobody else stores them), the other slots park their sum
-// for the row pass.  Fused epilogue: x'y as sum_slots x_target * sum.
+// at its place in the by-row array of the row pass.  Fused epilogue: x'y as
+// sum_slots x_target * sum.
 template <int SU, bool NT, class VT, class PT>
-__global__ __launch_bounds__(kBlock) void k_scatter_compact(
+__global__ __launch_bounds__(kCompactThreads) void k_scatter_compact(
     const int32_t *__restrict__ sidx, const VT *__restrict__ sval, const CompactBlock *__restrict__ blocks,
     int nblocks, const int32_t *__restrict__ slot_target, const uint16_t *__restrict__ seg,
-    const uint16_t *__restrict__ rank, const PT *__restrict__ x, double *__restrict__ y, double *__restrict__ part,
-    double *__restrict__ sig_part, DevState *st)
+    const uint16_t *__restrict__ rank, const int32_t *__restrict__ dest, const PT *__restrict__ x,
+    double *__restrict__ y, double *__restrict__ part, double *__restrict__ sig_part, DevState *st)
 {
 #pragma clang fp contract(off)
     constexpr int E = kStreamPerThread;
-    constexpr int kStarts = ((kBlock + kMaxScatterEntries + 1) + 7) / 8 * 8;
-    __shared__ double sp[kMaxScatterEntries];
+    constexpr int TB = kCompactThreads;
+    constexpr int kStarts = ((TB + kCompactEntries + 1) + 7) / 8 * 8;
+    __shared__ double sp[kCompactEntries];
     __shared__ __align__(16) uint16_t st16[kStarts];
-    __shared__ double red[kWaves];
+    __shared__ double red[TB / 64];
     if (st != nullptr && !iter_gate(st))
         return;
     const int t = threadIdx.x;
@@ -721,9 +723,9 @@ __global__ __launch_bounds__(kBlock) void k_scatter_compact(
         const bool mine = t < nl;
         // ---- independent loads: slot starts -> LDS, own line, LDS places,
         //      entries, and the rows of the parked slots
-        if (8 * t < bk.nslots + 1)
-            *reinterpret_cast<uint4v *>(st16 + 8 * t) =
-                matrix_load<NT>(reinterpret_cast<const uint4v *>(seg + bk.seg0) + t);
+        for (int i = t; 8 * i < bk.nslots + 1; i += TB)
+            *reinterpret_cast<uint4v *>(st16 + 8 * i) =
+                matrix_load<NT>(reinterpret_cast<const uint4v *>(seg + bk.seg0) + i);
         const int line = mine ? bk.line0 + t : -1; // rows renumbered in block order
         uint4v rk = {0xffffffffu, 0xffffffffu, 0xffffffffu, 0xffffffffu};
         if (mine)
@@ -752,11 +754,13 @@ __global__ __launch_bounds__(kBlock) void k_scatter_compact(
                 v[m + 1] = 0.0;
             }
         }
-        int tg[SU];
+        int tg[SU], pk[SU];
 #pragma unroll
         for (int u = 0; u < SU; ++u) {
-            const int s = t + u * kBlock;
-            tg[u] = s < nl ? line : s < bk.nslots ? matrix_load<NT>(slot_target + bk.slot0 + s) : -1;
+            const int s = t + u * TB;
+            const bool parked = s >= nl && s < bk.nslots;
+            tg[u] = s < nl ? line : parked ? matrix_load<NT>(slot_target + bk.slot0 + s) : -1;
+            pk[u] = parked ? matrix_load<NT>(dest + bk.park0 + (s - nl)) : -1;
         }
         // ---- gathers
         const double xo = mine ? (double)x[line] : 0.0;
@@ -767,7 +771,7 @@ __global__ __launch_bounds__(kBlock) void k_scatter_compact(
         double xt[SU];
 #pragma unroll
         for (int u = 0; u < SU; ++u)
-            xt[u] = t + u * kBlock < nl ? xo : tg[u] >= 0 ? (double)x[tg[u]] : 0.0;
+            xt[u] = t + u * TB < nl ? xo : tg[u] >= 0 ? (double)x[tg[u]] : 0.0;
         // ---- own row in registers; mirror products (not the diagonal) to their places
         const uint32_t rw[4] = {rk.x, rk.y, rk.z, rk.w};
         double own = 0.0;
@@ -785,7 +789,7 @@ __global__ __launch_bounds__(kBlock) void k_scatter_compact(
         for (int u = 0; u < SU; ++u) {
             if (tg[u] < 0)
                 continue;
-            const int s = t + u * kBlock;
+            const int s = t + u * TB;
             const bool own_slot = s < nl; // implies u == 0 and s == t
             double a = own_slot ? own : 0.0;
             const int hi = st16[s + 1];
@@ -794,14 +798,24 @@ __global__ __launch_bounds__(kBlock) void k_scatter_compact(
             if (own_slot)
                 y[tg[u]] = a;
             else
-                part[bk.park0 + (s - nl)] = a;
+                part[pk[u]] = a; // by row: the row pass reads each row's sums contiguously
             sig = fma(xt[u], a, sig);
         }
         __syncthreads(); // LDS is reused by the next block
     }
-    sig = block_sum(sig, red);
-    if (t == 0)
-        sig_part[blockIdx.x] = sig;
+    // workgroup sum of the x'y partial (fixed tree: waves, then in order)
+    sig = group_sum<64>(sig);
+    __syncthreads();
+    if ((t & 63) == 0)
+        red[t >> 6] = sig;
+    __syncthreads();
+    if (t == 0) {
+        double a = red[0];
+#pragma unroll
+        for (int w = 1; w < TB / 64; ++w)
+            a += red[w];
+        sig_part[blockIdx.x] = a;
+    }
 }
 
 // One thread per row: y_i = (y_i if a colour-0 block wrote it, else 0)
@@ -827,7 +841,7 @@ __global__ __launch_bounds__(kBlock) void k_scatter_gather(int n, const int32_t 
     }
     double a = c0 ? y[i] : 0.0;
     for (int k = k0; k < k1; ++k)
-        a += part[rs_idx[k]];
+        a += part[rs_idx != nullptr ? rs_idx[k] : k]; // null: parked sums stored by row
     y[i] = a;
 }
 
@@ -857,7 +871,7 @@ __global__ __launch_bounds__(kBlock) void k_panel_gather(int n, const uint8_t *_
 // Each workgroup owns a contiguous chunk (XCD-remapped).  The first kPre
 // elements per thread are loaded before the dot partials of the previous
 // kernel are reduced, so the two memory round trips overlap.
-constexpr int kPre = 4;
+constexpr int kPre = 8;
 
 // Rows finished by the row pass of a scatter product: GATHER folds that pass
 // (k_scatter_gather's sum, same terms, same order) into the r update, so the
@@ -865,8 +879,8 @@ constexpr int kPre = 4;
 // GATHER: 0 = no row pass; 1 = per-row lists of parked slots (symmetric
 // CSR, coloured plan); 2 = at most one parked sum per row, stored by row,
 // with a flag byte (bit 0: y_i holds a share, bit 1: part_i does; CSC
-// panels); 3 = per-row lists, y_i always stored (symmetric CSR, compact
-// blocks).
+// panels); 3 = parked sums stored by row at [rs_ptr[i], rs_ptr[i+1]), y_i
+// always stored (symmetric CSR, compact blocks).
 struct RowPass {
     const int32_t *rs_ptr = nullptr, *rs_idx = nullptr;
     const uint8_t *has_c0 = nullptr;
@@ -888,7 +902,7 @@ __device__ __forceinline__ double q_value(const double *__restrict__ q, const Ro
     const int k0 = g.rs_ptr[i], k1 = g.rs_ptr[i + 1];
     double a = (GATHER == 3 || g.has_c0[i]) ? q[i] : 0.0;
     for (int k = k0; k < k1; ++k)
-        a += g.part[g.rs_idx[k]];
+        a += g.part[GATHER == 3 ? k : g.rs_idx[k]]; // compact blocks: parked sums stored by row
     return a;
 }
 
@@ -1271,12 +1285,14 @@ void compact_launch(const DevMatrix &m, const VT *val, const PT *x, double *y, d
                     hipStream_t s)
 {
     if (m.matrix_cached)
-        hipLaunchKernelGGL((k_scatter_compact<SU, false, VT, PT>), dim3(m.scatter_wgs), dim3(kBlock), 0, s, m.ss_idx,
-                           sym_slice_vals(m, val), m.cblocks, m.nblocks, m.slot_target, m.seg, m.cp_rank, x, y, parked_buf(m, c),
+        hipLaunchKernelGGL((k_scatter_compact<SU, false, VT, PT>), dim3(m.scatter_wgs), dim3(kCompactThreads), 0, s,
+                           m.ss_idx,
+                           sym_slice_vals(m, val), m.cblocks, m.nblocks, m.slot_target, m.seg, m.cp_rank, m.cp_dest, x, y, parked_buf(m, c),
                            sig, c.st);
     else
-        hipLaunchKernelGGL((k_scatter_compact<SU, true, VT, PT>), dim3(m.scatter_wgs), dim3(kBlock), 0, s, m.ss_idx,
-                           sym_slice_vals(m, val), m.cblocks, m.nblocks, m.slot_target, m.seg, m.cp_rank, x, y, parked_buf(m, c),
+        hipLaunchKernelGGL((k_scatter_compact<SU, true, VT, PT>), dim3(m.scatter_wgs), dim3(kCompactThreads), 0, s,
+                           m.ss_idx,
+                           sym_slice_vals(m, val), m.cblocks, m.nblocks, m.slot_target, m.seg, m.cp_rank, m.cp_dest, x, y, parked_buf(m, c),
                            sig, c.st);
     if (m.parked > 0 && !c.defer_rows)
         hipLaunchKernelGGL(k_scatter_gather, dim3((m.n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, m.n, m.rs_ptr,
@@ -1287,12 +1303,12 @@ template <class VT, class PT>
 void compact_dispatch(const DevMatrix &m, const VT *val, const PT *x, double *y, double *sig, const IterCtx &c,
                       hipStream_t s)
 {
-    if (m.max_slots <= 2 * kBlock)
+    if (m.max_slots <= 2 * kCompactThreads)
         compact_launch<2>(m, val, x, y, sig, c, s);
-    else if (m.max_slots <= 4 * kBlock)
+    else if (m.max_slots <= 4 * kCompactThreads)
         compact_launch<4>(m, val, x, y, sig, c, s);
     else
-        compact_launch<9>(m, val, x, y, sig, c, s);
+        compact_launch<10>(m, val, x, y, sig, c, s); // <= lines + entries = 9 x 512
 }
 
 template <int E, class VT, class PT>

@@ -716,7 +716,7 @@ static bool plan_sym_compact(Plan &p, const int32_t *ptr, const int32_t *idx)
         stamp[seed] = nb;
         heap.push_back({key((int32_t)seed), (int32_t)seed});
         int lines = 0;
-        while (!heap.empty() && lines < kMaxBlockLines) {
+        while (!heap.empty() && lines < kCompactLines) {
             std::pop_heap(heap.begin(), heap.end());
             const Cand c = heap.back();
             heap.pop_back();
@@ -768,7 +768,7 @@ static bool plan_sym_compact(Plan &p, const int32_t *ptr, const int32_t *idx)
                 }
             int32_t best = -1;
             for (int32_t c : touched)
-                if (bl[c] + bl[b] <= kMaxBlockLines &&
+                if (bl[c] + bl[b] <= kCompactLines &&
                     (best < 0 || cnt[c] > cnt[best] || (cnt[c] == cnt[best] && c < best)))
                     best = c;
             for (int32_t c : touched)

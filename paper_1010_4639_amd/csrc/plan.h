@@ -32,7 +32,7 @@
 // mirror product of a range lands outside it.  Instead blocks are grown on
 // the graph of A: from the lowest-numbered free line, breadth first (lines
 // nearer the seed first, then those with more couplings into the block,
-// then the lowest number), up to kMaxBlockLines lines; leftover pockets of
+// then the lowest number), up to kCompactLines (512) lines; leftover pockets of
 // fewer than kMinCompactLines lines are merged into the neighbouring block
 // they couple to most when it has room.  Each line belongs to exactly one
 // block, and that block OWNS the line's row of y: its first slots are its
@@ -98,7 +98,10 @@ constexpr int64_t kCacheResidentBytes = 336ll << 20;
 constexpr int kPanelMinWidth = 4096;    // CSC panels span at least this many columns
 constexpr int kPanelChunkEntries = kStreamEntries; // entries per CSC panel chunk
 constexpr int kPanelChunkSlots = kBlock;           // slots per CSC panel chunk (one thread each)
-constexpr int kMinCompactLines = 128;    // compact blocks: smaller pockets are merged when possible
+constexpr int kCompactThreads = 512;     // compact blocks: workgroup size (one line per thread)
+constexpr int kCompactLines = kCompactThreads;             // lines per compact block at most
+constexpr int kCompactEntries = kCompactLines * kStreamPerThread; // entries per compact block at most
+constexpr int kMinCompactLines = kCompactLines / 2;        // smaller pockets are merged when possible
 constexpr uint8_t kSlotFirst = 1;
 constexpr uint8_t kSlotLast = 2;
 

@@ -231,7 +231,7 @@ def check_compact_plan(ptr, idx, base=0):
     assert P["stats"]["compact"] == 1 and P["stats"]["colors"] == 1
     assert bo.min() == 0 and bo.max() == nb - 1
     sizes = np.bincount(bo, minlength=nb)
-    assert np.array_equal(sizes, P["lines"]) and sizes.max() <= 256 and sizes.min() >= 1
+    assert np.array_equal(sizes, P["lines"]) and sizes.max() <= 512 and sizes.min() >= 1
     # blocks are numbered by their lowest row
     firsts = np.array([np.flatnonzero(bo == b)[0] for b in range(nb)])
     assert np.all(np.diff(firsts) > 0)
