@@ -900,9 +900,23 @@ __device__ __forceinline__ double q_value(const double *__restrict__ q, const Ro
         return a;
     }
     const int k0 = g.rs_ptr[i], k1 = g.rs_ptr[i + 1];
-    double a = (GATHER == 3 || g.has_c0[i]) ? q[i] : 0.0;
+    if (GATHER == 3) {
+        // parked sums stored by row: the first two loaded without a loop, so
+        // the loads of several rows are in flight together (rarely more)
+        double a = q[i];
+        const double p0 = k0 < k1 ? g.part[k0] : 0.0;
+        const double p1 = k0 + 1 < k1 ? g.part[k0 + 1] : 0.0;
+        if (k0 < k1)
+            a += p0;
+        if (k0 + 1 < k1)
+            a += p1;
+        for (int k = k0 + 2; k < k1; ++k)
+            a += g.part[k];
+        return a;
+    }
+    double a = g.has_c0[i] ? q[i] : 0.0;
     for (int k = k0; k < k1; ++k)
-        a += g.part[GATHER == 3 ? k : g.rs_idx[k]]; // compact blocks: parked sums stored by row
+        a += g.part[g.rs_idx[k]];
     return a;
 }
 

@@ -665,11 +665,26 @@ static bool compact_allowed()
     return !(e && std::strcmp(e, "colour") == 0);
 }
 
+// Lines per compact block: kCompactLines on large matrices; on small ones
+// fewer, so that there are about 512 blocks to spread over the 256 compute
+// units (a small system's iteration is bound by latency, not bytes).
+// Experiments: CGMI_COMPACT_LINES overrides (16 .. kCompactLines).
+static int compact_block_lines(int64_t n)
+{
+    int lines = kCompactLines;
+    while (lines > 64 && n / lines < 512)
+        lines /= 2;
+    if (const char *e = std::getenv("CGMI_COMPACT_LINES"))
+        lines = std::max(16, std::min(kCompactLines, std::atoi(e)));
+    return lines;
+}
+
 // Symmetric CSR, compact blocks (plan.h).  Returns false (plan untouched)
 // when some line has more than kStreamPerThread entries.
 static bool plan_sym_compact(Plan &p, const int32_t *ptr, const int32_t *idx)
 {
     const int64_t n = p.n;
+    const int cap = compact_block_lines(n);
     for (int64_t l = 0; l < n; ++l)
         if ((int64_t)ptr[l + 1] - ptr[l] > kStreamPerThread)
             return false;
@@ -716,7 +731,7 @@ static bool plan_sym_compact(Plan &p, const int32_t *ptr, const int32_t *idx)
         stamp[seed] = nb;
         heap.push_back({key((int32_t)seed), (int32_t)seed});
         int lines = 0;
-        while (!heap.empty() && lines < kCompactLines) {
+        while (!heap.empty() && lines < cap) {
             std::pop_heap(heap.begin(), heap.end());
             const Cand c = heap.back();
             heap.pop_back();
@@ -755,7 +770,7 @@ static bool plan_sym_compact(Plan &p, const int32_t *ptr, const int32_t *idx)
         std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return bl[a] < bl[b]; });
         std::vector<int32_t> cnt((size_t)nb, 0), touched;
         for (int32_t b : order) {
-            if (bl[b] == 0 || bl[b] >= kMinCompactLines)
+            if (bl[b] == 0 || bl[b] >= cap / 2)
                 continue;
             touched.clear();
             for (int32_t i : mem[b])
@@ -768,7 +783,7 @@ static bool plan_sym_compact(Plan &p, const int32_t *ptr, const int32_t *idx)
                 }
             int32_t best = -1;
             for (int32_t c : touched)
-                if (bl[c] + bl[b] <= kCompactLines &&
+                if (bl[c] + bl[b] <= cap &&
                     (best < 0 || cnt[c] > cnt[best] || (cnt[c] == cnt[best] && c < best)))
                     best = c;
             for (int32_t c : touched)

@@ -32,8 +32,9 @@
 // mirror product of a range lands outside it.  Instead blocks are grown on
 // the graph of A: from the lowest-numbered free line, breadth first (lines
 // nearer the seed first, then those with more couplings into the block,
-// then the lowest number), up to kCompactLines (512) lines; leftover pockets of
-// fewer than kMinCompactLines lines are merged into the neighbouring block
+// then the lowest number), up to kCompactLines (512) lines -- fewer on small
+// matrices, so that there are about 512 blocks; leftover pockets of fewer
+// than half that many lines are merged into the neighbouring block
 // they couple to most when it has room.  Each line belongs to exactly one
 // block, and that block OWNS the line's row of y: its first slots are its
 // own lines (ascending), whose sums -- the stored row itself plus the mirror
@@ -101,7 +102,6 @@ constexpr int kPanelChunkSlots = kBlock;           // slots per CSC panel chunk 
 constexpr int kCompactThreads = 512;     // compact blocks: workgroup size (one line per thread)
 constexpr int kCompactLines = kCompactThreads;             // lines per compact block at most
 constexpr int kCompactEntries = kCompactLines * kStreamPerThread; // entries per compact block at most
-constexpr int kMinCompactLines = kCompactLines / 2;        // smaller pockets are merged when possible
 constexpr uint8_t kSlotFirst = 1;
 constexpr uint8_t kSlotLast = 2;
 
