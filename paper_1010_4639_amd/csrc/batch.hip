@@ -347,14 +347,19 @@ __global__ __launch_bounds__(kBlock) void k_bspmm_slices(const WgDesc *__restric
                         const double2 *p2 = reinterpret_cast<const double2 *>(P + (size_t)max(c[u], 0) * R);
 #pragma unroll
                         for (int h2 = 0; h2 < R / 2; ++h2) {
-                            const double2 q2 = c[u] >= 0 ? p2[h2] : double2{0.0, 0.0};
-                            pv[u][2 * h2] = q2.x;
-                            pv[u][2 * h2 + 1] = q2.y;
+                            // unguarded load (row clamped to 0), then a select:
+                            // a guarded load would wait inside its branch
+                            const double2 q2 = p2[h2];
+                            pv[u][2 * h2] = c[u] >= 0 ? q2.x : 0.0;
+                            pv[u][2 * h2 + 1] = c[u] >= 0 ? q2.y : 0.0;
                         }
                     } else {
 #pragma unroll
                         for (int r = 0; r < R; ++r)
-                            pv[u][r] = c[u] >= 0 ? P[(size_t)c[u] * R + r] : 0.0;
+                        {
+                            const double q = P[(size_t)max(c[u], 0) * R + r];
+                            pv[u][r] = c[u] >= 0 ? q : 0.0;
+                        }
                     }
                 }
 #pragma unroll

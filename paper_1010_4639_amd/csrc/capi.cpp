@@ -271,7 +271,12 @@ int upload_all(cg_handle *h, const std::vector<int32_t> &ptr0, const std::vector
         int32_t *tg, *drsp, *ddst, *sidx, *ssrc, *vp, *vi;
         uint16_t *sg, *rk;
         double *part, *sv;
-        const size_t np = std::max<size_t>(p.ss_src.size(), 1);
+        // positions padded by two at the end: the product reads the single
+        // last entry of an odd-width block with a 2-wide load
+        didx.push_back(-1);
+        didx.push_back(-1);
+        dest.push_back(0); // and the parked-slot rows by one
+        const size_t np = p.ss_src.size() + 2;
         if ((st = upload(h, &cb, p.cp_blocks.data(), p.cp_blocks.size())) != CG_OK ||
             (st = upload(h, &tg, dtg.data(), dtg.size())) != CG_OK ||
             (st = upload(h, &vp, p.cp_perm.data(), p.cp_perm.size())) != CG_OK ||

@@ -21,6 +21,22 @@ __device__ __forceinline__ int xcd_remap(int bid, int nblk)
     return x * per + min(x, rem) + i;
 }
 
+// x[c] for c >= 0, else 0.  FP32 x: the load is unguarded (index clamped to
+// 0; x holds at least one element) and the value selected, since a guarded
+// load takes its conversion to FP64 into the branch and waits there,
+// serialising the gathers of a round.  FP64 x: a guarded load (nothing to
+// convert; the unguarded form costs address registers and occupancy).
+template <class PT>
+__device__ __forceinline__ PT gather0(const PT *__restrict__ x, int c)
+{
+    if constexpr (sizeof(PT) == 4) {
+        const PT v = x[c < 0 ? 0 : c];
+        return c >= 0 ? v : PT(0);
+    } else {
+        return c >= 0 ? x[c] : PT(0);
+    }
+}
+
 template <int W>
 __device__ __forceinline__ double group_sum(double v)
 {
@@ -55,10 +71,14 @@ static_assert(kMaxVecBlocks <= kMaxSpmvBlocks, "vector partials fit the same reg
 template <int N>
 __device__ __forceinline__ void partials_load(const double *__restrict__ part, int m, double (&pv)[N])
 {
+    // unguarded loads (index clamped to m - 1, m >= 1) and a select: a
+    // guarded load would take the first add of the sum into its branch and
+    // wait there before the next load is issued
 #pragma unroll
     for (int j = 0; j < N; ++j) {
         const int i = threadIdx.x + j * kBlock;
-        pv[j] = i < m ? part[i] : 0.0;
+        const double v = part[min(i, m - 1)];
+        pv[j] = i < m ? v : 0.0;
     }
 }
 

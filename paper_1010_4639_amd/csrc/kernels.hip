@@ -51,30 +51,25 @@ struct Vec2<float> {
 // same state; only workgroup 0 records the decision.
 __device__ bool iter_gate(DevState *st)
 {
-    if (st->status != kRun)
-        return false;
+    // all fields read before the first decision, and the common case taken
+    // on one test of all of them (one memory round trip)
+    const int status = st->status, k = st->k, maxit = st->maxit, conv = st->conv_next;
     const double rho = st->rho_next;
     const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
-    const int k = st->k;
-    if (st->conv_next) {
-        if (lead) {
+    if ((status == kRun) & (conv == 0) & (k < maxit)) {
+        if (lead)
             st->rho = rho;
-            st->iters = k;
-            st->status = kConverged;
-        }
-        return false;
+        return true;
     }
-    if (k >= st->maxit) {
-        if (lead) {
-            st->rho = rho;
-            st->iters = k;
-            st->status = kMaxit;
-        }
+    if (status != kRun)
         return false;
-    }
-    if (lead)
+    // converged (checked first) or out of iterations
+    if (lead) {
         st->rho = rho;
-    return true;
+        st->iters = k;
+        st->status = conv ? kConverged : kMaxit;
+    }
+    return false;
 }
 
 // ------------------------------------------------------------------ CSR
@@ -129,7 +124,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv_csr(int n, int rows_per_block, 
                 break;
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                const double xv = c[u] >= 0 ? (double)x[c[u]] : 0.0;
+                const double xv = (double)gather0(x, c[u]);
                 acc[u] = fma(v[u], xv, acc[u]);
             }
         }
@@ -320,7 +315,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv_slices(int nl, int ns, const in
             for (int j = 0; j < S; ++j)
 #pragma unroll
                 for (int u = 0; u < U; ++u)
-                    xv[j][u] = c[j][u] >= 0 ? x[c[j][u]] : PT(0);
+                    xv[j][u] = gather0(x, c[j][u]);
 #pragma unroll
             for (int j = 0; j < S; ++j)
 #pragma unroll
@@ -412,7 +407,7 @@ __global__ __launch_bounds__(kBlock) void k_panel_rows(int nch, const int32_t *_
         for (int m = 0; m < E; ++m)
             if (cc[m] >= 0)
                 prod[t + m * kBlock] = v[m] * (double)x[cc[m]];
-        const double xt = tg >= 0 ? (double)x[tg] : 0.0;
+        const double xt = (double)gather0(x, tg);
         __syncthreads();
         if (t < ns) {
             double a = 0.0;
@@ -523,11 +518,11 @@ __global__ __launch_bounds__(kBlock) void k_scatter_sums(
         double xg[E];
 #pragma unroll
         for (int m = 0; m < E; ++m)
-            xg[m] = c[m] >= 0 ? (double)x[c[m]] : 0.0;
+            xg[m] = (double)gather0(x, c[m]);
         double xt[SU];
 #pragma unroll
         for (int u = 0; u < SU; ++u)
-            xt[u] = tg[u] >= 0 ? (double)x[tg[u]] : 0.0;
+            xt[u] = (double)gather0(x, tg[u]);
         __syncthreads();
         // ---- line of every entry
         for (int l = t; l < nl; l += kBlock)
@@ -623,12 +618,12 @@ __global__ __launch_bounds__(kBlock) void k_scatter_slices(
             c[m] = ok ? matrix_load<NT>(sidx + q) : -1;
             v[m] = ok ? (double)matrix_load<NT>(sval + q) : 0.0;
         }
-        const double xo = mine ? (double)x[bk.line0 + t] : 0.0;
+        const double xo = (double)gather0(x, mine ? bk.line0 + t : -1);
         // ---- gathers
         double xg[E];
 #pragma unroll
         for (int m = 0; m < E; ++m)
-            xg[m] = c[m] >= 0 ? (double)x[c[m]] : 0.0;
+            xg[m] = (double)gather0(x, c[m]);
         // ---- own row in registers; mirror products (not the diagonal) to LDS
         double own = 0.0;
 #pragma unroll
@@ -655,7 +650,7 @@ __global__ __launch_bounds__(kBlock) void k_scatter_slices(
         double xt[SU];
 #pragma unroll
         for (int u = 0; u < SU; ++u)
-            xt[u] = tg[u] >= 0 ? (double)x[tg[u]] : 0.0;
+            xt[u] = (double)gather0(x, tg[u]);
         // ---- slot sums
         const bool first_colour = bk.pad == 0;
 #pragma unroll
@@ -721,57 +716,71 @@ __global__ __launch_bounds__(kCompactThreads) void k_scatter_compact(
         const CompactBlock bk = blocks[b];
         const int nl = bk.nl, L = bk.len;
         const bool mine = t < nl;
-        // ---- independent loads: slot starts -> LDS, own line, LDS places,
-        //      entries, and the rows of the parked slots
-        for (int i = t; 8 * i < bk.nslots + 1; i += TB)
-            *reinterpret_cast<uint4v *>(st16 + 8 * i) =
-                matrix_load<NT>(reinterpret_cast<const uint4v *>(seg + bk.seg0) + i);
+        // ---- independent loads, all issued before the first wait (loads
+        //      complete in issue order): slot starts, LDS places, entries,
+        //      and the targets and rows of the parked slots.  None sits in a
+        //      divergent branch, where it would wait before the next one is
+        //      issued: indices are clamped into the block and the values
+        //      selected afterwards; branches on the block's sizes are uniform.
+        const int nchunk = (bk.nslots + 8) / 8; // 16-byte chunks of the nslots + 1 slot starts
+        const uint4v *segv = reinterpret_cast<const uint4v *>(seg + bk.seg0);
+        const uint4v sg0 = matrix_load<NT>(segv + min(t, nchunk - 1));
+        uint4v sg1 = {0u, 0u, 0u, 0u};
+        if (nchunk > TB)
+            sg1 = matrix_load<NT>(segv + min(t + TB, nchunk - 1));
+        const int tl = mine ? t : 0;
         const int line = mine ? bk.line0 + t : -1; // rows renumbered in block order
-        uint4v rk = {0xffffffffu, 0xffffffffu, 0xffffffffu, 0xffffffffu};
-        if (mine)
-            rk = matrix_load<NT>(reinterpret_cast<const uint4v *>(rank) + (bk.line0 + t));
+        const uint4v rk = matrix_load<NT>(reinterpret_cast<const uint4v *>(rank) + (bk.line0 + tl));
+        // entries m, m + 1 side by side (one 8- / 16-byte load), or the
+        // single last entry of an odd width (the 2-wide load at its position
+        // reads one more, which the arrays' end padding keeps in bounds), or,
+        // past the width, the block's first position (discarded)
+        int2v craw[E / 2];
+        typename Vec2<VT>::type vraw[E / 2];
+#pragma unroll
+        for (int h = 0; h < E / 2; ++h) {
+            const int m = 2 * h;
+            const int q = m + 1 < L ? bk.pos0 + m * nl + 2 * tl : m < L ? bk.pos0 + m * nl + tl : bk.pos0;
+            craw[h] = matrix_load<NT>(reinterpret_cast<const int2v *>(sidx + q));
+            vraw[h] = matrix_load<NT>(reinterpret_cast<const typename Vec2<VT>::type *>(sval + q));
+        }
         int c[E];
         double v[E];
 #pragma unroll
-        for (int m = 0; m < E; m += 2) {
-            // entries m, m + 1 side by side (one 8- / 16-byte load), or the
-            // single last entry of an odd width
-            if (mine && m + 1 < L) {
-                const int q = bk.pos0 + m * nl + 2 * t;
-                const int2v cc = matrix_load<NT>(reinterpret_cast<const int2v *>(sidx + q));
-                const typename Vec2<VT>::type vv =
-                    matrix_load<NT>(reinterpret_cast<const typename Vec2<VT>::type *>(sval + q));
-                c[m] = cc.x;
-                c[m + 1] = cc.y;
-                v[m] = (double)vv.x;
-                v[m + 1] = (double)vv.y;
-            } else {
-                const bool ok = mine && m < L;
-                const int q = bk.pos0 + m * nl + t;
-                c[m] = ok ? matrix_load<NT>(sidx + q) : -1;
-                v[m] = ok ? (double)matrix_load<NT>(sval + q) : 0.0;
-                c[m + 1] = -1;
-                v[m + 1] = 0.0;
-            }
+        for (int h = 0; h < E / 2; ++h) {
+            const int m = 2 * h;
+            c[m] = mine && m < L ? craw[h].x : -1;
+            c[m + 1] = mine && m + 1 < L ? craw[h].y : -1;
+            v[m] = (double)vraw[h].x;
+            v[m + 1] = (double)vraw[h].y;
         }
         int tg[SU], pk[SU];
+        const int npk = bk.nslots - nl; // parked slots of the block
 #pragma unroll
         for (int u = 0; u < SU; ++u) {
             const int s = t + u * TB;
             const bool parked = s >= nl && s < bk.nslots;
-            tg[u] = s < nl ? line : parked ? matrix_load<NT>(slot_target + bk.slot0 + s) : -1;
-            pk[u] = parked ? matrix_load<NT>(dest + bk.park0 + (s - nl)) : -1;
+            const int ts = matrix_load<NT>(slot_target + bk.slot0 + min(max(s, nl), bk.nslots - 1));
+            tg[u] = s < nl ? line : parked ? ts : -1;
+            // (dest holds one element past its last parked slot)
+            const int ps = matrix_load<NT>(dest + bk.park0 + min(max(s - nl, 0), max(npk - 1, 0)));
+            pk[u] = parked ? ps : -1;
         }
         // ---- gathers
-        const double xo = mine ? (double)x[line] : 0.0;
+        const double xo = (double)gather0(x, mine ? line : -1);
         double xg[E];
 #pragma unroll
         for (int m = 0; m < E; ++m)
-            xg[m] = c[m] >= 0 ? (double)x[c[m]] : 0.0;
+            xg[m] = (double)gather0(x, c[m]);
         double xt[SU];
 #pragma unroll
         for (int u = 0; u < SU; ++u)
-            xt[u] = t + u * TB < nl ? xo : tg[u] >= 0 ? (double)x[tg[u]] : 0.0;
+            xt[u] = t + u * TB < nl ? xo : (double)gather0(x, tg[u]);
+        // ---- slot starts to LDS (read after the barrier below)
+        if (t < nchunk)
+            *reinterpret_cast<uint4v *>(st16 + 8 * t) = sg0;
+        if (nchunk > TB && t + TB < nchunk)
+            *reinterpret_cast<uint4v *>(st16 + 8 * (t + TB)) = sg1;
         // ---- own row in registers; mirror products (not the diagonal) to their places
         const uint32_t rw[4] = {rk.x, rk.y, rk.z, rk.w};
         double own = 0.0;
@@ -920,6 +929,75 @@ __device__ __forceinline__ double q_value(const double *__restrict__ q, const Ro
     return a;
 }
 
+// q (with the row pass of GATHER folded in: q_value's terms in q_value's
+// order) and r of a thread's first kPre rows (i0, i0 + kBlock, ...; rows from
+// i1 on give 0).  The loads go out in dependency order -- row-pass indices or
+// flags, then q and r, then the parked sums -- each group for every row before
+// anything waits (loads complete in issue order); a parked sum is read
+// unguarded (from element 0, or from q_i, when the row has none) and selected
+// afterwards, so no load shares a branch with its add and waits there.
+template <int GATHER>
+__device__ __forceinline__ void row_values(const double *__restrict__ q, const double *__restrict__ r,
+                                           const RowPass &g, int n, int i0, int i1, double (&qv)[kPre],
+                                           double (&rv)[kPre])
+{
+    int k0[kPre], k1[kPre], fl[kPre];
+#pragma unroll
+    for (int u = 0; u < kPre; ++u) {
+        const int i = i0 + u * kBlock;
+        const bool ok = i < i1;
+        k0[u] = 0;
+        k1[u] = 0;
+        fl[u] = 0;
+        if (GATHER == 3) { // unguarded (row clamped), then selected
+            const int ic = min(i, n - 1);
+            const int a = g.rs_ptr[ic], b = g.rs_ptr[ic + 1];
+            k0[u] = ok ? a : 0;
+            k1[u] = ok ? b : 0;
+        }
+        if (GATHER == 2)
+            fl[u] = ok ? (int)g.has_c0[i] : 0;
+    }
+#pragma unroll
+    for (int u = 0; u < kPre; ++u) {
+        const int i = i0 + u * kBlock;
+        const bool ok = i < i1;
+        if (GATHER == 1)
+            qv[u] = ok ? q_value<1>(q, g, i) : 0.0;
+        else
+            qv[u] = ok ? q[i] : 0.0;
+        rv[u] = ok ? r[i] : 0.0;
+    }
+    if constexpr (GATHER == 2 || GATHER == 3) {
+        double p0[kPre], p1[kPre];
+#pragma unroll
+        for (int u = 0; u < kPre; ++u) {
+            if (GATHER == 3) { // part holds at least one element
+                p0[u] = g.part[k0[u] < k1[u] ? k0[u] : 0];
+                p1[u] = g.part[k0[u] + 1 < k1[u] ? k0[u] + 1 : 0];
+            } else {
+                const int ic = min(i0 + u * kBlock, n - 1);
+                p0[u] = *((fl[u] & 2) ? g.part + ic : q + ic);
+                p1[u] = 0.0;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kPre; ++u) {
+            double a = qv[u];
+            if (GATHER == 2) {
+                a = (fl[u] & 1) ? a : 0.0;
+                a = (fl[u] & 2) ? a + p0[u] : a;
+            } else {
+                a = k0[u] < k1[u] ? a + p0[u] : a;
+                a = k0[u] + 1 < k1[u] ? a + p1[u] : a;
+                for (int k = k0[u] + 2; k < k1[u]; ++k) // rare: more than two parked sums
+                    a += g.part[k];
+            }
+            qv[u] = a;
+        }
+    }
+}
+
 // PPT: dot partials per thread (n_sig <= PPT * 256)
 template <int GATHER, int PPT>
 __global__ __launch_bounds__(kBlock) void k_update_r(int n, int chunk, double *__restrict__ r,
@@ -928,20 +1006,19 @@ __global__ __launch_bounds__(kBlock) void k_update_r(int n, int chunk, double *_
                                                      double *__restrict__ rho_part, RowPass g)
 {
     __shared__ double red[kWaves];
-    if (st->status != kRun)
-        return;
+    // the gate, the partials and the first vector elements are loaded
+    // together (one memory round trip); nothing is stored before the gate
+    const int status = st->status;
+    const double rho = st->rho;
     const int blk = xcd_remap(blockIdx.x, gridDim.x);
     const int i0 = blk * chunk, i1 = min(n, i0 + chunk);
     const int t = threadIdx.x;
     double pv[PPT];
-    partials_load(sig_part, n_sig, pv); // first, so their sum does not wait for the vector loads
+    partials_load(sig_part, n_sig, pv);
     double qv[kPre], rv[kPre];
-#pragma unroll
-    for (int u = 0; u < kPre; ++u) {
-        const int i = i0 + t + u * kBlock;
-        qv[u] = i < i1 ? q_value<GATHER>(q, g, i) : 0.0;
-        rv[u] = i < i1 ? r[i] : 0.0;
-    }
+    row_values<GATHER>(q, r, g, n, i0 + t, i1, qv, rv);
+    if (status != kRun)
+        return;
     const double sigma = partials_sum(pv, n_sig, red);
     const bool lead = blockIdx.x == 0 && t == 0;
     if (!(sigma > 0.0) || !isfinite(sigma)) {
@@ -952,7 +1029,7 @@ __global__ __launch_bounds__(kBlock) void k_update_r(int n, int chunk, double *_
         }
         return;
     }
-    const double alpha = st->rho / sigma;
+    const double alpha = rho / sigma;
     if (lead) {
         st->alpha = alpha;
         st->sigma = sigma;
@@ -990,13 +1067,15 @@ __global__ __launch_bounds__(kBlock) void k_update_xp(int n, int chunk, double *
                                                       int n_rho)
 {
     __shared__ double red[kWaves];
-    if (st->status != kRun)
-        return;
+    // the gate, the partials and the first vector elements are loaded
+    // together (one memory round trip); nothing is stored before the gate
+    const int status = st->status;
+    const double alpha = st->alpha, rho = st->rho;
     const int blk = xcd_remap(blockIdx.x, gridDim.x);
     const int i0 = blk * chunk, i1 = min(n, i0 + chunk);
     const int t = threadIdx.x;
     double part[kPartPerThread];
-    partials_load(rho_part, n_rho, part); // first, so their sum does not wait for the vector loads
+    partials_load(rho_part, n_rho, part);
     double pv[kPre], xv[kPre], rv[kPre];
 #pragma unroll
     for (int u = 0; u < kPre; ++u) {
@@ -1006,9 +1085,10 @@ __global__ __launch_bounds__(kBlock) void k_update_xp(int n, int chunk, double *
         xv[u] = ok ? x[i] : 0.0;
         rv[u] = ok ? r[i] : 0.0;
     }
+    if (status != kRun)
+        return;
     const double rho_new = partials_sum(part, n_rho, red);
-    const double alpha = st->alpha;
-    const double beta = rho_new / st->rho;
+    const double beta = rho_new / rho;
     // last step: x only -- except for the FP32 directions of the mixed inner
     // solve, whose next direction carries over to the next refinement step
     const bool conv = sqrt(rho_new) <= st->tol_nb && sizeof(PT) == 8;
