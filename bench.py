@@ -172,7 +172,7 @@ def product_figures(torch, timer, S, xs, ys, nbytes, reps, flush):
     st = S.stats()
     out = dict(us=round(us, 3), GBps=round(nbytes / us / 1e3, 1), cold_us=round(cus, 3),
                cold_GBps=round(nbytes / cus / 1e3, 1), bytes=nbytes, colors=st["colors"],
-               sliced=st["slices"] == 1, matrix_cache_resident=st["cached_loads"] == 1,
+               sliced=st["slices"] >= 1, col16=st["slices"] == 2, matrix_cache_resident=st["cached_loads"] == 1,
                plan_bytes=st["plan_bytes"], device_bytes=st["device_bytes"])
     if st["format"] == 1:
         out.update(compact_blocks=st["compact"] == 1, parked_per_row=round(st["parked"] / max(st["n"], 1), 3))

@@ -176,10 +176,12 @@ int upload_all(cg_handle *h, const std::vector<int32_t> &ptr0, const std::vector
         m.csr_nrb = (int)p.csr_rb.size() - 1;
     }
     if (p.slices) {
-        int32_t *off, *col, *src;
+        int32_t *off, *col = nullptr, *src;
+        int16_t *d16 = nullptr;
         double *sv;
         if ((st = upload(h, &off, p.sl_off.data(), p.sl_off.size())) != CG_OK ||
-            (st = upload(h, &col, p.sl_col.data(), p.sl_col.size())) != CG_OK ||
+            (p.sl_d16.empty() ? (st = upload(h, &col, p.sl_col.data(), p.sl_col.size()))
+                              : (st = upload(h, &d16, p.sl_d16.data(), p.sl_d16.size()))) != CG_OK ||
             (st = upload(h, &src, p.sl_src.data(), p.sl_src.size())) != CG_OK ||
             (st = dalloc(h, &sv, std::max<size_t>(p.sl_src.size(), 1))) != CG_OK)
             return st;
@@ -188,6 +190,7 @@ int upload_all(cg_handle *h, const std::vector<int32_t> &ptr0, const std::vector
         m.nslices = (int)p.sl_off.size() - 1;
         m.sl_off = off;
         m.sl_col = col;
+        m.sl_d16 = d16;
         m.sl_src = src;
         m.sl_val = sv;
         if (h->mixed && (st = dalloc(h, &m.sl_val32, std::max<size_t>(p.sl_src.size(), 1))) != CG_OK)
@@ -271,12 +274,10 @@ int upload_all(cg_handle *h, const std::vector<int32_t> &ptr0, const std::vector
         int32_t *tg, *drsp, *ddst, *sidx, *ssrc, *vp, *vi;
         uint16_t *sg, *rk;
         double *part, *sv;
-        // positions padded by two at the end: the product reads the single
-        // last entry of an odd-width block with a 2-wide load
-        didx.push_back(-1);
-        didx.push_back(-1);
-        dest.push_back(0); // and the parked-slot rows by one
-        const size_t np = p.ss_src.size() + 2;
+        // parked-slot rows padded by one: the product reads a block's first
+        // one unguarded, also when the block has none
+        dest.push_back(0);
+        const size_t np = std::max<size_t>(p.ss_src.size(), 1);
         if ((st = upload(h, &cb, p.cp_blocks.data(), p.cp_blocks.size())) != CG_OK ||
             (st = upload(h, &tg, dtg.data(), dtg.size())) != CG_OK ||
             (st = upload(h, &vp, p.cp_perm.data(), p.cp_perm.size())) != CG_OK ||
@@ -453,7 +454,7 @@ void fill_stats(const Plan &p, cg_plan_stats *s)
     s->vec_blocks = p.vec_blocks;
     s->colors = p.ncolors;
     s->max_block_entries = p.max_entries;
-    s->slices = p.slices || p.sym_slices || p.sym_compact ? 1 : 0;
+    s->slices = !p.sl_d16.empty() ? 2 : p.slices || p.sym_slices || p.sym_compact ? 1 : 0;
     s->compact = p.sym_compact ? 1 : 0;
     s->parked = p.sym_compact ? p.cp_parked : 0;
     s->cached_loads = p.matrix_cached() ? 1 : 0;

@@ -44,6 +44,19 @@ template <>
 struct Vec2<float> {
     typedef float type __attribute__((ext_vector_type(2)));
 };
+template <>
+struct Vec2<int32_t> {
+    typedef int32_t type __attribute__((ext_vector_type(2)));
+};
+template <>
+struct Vec2<int16_t> {
+    typedef int16_t type __attribute__((ext_vector_type(2)));
+};
+
+// Column of a slice entry: stored as is (int32_t, -1 = padding) or as its
+// offset from the line's row (int16_t, kPad16 = padding).
+__device__ __forceinline__ int col_of(int32_t raw, int) { return raw; }
+__device__ __forceinline__ int col_of(int16_t raw, int row) { return raw == kPad16 ? -1 : row + raw; }
 
 // Start of an iteration (before its product): stop when the current residual
 // meets the tolerance (decided and published by the previous x/p update, or by
@@ -244,9 +257,9 @@ __global__ __launch_bounds__(kBlock) void k_spmv_csr_rows(int nrb, const int2 *_
 // panel slots; a colour-0 slot stores y[target], a colour-1 slot parks its
 // sum at part[target] for the row pass.  Fused epilogue: partial of x'y (linear in the line
 // sums, so x_target * sum per line).
-template <bool PANEL, int S, bool NT, class VT, class PT>
+template <bool PANEL, int S, bool NT, class VT, class PT, class CT>
 __global__ __launch_bounds__(kBlock) void k_spmv_slices(int nl, int ns, const int32_t *__restrict__ off,
-                                                        const int32_t *__restrict__ col, const VT *__restrict__ val,
+                                                        const CT *__restrict__ col, const VT *__restrict__ val,
                                                         const PT *__restrict__ x, double *__restrict__ y,
                                                         const int32_t *__restrict__ target, double *__restrict__ part,
                                                         int first_parked, double *__restrict__ sig_part, DevState *st)
@@ -286,30 +299,35 @@ __global__ __launch_bounds__(kBlock) void k_spmv_slices(int nl, int ns, const in
             int c[S][U];
             VT v[S][U];
             PT xv[S][U];
+            // One 2-wide load per entry pair, unconditional: entries k, k + 1
+            // side by side; the single last entry of an odd-width slice
+            // through the aligned pair holding it (the lane's parity picks
+            // the half); past the width, positions 0 and 1 (discarded).  No
+            // load sits in a branch, where it would wait for the loads before
+            // it; the entries are then selected.
+            typename Vec2<CT>::type craw[S][U / 2];
+            typename Vec2<VT>::type vraw[S][U / 2];
 #pragma unroll
             for (int j = 0; j < S; ++j)
 #pragma unroll
                 for (int u = 0; u < U; u += 2) {
-                    // entries k, k + 1 side by side (one 8- / 16-byte load per
-                    // lane), or the single last entry of an odd-width slice
                     const int k = k0 + u;
-                    const int e = e0[j] + (k >> 1) * (2 * kSliceRows) + 2 * lane;
-                    if (k + 1 < len[j]) {
-                        const int2v cc = matrix_load<NT>(reinterpret_cast<const int2v *>(col + e));
-                        const typename Vec2<VT>::type vv = matrix_load<NT>(
-                            reinterpret_cast<const typename Vec2<VT>::type *>(val + e));
-                        c[j][u] = cc.x;
-                        c[j][u + 1] = cc.y;
-                        v[j][u] = vv.x;
-                        v[j][u + 1] = vv.y;
-                    } else {
-                        const bool ok = k < len[j];
-                        const int e1 = e0[j] + k * kSliceRows + lane;
-                        c[j][u] = ok ? matrix_load<NT>(col + e1) : -1;
-                        v[j][u] = ok ? matrix_load<NT>(val + e1) : VT(0);
-                        c[j][u + 1] = -1;
-                        v[j][u + 1] = VT(0);
-                    }
+                    const int e = k + 1 < len[j] ? e0[j] + (k >> 1) * (2 * kSliceRows) + 2 * lane
+                                  : k < len[j]   ? e0[j] + k * kSliceRows + (lane & ~1)
+                                                 : 0;
+                    craw[j][u >> 1] = matrix_load<NT>(reinterpret_cast<const typename Vec2<CT>::type *>(col + e));
+                    vraw[j][u >> 1] = matrix_load<NT>(reinterpret_cast<const typename Vec2<VT>::type *>(val + e));
+                }
+#pragma unroll
+            for (int j = 0; j < S; ++j)
+#pragma unroll
+                for (int u = 0; u < U; u += 2) {
+                    const int k = k0 + u;
+                    const bool pair = k + 1 < len[j], hi = !pair && (lane & 1);
+                    c[j][u] = k < len[j] ? col_of(hi ? craw[j][u >> 1].y : craw[j][u >> 1].x, l[j]) : -1;
+                    c[j][u + 1] = pair ? col_of(craw[j][u >> 1].y, l[j]) : -1;
+                    v[j][u] = hi ? vraw[j][u >> 1].y : vraw[j][u >> 1].x;
+                    v[j][u + 1] = vraw[j][u >> 1].y;
                 }
 #pragma unroll
             for (int j = 0; j < S; ++j)
@@ -732,15 +750,15 @@ __global__ __launch_bounds__(kCompactThreads) void k_scatter_compact(
         const int line = mine ? bk.line0 + t : -1; // rows renumbered in block order
         const uint4v rk = matrix_load<NT>(reinterpret_cast<const uint4v *>(rank) + (bk.line0 + tl));
         // entries m, m + 1 side by side (one 8- / 16-byte load), or the
-        // single last entry of an odd width (the 2-wide load at its position
-        // reads one more, which the arrays' end padding keeps in bounds), or,
-        // past the width, the block's first position (discarded)
+        // single last entry of an odd width through the aligned pair holding
+        // it (the thread's parity picks the half), or, past the width, the
+        // block's first pair (discarded)
         int2v craw[E / 2];
         typename Vec2<VT>::type vraw[E / 2];
 #pragma unroll
         for (int h = 0; h < E / 2; ++h) {
             const int m = 2 * h;
-            const int q = m + 1 < L ? bk.pos0 + m * nl + 2 * tl : m < L ? bk.pos0 + m * nl + tl : bk.pos0;
+            const int q = m + 1 < L ? bk.pos0 + m * nl + 2 * tl : m < L ? bk.pos0 + m * nl + (tl & ~1) : bk.pos0;
             craw[h] = matrix_load<NT>(reinterpret_cast<const int2v *>(sidx + q));
             vraw[h] = matrix_load<NT>(reinterpret_cast<const typename Vec2<VT>::type *>(sval + q));
         }
@@ -749,9 +767,10 @@ __global__ __launch_bounds__(kCompactThreads) void k_scatter_compact(
 #pragma unroll
         for (int h = 0; h < E / 2; ++h) {
             const int m = 2 * h;
-            c[m] = mine && m < L ? craw[h].x : -1;
+            const bool hi = m + 1 >= L && (tl & 1);
+            c[m] = mine && m < L ? (hi ? craw[h].y : craw[h].x) : -1;
             c[m + 1] = mine && m + 1 < L ? craw[h].y : -1;
-            v[m] = (double)vraw[h].x;
+            v[m] = (double)(hi ? vraw[h].y : vraw[h].x);
             v[m + 1] = (double)vraw[h].y;
         }
         int tg[SU], pk[SU];
@@ -1451,9 +1470,15 @@ template <bool PANEL, int S, bool NT, class VT, class PT>
 void slices_launch_nt(const DevMatrix &m, const VT *val, const PT *x, double *y, double *sig_part, const IterCtx &c,
                       hipStream_t s)
 {
-    hipLaunchKernelGGL((k_spmv_slices<PANEL, S, NT, VT, PT>), dim3(m.csr_blocks), dim3(kBlock), 0, s, m.sl_lines,
-                       m.nslices, m.sl_off, m.sl_col, val, x, y, PANEL ? m.pn_slot_target : nullptr,
-                       PANEL ? parked_buf(m, c) : nullptr, PANEL ? m.pn_first_parked : 0, sig_part, c.st);
+    if (!PANEL && m.sl_d16 != nullptr)
+        hipLaunchKernelGGL((k_spmv_slices<false, S, NT, VT, PT, int16_t>), dim3(m.csr_blocks), dim3(kBlock), 0, s,
+                           m.sl_lines, m.nslices, m.sl_off, m.sl_d16, val, x, y, nullptr, nullptr, 0, sig_part,
+                           c.st);
+    else
+        hipLaunchKernelGGL((k_spmv_slices<PANEL, S, NT, VT, PT, int32_t>), dim3(m.csr_blocks), dim3(kBlock), 0, s,
+                           m.sl_lines, m.nslices, m.sl_off, m.sl_col, val, x, y,
+                           PANEL ? m.pn_slot_target : nullptr, PANEL ? parked_buf(m, c) : nullptr,
+                           PANEL ? m.pn_first_parked : 0, sig_part, c.st);
 }
 
 template <bool PANEL, int S, class VT, class PT>

@@ -12,8 +12,8 @@ namespace cgmi {
 
 int64_t Plan::device_bytes() const
 {
-    // slices: offsets + entry source, column, value per position
-    const int64_t sl = (int64_t)sl_off.size() * 4 + (int64_t)sl_src.size() * (4 + 4 + 8);
+    // slices: offsets + entry source, column (or 16-bit offset), value per position
+    const int64_t sl = (int64_t)sl_off.size() * 4 + (int64_t)sl_src.size() * (4 + (sl_d16.empty() ? 4 : 2) + 8);
     if (format == kCsr) // row-block starts or slices
         return (int64_t)csr_rb.size() * 4 + sl;
     if (panel && slices) // slices; slot targets; parked sums and flags by row
@@ -37,7 +37,7 @@ int64_t Plan::device_bytes() const
 int64_t Plan::slice_stream_bytes() const
 {
     if (slices) // positions, slice offsets; CSC: slot targets, parked sums written and read
-        return (int64_t)sl_src.size() * 12 + (int64_t)sl_off.size() * 4 +
+        return (int64_t)sl_src.size() * (sl_d16.empty() ? 12 : 10) + (int64_t)sl_off.size() * 4 +
                (panel ? (int64_t)pn_slot_target.size() * 4 + n * 17 : 0);
     if (sym_compact) // positions; slot targets, starts; LDS ranks; parked sums written and read, row lists
         return (int64_t)ss_src.size() * 12 + (int64_t)slot_target.size() * (4 + 2) + (int64_t)cp_rank.size() * 2 +
@@ -273,13 +273,40 @@ static int slice_mode()
     return std::strcmp(e, "slices") == 0 ? 1 : std::strcmp(e, "rows") == 0 ? -1 : 0;
 }
 
+// 16-bit column offsets of CSR slices (plan.h) when every column is within
+// 32767 of its row; experiments: CGMI_COL16=0 keeps 32-bit columns.
+static void plan_col16(Plan &p)
+{
+    if (const char *e = std::getenv("CGMI_COL16"))
+        if (std::strcmp(e, "0") == 0)
+            return;
+    const int64_t ns = (int64_t)p.sl_off.size() - 1;
+    std::vector<int16_t> d16(p.sl_col.size(), kPad16);
+    for (int64_t sl = 0; sl < ns; ++sl) {
+        const int64_t w = (p.sl_off[sl + 1] - p.sl_off[sl]) / kSliceRows;
+        for (int64_t lane = 0; lane < kSliceRows; ++lane)
+            for (int64_t k = 0; k < w; ++k) {
+                const int64_t q = p.sl_off[sl] + slice_position(k, lane, w);
+                if (p.sl_col[q] < 0)
+                    continue;
+                const int64_t d = (int64_t)p.sl_col[q] - (sl * kSliceRows + lane);
+                if (d < -32767 || d > 32767)
+                    return;
+                d16[q] = (int16_t)d;
+            }
+    }
+    p.sl_d16.swap(d16);
+}
+
 static void plan_csr(Plan &p, const int32_t *ptr, const int32_t *idx)
 {
     const int64_t n = p.n;
     const double mean = (double)p.nnz / (double)n;
     const int mode = slice_mode();
-    if (mode >= 0 && plan_slices(p, n, ptr, idx, nullptr, mode))
+    if (mode >= 0 && plan_slices(p, n, ptr, idx, nullptr, mode)) {
+        plan_col16(p);
         return;
+    }
     if (mean <= kStreamMaxMeanRow) {
         // row blocks: <= `be` entries (<= kStreamEntries) and <= kStreamRows
         // rows; a row longer than kStreamEntries is a block of its own

@@ -65,7 +65,11 @@
 // sorting and two-entry packing: for a stencil-like matrix the lanes of one
 // load read neighbouring x entries, so the gather of x becomes a
 // near-contiguous load.  Chosen when the padding stays small; each line is
-// still summed left to right by one lane.
+// still summed left to right by one lane.  CSR rows whose columns all lie
+// within 32767 of the row (any banded numbering, e.g. a 3D grid numbered
+// lexicographically up to 181 x 181 nodes a plane) store each column as its
+// 16-bit offset from the row (-32768 = padding) instead of the 32-bit index:
+// 10 instead of 12 bytes per FP64 entry, 6 instead of 8 per FP32 one.
 #pragma once
 
 #include <cstdint>
@@ -75,6 +79,7 @@
 namespace cgmi {
 
 constexpr int kBlock = 256;             // threads per workgroup in every kernel
+constexpr int16_t kPad16 = -32768;      // padding in 16-bit column offsets
 constexpr int kDefaultScatterEntries = 2048;
 constexpr int kMaxScatterEntries = 2048;   // 8 entries per thread held in registers
 constexpr int kMaxBlockLines = 256;
@@ -154,6 +159,7 @@ struct Plan {
     std::vector<int32_t> sl_off;          // [slices + 1] first position of each slice (multiple of 64)
     std::vector<int32_t> sl_src;          // [positions] caller entry (0-based) at each position, -1 = padding
     std::vector<int32_t> sl_col;          // [positions] column at each position, -1 = padding
+    std::vector<int16_t> sl_d16;          // CSR, banded: column - row at each position, kPad16 = padding (else empty)
     // scatter formats
     int nblocks = 0, ncolors = 0, max_entries = 0, max_lines = 0, max_slots = 0;
     std::vector<ScatterBlock> blocks;     // by block id

@@ -162,7 +162,7 @@ def test_early_iterates_8192_partials():
     val = np.where(col == i, 2.5, -1.0)
     b = W.uniform_vector(n, seed=33)
     st, stats = cgmi.cg_analyze(CSR, n, ptr, col, val)
-    assert stats["slices"] == 1 and stats["spmv_blocks"] == 8192
+    assert stats["slices"] == 2 and stats["spmv_blocks"] == 8192
     for k in (1, 5, 20):
         with cgmi.Solver(CSR, ptr, col, val) as S:
             xg, info = S.solve(to_dev(b), tol=0.0, maxit=k, check=False)

@@ -182,7 +182,7 @@ def test_lane_widths(monkeypatch, mean_len, layout):
     n = 1500
     ptr, col, val = W.random_sparse(n, density=mean_len / n, seed=mean_len)
     st, stats = cgmi.cg_analyze(CSR, n, ptr, col, val)
-    assert stats["slices"] == (layout == "slices")
+    assert bool(stats["slices"]) == (layout == "slices")
     say(f"lanes={stats['lanes_per_line']} slices={stats['slices']}")
     y, yo = check_spmv(CSR, ptr, col, val, W.uniform_vector(n, seed=14), label=f"mean_len={mean_len}")
     if layout == "slices":   # every row summed left to right by one lane
@@ -266,15 +266,48 @@ def test_csr_bit_identical_to_oracle(monkeypatch, case, layout):
     assert np.array_equal(y, yo)
 
 
+@pytest.mark.parametrize("col16", ["1", "0"])
 @pytest.mark.parametrize("n", [1, 63, 64, 65, 200, 4097])
-def test_csr_slices_ragged_shapes(monkeypatch, n):
-    # partial last slice, empty rows, one row far longer than the rest
+def test_csr_slices_ragged_shapes(monkeypatch, n, col16):
+    # partial last slice, empty rows, one row far longer than the rest; the
+    # columns as 16-bit offsets from the row (every column is within 32767
+    # here) or as 32-bit indices
     monkeypatch.setenv("CGMI_ROW_LAYOUT", "slices")
+    monkeypatch.setenv("CGMI_COL16", col16)
     ptr, col, val = W.random_sparse(n, density=min(1.0, 9.0 / n), seed=n, empty_rows=n // 7,
                                     long_rows=1 if n > 1 else 0, long_len=min(n, 700))
     st, stats = cgmi.cg_analyze(CSR, n, ptr, col, val)
-    assert st == 0 and stats["slices"] == 1
+    assert st == 0 and stats["slices"] == (2 if col16 == "1" else 1)
     y, yo = check_spmv(CSR, ptr, col, val, W.uniform_vector(n, seed=n + 1), label=f"slices n={n}")
+    assert np.array_equal(y, yo)
+
+
+def test_csr_col16_same_bits_and_fallback(monkeypatch):
+    """CSR slices with 16-bit column offsets against 32-bit columns: the same
+    products and CG iterates bit for bit (only the storage of the columns
+    differs), and a matrix with a column farther than 32767 from its row
+    keeps 32-bit columns."""
+    monkeypatch.setenv("CGMI_ROW_LAYOUT", "slices")
+    s = W.fem_p1_system(20, 18, 16, seed=27)
+    x = W.uniform_vector(s.n, seed=28)
+    ys, xs = {}, {}
+    for col16 in ("1", "0"):
+        monkeypatch.setenv("CGMI_COL16", col16)
+        st, stats = cgmi.cg_analyze(CSR, s.n, s.rowptr, s.col, s.val)
+        assert st == 0 and stats["slices"] == (2 if col16 == "1" else 1)
+        ys[col16], _ = check_spmv(CSR, s.rowptr, s.col, s.val, x, label=f"fem col16={col16}")
+        with cgmi.Solver("csr", s.rowptr, s.col, s.val) as S:
+            xg, info = S.solve(to_dev(s.b), tol=1e-10, maxit=5000)
+            xs[col16] = (xg.cpu().numpy(), info["iters"])
+    assert np.array_equal(ys["1"], ys["0"])
+    assert np.array_equal(xs["1"][0], xs["0"][0]) and xs["1"][1] == xs["0"][1]
+    monkeypatch.delenv("CGMI_COL16")
+    n = 40000
+    ptr, col, val = W.random_sparse(n, density=9.0 / n, seed=29)
+    assert np.max(np.abs(col - np.repeat(np.arange(n), np.diff(ptr)))) > 32767
+    st, stats = cgmi.cg_analyze(CSR, n, ptr, col, val)
+    assert st == 0 and stats["slices"] == 1
+    y, yo = check_spmv(CSR, ptr, col, val, W.uniform_vector(n, seed=30), label="wide band, 32-bit columns")
     assert np.array_equal(y, yo)
 
 
@@ -291,7 +324,7 @@ def test_csr_slices_several_per_wave():
     col = (i + off).astype(np.int32)
     val = np.where(col == i, 2.0, -1.0) + 1e-3 * W.uniform_vector(ptr[-1], seed=30)
     st, stats = cgmi.cg_analyze(CSR, n, ptr, col, val)
-    assert st == 0 and stats["slices"] == 1 and stats["spmv_blocks"] == 8192
+    assert st == 0 and stats["slices"] == 2 and stats["spmv_blocks"] == 8192
     y, yo = check_spmv(CSR, ptr, col, val, W.uniform_vector(n, seed=31), label="3.3M rows, 3 per row")
     assert np.array_equal(y, yo)
 

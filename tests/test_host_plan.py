@@ -80,13 +80,30 @@ def _slice_positions(ptr):
 def test_csr_layout_choice(monkeypatch):
     CSR = cgmi.CG_FMT_CSR
     # FEM rows differ little in length: sliced layout, padding within 12.5 %
+    # (columns within 32767 of their rows: 16-bit offsets, 14 bytes a position
+    # with the entry source and the value; else 32-bit columns, 16 bytes)
     s = W.fem_config("fem32x32x30")
     st, stats = cgmi.cg_analyze(CSR, s.n, s.rowptr, s.col, s.val)
     pos, ns = _slice_positions(s.rowptr)
-    assert st == 0 and stats["slices"] == 1
+    assert st == 0 and stats["slices"] == 2
     assert s.nnz <= pos <= 1.125 * s.nnz
-    assert stats["plan_bytes"] == 4 * (ns + 1) + 16 * pos
+    assert stats["plan_bytes"] == 4 * (ns + 1) + 14 * pos
     assert stats["spmv_blocks"] == min((ns + 3) // 4, 8192)
+    monkeypatch.setenv("CGMI_COL16", "0")
+    st, stats = cgmi.cg_analyze(CSR, s.n, s.rowptr, s.col, s.val)
+    assert st == 0 and stats["slices"] == 1 and stats["plan_bytes"] == 4 * (ns + 1) + 16 * pos
+    monkeypatch.delenv("CGMI_COL16")
+    # one column 32768 away from its row: 32-bit columns
+    n = 40000
+    ptr = np.arange(n + 1, dtype=np.int32)
+    ptr[-1] = n + 1  # the last row holds two entries: columns n - 32769 and n - 1
+    col = np.insert(np.arange(n, dtype=np.int32), n - 1, n - 1 - 32768).astype(np.int32)
+    val = np.ones(n + 1)
+    st, stats = cgmi.cg_analyze(CSR, n, ptr, col, val)
+    assert st == 0 and stats["slices"] == 1
+    col[n - 1] = n - 1 - 32767  # 32767 away: still 16-bit
+    st, stats = cgmi.cg_analyze(CSR, n, ptr, col, val)
+    assert st == 0 and stats["slices"] == 2
     # two 1500-entry rows among ~15-entry rows: padding too large, row blocks
     ptr, col, val = W.random_sparse(5000, density=0.003, seed=21, empty_rows=40, long_rows=2, long_len=1500)
     st, stats = cgmi.cg_analyze(CSR, 5000, ptr, col, val)
@@ -95,7 +112,7 @@ def test_csr_layout_choice(monkeypatch):
     monkeypatch.setenv("CGMI_ROW_LAYOUT", "slices")
     st, stats = cgmi.cg_analyze(CSR, 5000, ptr, col, val)
     pos, ns = _slice_positions(ptr)
-    assert st == 0 and stats["slices"] == 1 and stats["plan_bytes"] == 4 * (ns + 1) + 16 * pos
+    assert st == 0 and stats["slices"] == 2 and stats["plan_bytes"] == 4 * (ns + 1) + 14 * pos
     monkeypatch.setenv("CGMI_ROW_LAYOUT", "rows")
     st, stats = cgmi.cg_analyze(CSR, s.n, s.rowptr, s.col, s.val)
     assert st == 0 and stats["slices"] == 0
@@ -133,8 +150,8 @@ def test_matrix_loads_choice(monkeypatch):
     for fmt, arrs in ((cgmi.CG_FMT_CSR, (s.rowptr, s.col, s.val)), (cgmi.CG_FMT_SYM_CSR, up),
                       (cgmi.CG_FMT_CSC, (s.rowptr, s.col, s.val))):
         st, stats = cgmi.cg_analyze(fmt, s.n, *arrs)
-        assert st == 0 and stats["slices"] == 1 and stats["cached_loads"] == 1
-    n = 5_000_000                      # tridiagonal: 15 M positions, 180 MB + 40 B per row > 336 MiB
+        assert st == 0 and stats["slices"] >= 1 and stats["cached_loads"] == 1
+    n = 5_500_000                      # tridiagonal: 16.5 M positions, 165 MB + 40 B per row > 336 MiB
     lens = np.full(n, 3)
     lens[0] = lens[-1] = 2
     ptr = np.zeros(n + 1, np.int32)
@@ -142,7 +159,7 @@ def test_matrix_loads_choice(monkeypatch):
     i = np.repeat(np.arange(n), lens)
     col = (i + np.arange(ptr[-1]) - ptr[i] - (i > 0)).astype(np.int32)
     st, stats = cgmi.cg_analyze(cgmi.CG_FMT_CSR, n, ptr, col, None)
-    assert st == 0 and stats["slices"] == 1 and stats["cached_loads"] == 0
+    assert st == 0 and stats["slices"] == 2 and stats["cached_loads"] == 0
     monkeypatch.setenv("CGMI_MATRIX_LOADS", "cached")
     st, stats = cgmi.cg_analyze(cgmi.CG_FMT_CSR, n, ptr, col, None)
     assert st == 0 and stats["cached_loads"] == 1
