@@ -97,9 +97,9 @@ typedef struct {
     int32_t scatter_blocks;  /* scatter formats: blocks of the plan (sizes of cg_analyze_export) */
     int32_t max_block_entries;
     int32_t slices;          /* 1 = sliced layout (CSR: 64-row slices; CSC: 64-slot slices;
-                                symmetric CSR: blocks stored k-th entry first); 2 = CSR slices
-                                whose columns are stored as 16-bit offsets from the row (every
-                                column within 32767 of its row) */
+                                symmetric CSR: blocks stored k-th entry first); 2 = CSR or CSC
+                                slices whose columns are stored as 16-bit offsets from the row
+                                the line adds to (every column within 32767 of it) */
     int32_t cached_loads;    /* 1 = the sliced product reads the matrix with ordinary loads, so that
                                 it stays in the Infinity Cache between iterations (small enough);
                                 0 = non-temporal loads */

@@ -65,7 +65,7 @@ struct DevMatrix {
     bool slices = false;                 // sliced layout of CSR rows / CSC panel slots (plan.h)
     int sl_lines = 0, nslices = 0;
     const int32_t *sl_off = nullptr, *sl_col = nullptr, *sl_src = nullptr;
-    const int16_t *sl_d16 = nullptr;     // CSR, banded: 16-bit column offsets instead of sl_col
+    const int16_t *sl_d16 = nullptr;     // banded: 16-bit column offsets from the line's row instead of sl_col
     double *sl_val = nullptr;            // values at the slice positions (0 at padding)
     float *sl_val32 = nullptr;           // mixed precision: val32 at the slice positions
     // scatter

@@ -324,8 +324,9 @@ __global__ __launch_bounds__(kBlock) void k_spmv_slices(int nl, int ns, const in
                 for (int u = 0; u < U; u += 2) {
                     const int k = k0 + u;
                     const bool pair = k + 1 < len[j], hi = !pair && (lane & 1);
-                    c[j][u] = k < len[j] ? col_of(hi ? craw[j][u >> 1].y : craw[j][u >> 1].x, l[j]) : -1;
-                    c[j][u + 1] = pair ? col_of(craw[j][u >> 1].y, l[j]) : -1;
+                    const int row = PANEL ? tg[j] : l[j]; // the row the line adds to
+                    c[j][u] = k < len[j] ? col_of(hi ? craw[j][u >> 1].y : craw[j][u >> 1].x, row) : -1;
+                    c[j][u + 1] = pair ? col_of(craw[j][u >> 1].y, row) : -1;
                     v[j][u] = hi ? vraw[j][u >> 1].y : vraw[j][u >> 1].x;
                     v[j][u + 1] = vraw[j][u >> 1].y;
                 }
@@ -1470,10 +1471,11 @@ template <bool PANEL, int S, bool NT, class VT, class PT>
 void slices_launch_nt(const DevMatrix &m, const VT *val, const PT *x, double *y, double *sig_part, const IterCtx &c,
                       hipStream_t s)
 {
-    if (!PANEL && m.sl_d16 != nullptr)
-        hipLaunchKernelGGL((k_spmv_slices<false, S, NT, VT, PT, int16_t>), dim3(m.csr_blocks), dim3(kBlock), 0, s,
-                           m.sl_lines, m.nslices, m.sl_off, m.sl_d16, val, x, y, nullptr, nullptr, 0, sig_part,
-                           c.st);
+    if (m.sl_d16 != nullptr)
+        hipLaunchKernelGGL((k_spmv_slices<PANEL, S, NT, VT, PT, int16_t>), dim3(m.csr_blocks), dim3(kBlock), 0, s,
+                           m.sl_lines, m.nslices, m.sl_off, m.sl_d16, val, x, y,
+                           PANEL ? m.pn_slot_target : nullptr, PANEL ? parked_buf(m, c) : nullptr,
+                           PANEL ? m.pn_first_parked : 0, sig_part, c.st);
     else
         hipLaunchKernelGGL((k_spmv_slices<PANEL, S, NT, VT, PT, int32_t>), dim3(m.csr_blocks), dim3(kBlock), 0, s,
                            m.sl_lines, m.nslices, m.sl_off, m.sl_col, val, x, y,

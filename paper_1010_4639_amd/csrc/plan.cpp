@@ -273,9 +273,11 @@ static int slice_mode()
     return std::strcmp(e, "slices") == 0 ? 1 : std::strcmp(e, "rows") == 0 ? -1 : 0;
 }
 
-// 16-bit column offsets of CSR slices (plan.h) when every column is within
-// 32767 of its row; experiments: CGMI_COL16=0 keeps 32-bit columns.
-static void plan_col16(Plan &p)
+// 16-bit column offsets of CSR slices or CSC panel-slot slices (plan.h) when
+// every column is within 32767 of the row its line adds to (line_row: the
+// row of each line; null: the line itself, CSR); experiments: CGMI_COL16=0
+// keeps 32-bit columns.
+static void plan_col16(Plan &p, const int32_t *line_row)
 {
     if (const char *e = std::getenv("CGMI_COL16"))
         if (std::strcmp(e, "0") == 0)
@@ -289,7 +291,8 @@ static void plan_col16(Plan &p)
                 const int64_t q = p.sl_off[sl] + slice_position(k, lane, w);
                 if (p.sl_col[q] < 0)
                     continue;
-                const int64_t d = (int64_t)p.sl_col[q] - (sl * kSliceRows + lane);
+                const int64_t l = sl * kSliceRows + lane;
+                const int64_t d = (int64_t)p.sl_col[q] - (line_row ? line_row[l] : l);
                 if (d < -32767 || d > 32767)
                     return;
                 d16[q] = (int16_t)d;
@@ -304,7 +307,7 @@ static void plan_csr(Plan &p, const int32_t *ptr, const int32_t *idx)
     const double mean = (double)p.nnz / (double)n;
     const int mode = slice_mode();
     if (mode >= 0 && plan_slices(p, n, ptr, idx, nullptr, mode)) {
-        plan_col16(p);
+        plan_col16(p, nullptr);
         return;
     }
     if (mean <= kStreamMaxMeanRow) {
@@ -431,7 +434,8 @@ static int plan_panels(Plan &p, const int32_t *ptr, const int32_t *idx, std::str
     p.max_lines = 0;
     const int mode = slice_mode();
     if (mode >= 0)
-        plan_slices(p, ns, p.pn_slot_ptr.data(), p.pn_col.data(), p.pn_src.data(), mode);
+        if (plan_slices(p, ns, p.pn_slot_ptr.data(), p.pn_col.data(), p.pn_src.data(), mode))
+            plan_col16(p, p.pn_slot_target.data());
     return CG_OK;
 }
 

@@ -65,11 +65,12 @@
 // sorting and two-entry packing: for a stencil-like matrix the lanes of one
 // load read neighbouring x entries, so the gather of x becomes a
 // near-contiguous load.  Chosen when the padding stays small; each line is
-// still summed left to right by one lane.  CSR rows whose columns all lie
-// within 32767 of the row (any banded numbering, e.g. a 3D grid numbered
-// lexicographically up to 181 x 181 nodes a plane) store each column as its
-// 16-bit offset from the row (-32768 = padding) instead of the 32-bit index:
-// 10 instead of 12 bytes per FP64 entry, 6 instead of 8 per FP32 one.
+// still summed left to right by one lane.  When every column lies within
+// 32767 of the row its line adds to (the CSR row, or the CSC slot's target
+// row; any banded numbering, e.g. a 3D grid numbered lexicographically up to
+// 181 x 181 nodes a plane) each column is stored as its 16-bit offset from
+// that row (-32768 = padding) instead of the 32-bit index: 10 instead of 12
+// bytes per FP64 entry, 6 instead of 8 per FP32 one.
 #pragma once
 
 #include <cstdint>
@@ -159,7 +160,7 @@ struct Plan {
     std::vector<int32_t> sl_off;          // [slices + 1] first position of each slice (multiple of 64)
     std::vector<int32_t> sl_src;          // [positions] caller entry (0-based) at each position, -1 = padding
     std::vector<int32_t> sl_col;          // [positions] column at each position, -1 = padding
-    std::vector<int16_t> sl_d16;          // CSR, banded: column - row at each position, kPad16 = padding (else empty)
+    std::vector<int16_t> sl_d16;          // banded: column - (row of the line) at each position, kPad16 = padding (else empty)
     // scatter formats
     int nblocks = 0, ncolors = 0, max_entries = 0, max_lines = 0, max_slots = 0;
     std::vector<ScatterBlock> blocks;     // by block id

@@ -123,7 +123,7 @@ def test_csr_layout_choice(monkeypatch):
     st, stats = cgmi.cg_analyze(cgmi.CG_FMT_CSC, s.n, s.rowptr, s.col, s.val)
     st2, P = cgmi.cg_analyze_panels(s.n, s.rowptr, s.col)
     pos, ns = _slice_positions(P["slot_ptr"])
-    assert st == 0 and stats["slices"] == 1 and stats["spmv_blocks"] == min((ns + 3) // 4, 8192)
+    assert st == 0 and stats["slices"] == 2 and stats["spmv_blocks"] == min((ns + 3) // 4, 8192)
     assert s.nnz <= pos <= 1.125 * s.nnz
     # symmetric CSR: sliced blocks when no stored line has more than 8
     # entries (FEM upper triangle: the diagonal and 7 neighbours at most)
