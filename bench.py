@@ -60,7 +60,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--mode", default="bench", choices=("bench", "counters", "parse-counters"))
+    ap.add_argument("--mode", default="bench", choices=("bench", "counters", "parse-counters", "summarize-trace"))
     ap.add_argument("--workload", default="fem160")
     ap.add_argument("--format", default="csr", choices=("csr", "symcsr", "csc"))
     ap.add_argument("--tol", type=float, default=1e-10)
@@ -73,6 +73,7 @@ def parse():
     ap.add_argument("--loop-systems", type=int, default=256, help="batch extra: systems in the loop of single solves")
     ap.add_argument("--formats", default="csr,symcsr,csc", help="counters mode: formats to run")
     ap.add_argument("--counter-dirs", default="", help="parse-counters: FETCH_SIZE run dir,WRITE_SIZE run dir")
+    ap.add_argument("--trace-dir", default="", help="summarize-trace: a rocprofv3 --kernel-trace --stats output dir")
     a = ap.parse_args()
     a.extras = set(EXTRAS) if a.extras == "all" else set() if a.extras == "none" else set(a.extras.split(","))
     return a
@@ -415,6 +416,52 @@ def counters_mode(a):
     print(json.dumps(out), flush=True)
 
 
+def short_kernel_name(k):
+    """A profiler kernel name without namespaces and argument list."""
+    k = k.replace("void ", "").replace("cgmi::", "").replace("(anonymous namespace)::", "")
+    depth = 0
+    for i, ch in enumerate(k):
+        if ch == "<":
+            depth += 1
+        elif ch == ">":
+            depth -= 1
+        elif ch == "(" and depth == 0:
+            return k[:i]
+    return k
+
+
+def summarize_trace(a):
+    """Markdown tables from a rocprofv3 run: its --stats summary per kernel,
+    and per kernel and grid size the launches and median / mean duration
+    from the kernel trace (raw trace files are not kept)."""
+    stats = glob.glob(os.path.join(a.trace_dir, "**", "*kernel_stats.csv"), recursive=True)
+    trace = glob.glob(os.path.join(a.trace_dir, "**", "*kernel_trace.csv"), recursive=True)
+    lines = []
+    for f in stats:
+        with open(f) as fh:
+            rows = list(csv.DictReader(fh))
+        lines += ["## rocprofv3 --stats (kernel_stats.csv)", "",
+                  "| kernel | calls | avg us | min us | max us | total ms | % |", "|---|---|---|---|---|---|---|"]
+        for r in rows[:25]:
+            lines.append(f"| `{short_kernel_name(r['Name'])}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.2f} | "
+                         f"{float(r['MinNs']) / 1e3:.2f} | {float(r['MaxNs']) / 1e3:.2f} | "
+                         f"{float(r['TotalDurationNs']) / 1e6:.1f} | {float(r['Percentage']):.1f} |")
+        lines.append("")
+    for f in trace:
+        per = {}
+        with open(f) as fh:
+            for r in csv.DictReader(fh):
+                key = (short_kernel_name(r["Kernel_Name"]), int(r.get("Grid_Size_X") or r.get("Grid_Size") or 0))
+                per.setdefault(key, []).append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+        lines += ["## Per kernel and grid size (work-items), from the kernel trace", "",
+                  "| kernel | grid | launches | median us | mean us | total ms |", "|---|---|---|---|---|---|"]
+        for (k, g), v in sorted(per.items(), key=lambda kv: -sum(kv[1]))[:25]:
+            lines.append(f"| `{k}` | {g} | {len(v)} | {statistics.median(v):.2f} | {statistics.mean(v):.2f} | "
+                         f"{sum(v) / 1e3:.1f} |")
+        lines.append("")
+    print("\n".join(lines))
+
+
 def parse_counters(a):
     """Per-launch HBM bytes of each format's product from a FETCH_SIZE run and
     a WRITE_SIZE run of `--mode counters` (rocprofv3 counter_collection.csv),
@@ -464,6 +511,8 @@ def main():
         sys.exit(2)
     if a.mode == "parse-counters":
         return parse_counters(a)
+    if a.mode == "summarize-trace":
+        return summarize_trace(a)
     if a.mode == "counters":
         return counters_mode(a)
     import numpy as np
