@@ -74,6 +74,8 @@ def parse():
     ap.add_argument("--formats", default="csr,symcsr,csc", help="counters mode: formats to run")
     ap.add_argument("--counter-dirs", default="", help="parse-counters: FETCH_SIZE run dir,WRITE_SIZE run dir")
     ap.add_argument("--trace-dir", default="", help="summarize-trace: a rocprofv3 --kernel-trace --stats output dir")
+    ap.add_argument("--windows", default="", help="summarize-trace: first,last kernel name prefixes of the solve "
+                    "windows whose idle time to report (e.g. k_binit_vec,k_bfinish)")
     a = ap.parse_args()
     a.extras = set(EXTRAS) if a.extras == "all" else set() if a.extras == "none" else set(a.extras.split(","))
     return a
@@ -426,8 +428,44 @@ def short_kernel_name(k):
         elif ch == ">":
             depth -= 1
         elif ch == "(" and depth == 0:
-            return k[:i]
-    return k
+            k = k[:i]
+            break
+    return k if len(k) <= 90 else k[:87] + "..."
+
+
+def window_idle(trace_csv, first, last):
+    """Per window from a launch of `first` to the next launch of `last`: wall
+    time, time with at least one kernel running, and the rest (launch gaps)."""
+    ev = []
+    with open(trace_csv) as fh:
+        for r in csv.DictReader(fh):
+            ev.append((int(r["Start_Timestamp"]), int(r["End_Timestamp"]), short_kernel_name(r["Kernel_Name"])))
+    ev.sort()
+    out = ["## Solve windows (" + first + " ... " + last + ")", "",
+           "| window | launches | wall ms | kernel-busy ms | idle % | largest gap us |", "|---|---|---|---|---|---|"]
+    i, w = 0, 0
+    while i < len(ev):
+        if not ev[i][2].startswith(first):
+            i += 1
+            continue
+        j = i
+        while j < len(ev) and not ev[j][2].startswith(last):
+            j += 1
+        if j == len(ev):
+            break
+        seg = ev[i:j + 1]
+        busy, end, gap = 0, seg[0][0], 0
+        for s0, e0, _ in seg:
+            if s0 > end:
+                gap = max(gap, s0 - end)
+            busy += max(0, e0 - max(s0, end))
+            end = max(end, e0)
+        wall = end - seg[0][0]
+        w += 1
+        out.append(f"| {w} | {len(seg)} | {wall / 1e6:.2f} | {busy / 1e6:.2f} | {100 * (wall - busy) / wall:.3f} | "
+                   f"{gap / 1e3:.1f} |")
+        i = j + 1
+    return out + [""]
 
 
 def summarize_trace(a):
@@ -453,6 +491,8 @@ def summarize_trace(a):
             for r in csv.DictReader(fh):
                 key = (short_kernel_name(r["Kernel_Name"]), int(r.get("Grid_Size_X") or r.get("Grid_Size") or 0))
                 per.setdefault(key, []).append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+        if a.windows:
+            lines += window_idle(f, *a.windows.split(","))
         lines += ["## Per kernel and grid size (work-items), from the kernel trace", "",
                   "| kernel | grid | launches | median us | mean us | total ms |", "|---|---|---|---|---|---|"]
         for (k, g), v in sorted(per.items(), key=lambda kv: -sum(kv[1]))[:25]:

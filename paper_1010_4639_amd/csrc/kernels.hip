@@ -10,6 +10,8 @@
 #include "devutil.h"
 
 #include <cmath>
+#include <cstdlib>
+#include <cstring>
 
 namespace cgmi {
 
@@ -1500,10 +1502,14 @@ void spmv_any(const DevMatrix &m, const VT *val, const PT *x, double *y, double 
     if (m.n == 0)
         return;
     if (m.slices) {
-        // two slices per wave at a time once the waves average 1.5 or more, for
-        // FP64 values (160^3: 163 -> 158 us; the FP32 product of mixed
-        // precision measured slower that way, 150 -> 209 us, and keeps one)
-        const bool two = sizeof(VT) == 8 && 2 * (int64_t)m.nslices >= (int64_t)3 * kWaves * m.csr_blocks;
+        // two slices per wave at a time once the waves average 1.5 or more
+        // (160^3 CSR: FP64 132.8 -> 128.5 us per product; the FP32 product of
+        // mixed precision gains too, the mixed solve 72.5 -> 71.4 ms)
+        static const bool two_knob = [] { // experiments: CGMI_SLICE_TWO=0, one slice at a time
+            const char *e = std::getenv("CGMI_SLICE_TWO");
+            return !(e && std::strcmp(e, "0") == 0);
+        }();
+        const bool two = two_knob && 2 * (int64_t)m.nslices >= (int64_t)3 * kWaves * m.csr_blocks;
         if (m.panel && two)
             slices_launch<true, 2>(m, slice_vals(m, val), x, y, sig_part, c, s);
         else if (m.panel)

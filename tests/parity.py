@@ -135,3 +135,53 @@ def load_reference(name):
 
 def sha(a):
     return hashlib.sha256(np.ascontiguousarray(a).tobytes()).hexdigest()
+
+
+FMT_NAMES = {0: "CSR", 1: "symmetric CSR", 2: "CSC"}
+
+
+def records_markdown(path):
+    """The parity records of one GPU test run (CGMI_PARITY_RECORD) as
+    markdown tables: FP64 CG against the oracle, the full-size solves against
+    the stored oracle run, mixed precision, and a summary of the batched
+    pairs."""
+    rows = [json.loads(line) for line in open(path)]
+    fmt = lambda v: "–" if v is None else (f"{v:.3g}" if isinstance(v, float) else str(v))
+    out = ["| case | format | iters GPU / oracle | 2-norm diff | bar | energy-norm diff | true relres |",
+           "|---|---|---|---|---|---|---|"]
+    for r in rows:
+        if "err2" in r and "bar2" in r and not r["test"].startswith(("batch", "mixed")):
+            out.append(f"| {r['test']} | {FMT_NAMES.get(r['fmt'], r['fmt'])} | {r.get('iters')} / "
+                       f"{r.get('oracle_iters')} | {fmt(r['err2'])} | {fmt(r['bar2'])} | {fmt(r.get('errA'))} | "
+                       f"{fmt(r.get('relres_true'))} |")
+    out += ["", "Full-size solves against the stored serial oracle run (4096 sampled entries; errors against "
+            "x_true over all entries):", "",
+            "| case | sampled 2-norm diff | bar | energy-norm error vs x_true (oracle) | 2-norm error vs x_true "
+            "(oracle) | iters GPU / oracle |", "|---|---|---|---|---|---|"]
+    for r in rows:
+        if "err2_sampled" in r:
+            bar = "not asserted (mixed)" if "mixed" in r["test"] else fmt(r["bar2"])
+            out.append(f"| {r['test']} | {fmt(r['err2_sampled'])} | {bar} | {fmt(r['errA_vs_true'])} "
+                       f"({fmt(r['oracle_errA_vs_true'])}) | {fmt(r['err2_vs_true'])} ({fmt(r['oracle_err2_vs_true'])}) "
+                       f"| {fmt(r.get('iters'))} / {fmt(r.get('oracle_iters'))} |")
+    out += ["", "Mixed precision (refinement stops on the true residual; energy-norm difference to the FP64 "
+            "oracle, 2-norm errors against x_true):", "",
+            "| case | format | energy-norm diff | 2-norm diff | 2-norm error vs x_true (oracle's) | inner / outer |",
+            "|---|---|---|---|---|---|"]
+    for r in rows:
+        if r["test"].startswith("mixed") and "errA" in r:
+            out.append(f"| {r['test']} | {FMT_NAMES.get(r['fmt'], r['fmt'])} | {fmt(r['errA'])} | {fmt(r['err2'])} | "
+                       f"{fmt(r['err2_vs_true'])} ({fmt(r['oracle_err2_vs_true'])}) | {r.get('inner_iters')} / "
+                       f"{r.get('outer')} |")
+    batch = [r for r in rows if r["test"].startswith("batch")]
+    if batch:
+        worst = max(batch, key=lambda r: r.get("err2", 0.0) / max(r.get("bar2", 1.0), 1e-300))
+        out += ["", f"Batched: {len(batch)} (system, right-hand side) pairs against single oracle solves; worst "
+                f"2-norm diff / bar: {fmt(worst.get('err2'))} / {fmt(worst.get('bar2'))} ({worst['test']}); "
+                f"largest energy-norm diff {fmt(max(r.get('errA', 0.0) for r in batch))}."]
+    return "\n".join(out)
+
+
+if __name__ == "__main__":
+    import sys
+    print(records_markdown(sys.argv[1]))
