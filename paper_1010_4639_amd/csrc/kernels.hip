@@ -1082,7 +1082,7 @@ __global__ __launch_bounds__(kBlock) void k_update_r(int n, int chunk, double *_
 // kernel reads those two fields).
 // PT: storage type of p (double; float for the inner solves of mixed
 // precision, where p is rounded to FP32 after the FP64 update).
-template <class PT>
+template <class PT, int PPT>
 __global__ __launch_bounds__(kBlock) void k_update_xp(int n, int chunk, double *__restrict__ x,
                                                       PT *__restrict__ p, const double *__restrict__ r,
                                                       DevState *st, const double *__restrict__ rho_part,
@@ -1096,7 +1096,7 @@ __global__ __launch_bounds__(kBlock) void k_update_xp(int n, int chunk, double *
     const int blk = xcd_remap(blockIdx.x, gridDim.x);
     const int i0 = blk * chunk, i1 = min(n, i0 + chunk);
     const int t = threadIdx.x;
-    double part[kPartPerThread];
+    double part[PPT];
     partials_load(rho_part, n_rho, part);
     double pv[kPre], xv[kPre], rv[kPre];
 #pragma unroll
@@ -1566,10 +1566,13 @@ void launch_update_r(const DevMatrix &m, double *r, const double *q, DevState *s
 {
     static_assert(kMaxSliceWgs <= 4 * kPartPerThread * kBlock, "slice partials fit four times the registers");
     // slices: up to kMaxSliceWgs dot partials (one slice per wavefront); the
-    // r update then holds 16 or 32 of them per thread (it runs at ~4 waves
-    // per SIMD anyway, so the registers cost no occupancy that matters)
+    // r update then holds up to 32 of them per thread
     const int nsig = m.spmv_blocks();
-    const int ppt = nsig <= kPartPerThread * kBlock ? 1 : nsig <= 2 * kPartPerThread * kBlock ? 2 : 4;
+    // partials per thread: the smallest power of two that covers nsig (each
+    // is a load, also past nsig: they are read unguarded, at a clamped index)
+    int ppt = 1;
+    while (ppt * kBlock < nsig)
+        ppt *= 2;
     RowPass g;
     g.rs_ptr = m.rs_ptr;
     g.rs_idx = m.rs_idx;
@@ -1578,16 +1581,17 @@ void launch_update_r(const DevMatrix &m, double *r, const double *q, DevState *s
     const int mode = rows_deferred && m.row_pass() ? (m.panel ? 2 : m.compact ? 3 : 1) : 0;
     const dim3 grid(m.vec_blocks), blk(kBlock);
 #define CGMI_UPDATE_R(G, P)                                                                                  \
-    hipLaunchKernelGGL((k_update_r<G, P * kPartPerThread>), grid, blk, 0, s, m.n, m.vec_chunk, r, q, st, sig_part, \
-                       nsig, rho_part, g)
+    hipLaunchKernelGGL((k_update_r<G, P>), grid, blk, 0, s, m.n, m.vec_chunk, r, q, st, sig_part, nsig, rho_part, g)
 #define CGMI_UPDATE_R_PPT(G)                                                                                 \
     do {                                                                                                     \
-        if (ppt == 1)                                                                                        \
-            CGMI_UPDATE_R(G, 1);                                                                             \
-        else if (ppt == 2)                                                                                   \
-            CGMI_UPDATE_R(G, 2);                                                                             \
-        else                                                                                                 \
-            CGMI_UPDATE_R(G, 4);                                                                             \
+        switch (ppt) {                                                                                       \
+        case 1: CGMI_UPDATE_R(G, 1); break;                                                                  \
+        case 2: CGMI_UPDATE_R(G, 2); break;                                                                  \
+        case 4: CGMI_UPDATE_R(G, 4); break;                                                                  \
+        case 8: CGMI_UPDATE_R(G, 8); break;                                                                  \
+        case 16: CGMI_UPDATE_R(G, 16); break;                                                                \
+        default: CGMI_UPDATE_R(G, 32); break;                                                                \
+        }                                                                                                    \
     } while (0)
     if (mode == 3)
         CGMI_UPDATE_R_PPT(3);
@@ -1601,18 +1605,37 @@ void launch_update_r(const DevMatrix &m, double *r, const double *q, DevState *s
 #undef CGMI_UPDATE_R
 }
 
+// x/p update with PPT partials per thread: the smallest power of two that
+// covers the vector kernels' workgroups
+template <class PT>
+void update_xp_launch(const DevMatrix &m, double *x, PT *p, const double *r, DevState *st, const double *rho_part,
+                      hipStream_t s)
+{
+    static_assert(kMaxVecBlocks <= 8 * kBlock, "vector partials fit eight per thread");
+    const dim3 grid(m.vec_blocks), blk(kBlock);
+#define CGMI_UPDATE_XP(P)                                                                                    \
+    hipLaunchKernelGGL((k_update_xp<PT, P>), grid, blk, 0, s, m.n, m.vec_chunk, x, p, r, st, rho_part, m.vec_blocks)
+    if (m.vec_blocks <= kBlock)
+        CGMI_UPDATE_XP(1);
+    else if (m.vec_blocks <= 2 * kBlock)
+        CGMI_UPDATE_XP(2);
+    else if (m.vec_blocks <= 4 * kBlock)
+        CGMI_UPDATE_XP(4);
+    else
+        CGMI_UPDATE_XP(8);
+#undef CGMI_UPDATE_XP
+}
+
 void launch_update_xp(const DevMatrix &m, double *x, double *p, const double *r, DevState *st,
                       const double *rho_part, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_update_xp<double>, dim3(m.vec_blocks), dim3(kBlock), 0, s, m.n, m.vec_chunk, x, p, r, st,
-                       rho_part, m.vec_blocks);
+    update_xp_launch(m, x, p, r, st, rho_part, s);
 }
 
 void launch_update_xp32(const DevMatrix &m, double *x, float *p, const double *r, DevState *st,
                         const double *rho_part, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_update_xp<float>, dim3(m.vec_blocks), dim3(kBlock), 0, s, m.n, m.vec_chunk, x, p, r, st,
-                       rho_part, m.vec_blocks);
+    update_xp_launch(m, x, p, r, st, rho_part, s);
 }
 
 void launch_mx_init(const DevMatrix &m, const double *r_out, double *rh, float *p, double *c, double *rho_part,

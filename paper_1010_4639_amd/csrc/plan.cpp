@@ -258,7 +258,10 @@ static bool plan_slices(Plan &p, int64_t nl, const int32_t *seg_ptr, const int32
     // one slice per wavefront up to kMaxSliceWgs workgroups, then each wave
     // takes several (contiguous per workgroup)
     const int64_t g = (ns + kWavesPerBlock - 1) / kWavesPerBlock;
-    p.csr_blocks = (int)std::max<int64_t>(1, std::min<int64_t>(g, kMaxSliceWgs));
+    int64_t cap = kMaxSliceWgs;
+    if (const char *e = std::getenv("CGMI_SLICE_WGS")) // experiments: fewer workgroups (dot partials)
+        cap = std::max<int64_t>(1, std::min<int64_t>(cap, std::atoll(e)));
+    p.csr_blocks = (int)std::max<int64_t>(1, std::min<int64_t>(g, cap));
     p.csr_rows_per_block = 0;
     return true;
 }
