@@ -41,6 +41,10 @@ struct cg_handle {
     size_t dev_bytes = 0; // sum of the allocations
     double *r = nullptr, *p = nullptr, *q = nullptr, *xw = nullptr;
     double *bp = nullptr; // b in the device row order (renumbered plans)
+    // two kernels per CG iteration (small CSR-slice or compact plans): the
+    // product forms the direction, which alternates between p and p2
+    bool fused = false;
+    double *p2 = nullptr;
     double *sig = nullptr, *sig_spmv = nullptr, *rho = nullptr, *bb = nullptr;
     DevState *st = nullptr;
     DevState *host_st = nullptr; // pinned, 2 entries
@@ -312,7 +316,7 @@ int upload_all(cg_handle *h, const std::vector<int32_t> &ptr0, const std::vector
         m.scatter_wgs = p.scatter_wgs();
         if (h->mixed && (st = dalloc(h, &m.ss_val32, np)) != CG_OK)
             return st;
-    } else if (p.format != kCsr && n > 0) {
+    } else if (p.format != kCsr && !p.sym_expanded && n > 0) {
         // device arrays in colour order: the blocks of one colour, and their
         // write slots, are contiguous
         const int nb = p.nblocks;
@@ -416,6 +420,17 @@ int upload_all(cg_handle *h, const std::vector<int32_t> &ptr0, const std::vector
     if ((st = dalloc(h, &h->r, nv)) != CG_OK || (st = dalloc(h, &h->p, nv)) != CG_OK ||
         (st = dalloc(h, &h->q, nv)) != CG_OK || (st = dalloc(h, &h->xw, nv)) != CG_OK)
         return st;
+    // Two kernels per iteration where launches, not bytes, bound the
+    // iteration: vector kernels of at most 256 workgroups (n <= 65 536).
+    // There every product workgroup reducing the r'r partials and gathering
+    // r and p costs less than the third launch; on large systems it costs
+    // more.  Experiments: CGMI_FUSED=0 / 1 (1: wherever the plan allows).
+    bool fuse = p.vec_blocks <= kBlock;
+    if (const char *e = std::getenv("CGMI_FUSED"))
+        fuse = std::strcmp(e, "0") != 0;
+    h->fused = fuse && n > 0 && ((m.slices && !m.panel) || m.compact);
+    if (h->fused && (st = dalloc(h, &h->p2, nv)) != CG_OK)
+        return st;
     const size_t ns = (size_t)std::max(1, std::max(p.spmv_blocks(), p.vec_blocks));
     if ((st = dalloc(h, &h->sig, ns)) != CG_OK || (st = dalloc(h, &h->sig_spmv, ns)) != CG_OK ||
         (st = dalloc(h, &h->rho, ns)) != CG_OK || (st = dalloc(h, &h->bb, ns)) != CG_OK ||
@@ -477,13 +492,25 @@ int scatter_entries_override()
 }
 
 // One CG iteration on the handle's vectors, in CG (gated) mode.
-void enqueue_iteration(cg_handle *h, hipStream_t s)
+void enqueue_iteration(cg_handle *h, hipStream_t s, int parity)
 {
     IterCtx c;
     c.st = h->st;
     c.rho_part = h->rho;
     c.n_rho = h->dm.vec_blocks;
     c.defer_rows = true;
+    if (h->fused) {
+        // product with the direction update (p_(k-1) in one buffer, p_k
+        // written to the other), then the r update
+        c.fused = true;
+        c.pold = parity ? h->p2 : h->p;
+        c.pnew = parity ? h->p : h->p2;
+        c.r = h->r;
+        c.x = h->xw;
+        launch_spmv(h->dm, c.pold, h->q, h->sig, c, s);
+        launch_update_r(h->dm, h->r, h->q, h->st, h->sig, h->rho, s, true, true);
+        return;
+    }
     launch_spmv(h->dm, h->p, h->q, h->sig, c, s);
     launch_update_r(h->dm, h->r, h->q, h->st, h->sig, h->rho, s, true);
     launch_update_xp(h->dm, h->xw, h->p, h->r, h->st, h->rho, s);
@@ -526,13 +553,18 @@ int build_graph_generic(cg_handle *h, bool mixed)
     if (mixed)
         if (const char *e = std::getenv("CGMI_MIXED_BATCH"))
             nb = std::max(1, std::atoi(e));
+    const bool fused = !mixed && h->fused;
+    if (fused) // the directions alternate between two buffers: an even count
+        nb += nb & 1;
     for (int i = 0; i < nb; ++i) {
         if (mixed)
             enqueue_iteration32(h, h->capture);
         else
-            enqueue_iteration(h, h->capture);
+            enqueue_iteration(h, h->capture, i & 1);
     }
-    launch_check(h->dm, mixed ? h->st_in : h->st, h->rho, h->capture);
+    // (the fused iteration records its stops in its own r update)
+    if (!fused)
+        launch_check(h->dm, mixed ? h->st_in : h->st, h->rho, h->capture);
     hipError_t e = hipStreamEndCapture(h->capture, &g);
     if (e != hipSuccess)
         return hip_fail(h->err, e, "hipStreamEndCapture");
@@ -1003,6 +1035,8 @@ int cg_solve(cg_handle *h, const double *b, double *x, double tol, int32_t maxit
     launch_spmv(h->dm, x0, h->q, h->sig_spmv, IterCtx{}, s);
     launch_init_vec(h->dm, bi, x0, h->q, h->r, h->p, h->xw, h->rho, h->bb, s);
     launch_init_state(h->dm, h->st, h->bb, h->rho, tol, maxit, s);
+    if (h->fused) // the first fused step forms p_0 = r_0 + beta * 0
+        launch_fill(n, h->p, 0.0, s);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess)
         return done(hip_fail(h->err, e, "launch"));

@@ -46,6 +46,24 @@ __device__ __forceinline__ double group_sum(double v)
     return v; // butterfly: every lane of the group holds the same bits
 }
 
+// Sum over a workgroup of TB threads (red: TB / 64 entries); every thread
+// returns the same bits.  Waves are added in index order, so waves whose
+// threads all hold +0.0 leave the bits of the sum over the others unchanged.
+template <int TB>
+__device__ __forceinline__ double block_sum_n(double v, double *red)
+{
+    v = group_sum<64>(v);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0)
+        red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double t = red[0];
+#pragma unroll
+    for (int w = 1; w < TB / 64; ++w)
+        t += red[w];
+    return t;
+}
+
 // Sum over the workgroup; every thread returns the same bits.
 __device__ __forceinline__ double block_sum(double v, double *red)
 {

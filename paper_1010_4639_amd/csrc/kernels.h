@@ -135,6 +135,15 @@ struct IterCtx {
     // parked sums of a scatter product in this buffer instead of the
     // handle's (at least DevMatrix::part_doubles entries)
     double *part = nullptr;
+    // Two kernels per CG iteration (small systems): the product forms the
+    // search direction p = r + beta p_prev itself -- for every gathered
+    // column and for its own rows, which it stores in pnew -- and applies
+    // x += alpha p_prev to its own rows; beta and the stop decision come from
+    // the r update's partials (rho_part), which it reduces like the x/p
+    // update does.  Same arithmetic, same bits as three kernels.
+    bool fused = false;
+    const double *pold = nullptr, *r = nullptr;
+    double *pnew = nullptr, *x = nullptr;
 };
 
 // y = A x; writes spmv_blocks() partials of x'y into sig_part.
@@ -147,7 +156,7 @@ void launch_spmv32(const DevMatrix &m, const float *x, double *y, double *sig_pa
 // rows_deferred: q came from a product launched with defer_rows, so each
 // q_i is finished here from the parked slot sums first.
 void launch_update_r(const DevMatrix &m, double *r, const double *q, DevState *st, const double *sig_part,
-                     double *rho_part, hipStream_t s, bool rows_deferred = false);
+                     double *rho_part, hipStream_t s, bool rows_deferred = false, bool fused = false);
 // x += alpha p; p = r + beta p (unless converged) with beta = sum(rho_part) / rho.
 void launch_update_xp(const DevMatrix &m, double *x, double *p, const double *r, DevState *st,
                       const double *rho_part, hipStream_t s);

@@ -87,6 +87,73 @@ __device__ bool iter_gate(DevState *st)
     return false;
 }
 
+// Two kernels per iteration (IterCtx::fused): what the product needs besides
+// its matrix -- the previous direction, the residual, the vectors it writes,
+// and the r update's partials of r'r.
+struct FusedDir {
+    const double *pold = nullptr, *r = nullptr;
+    double *pnew = nullptr, *x = nullptr;
+    const double *rho_part = nullptr;
+    int n_rho = 0;
+};
+
+struct FusedStep {
+    bool xupd;    // this iteration's x += alpha p_prev is still to be applied
+    bool run;     // and the iteration goes on (product, new direction)
+    double alpha; // alpha of the previous iteration (0 before the first)
+    double beta;  // rho_k / rho_(k-1)
+};
+
+// Start of iteration k in the fused form: r'r of the current residual from
+// the r update's partials (fixed order: the bits the x/p update computes),
+// the unfused gate's decision (converged first, then maxit), and beta.
+// Workgroup 0 publishes r'r and the decision; the r update that follows
+// records a stop (no workgroup of this kernel reads those fields, and no
+// status changes here, so every workgroup applies the x update it owes).
+// TB: threads of the calling kernel's workgroup (red: TB / 64 entries); the
+// first kBlock threads hold the partials as the x/p update's threads do, the
+// others add +0.0, so the sum has the x/p update's bits.
+template <int TB>
+__device__ FusedStep fused_gate(DevState *st, const FusedDir &fd, double *red)
+{
+    const int status = st->status, k = st->k, maxit = st->maxit;
+    const double rho_prev = st->rho, alpha = st->alpha, tol_nb = st->tol_nb;
+    double sv = 0.0;
+    if (threadIdx.x < kBlock) {
+        double pv[kPartPerThread];
+        partials_load(fd.rho_part, fd.n_rho, pv);
+#pragma unroll
+        for (int j = 0; j < kPartPerThread; ++j)
+            if ((int)threadIdx.x + j * kBlock < fd.n_rho)
+                sv += pv[j];
+    }
+    const double rho = block_sum_n<TB>(sv, red);
+    FusedStep f{status == kRun, false, alpha, 0.0};
+    if (!f.xupd)
+        return f;
+    const int stop = sqrt(rho) <= tol_nb ? 1 : (k >= maxit ? 2 : 0);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        st->rho_next = rho;
+        st->conv_next = stop;
+    }
+    f.run = stop == 0;
+    f.beta = f.run ? rho / rho_prev : 0.0;
+    return f;
+}
+
+// p_k[c] = r[c] + beta p_(k-1)[c] for a gathered column (0 for padding):
+// the fused product's x operand, bit-identical to what the x/p update
+// stores.
+__device__ __forceinline__ double fused_dir(const FusedDir &fd, double beta, int c)
+{
+    // two guarded loads with nothing else in their branch (so neither waits
+    // there, and a wave with no column skips both), then the update outside:
+    // fma(beta, 0, 0) = 0 for padding
+    const double po = c >= 0 ? fd.pold[c] : 0.0;
+    const double rr = c >= 0 ? fd.r[c] : 0.0;
+    return fma(beta, po, rr);
+}
+
 // ------------------------------------------------------------------ CSR
 // W lanes per row (4..64), U rows per lane group in flight, rows of the
 // workgroup's contiguous range visited in passes of (256 / W) * U rows.
@@ -259,23 +326,39 @@ __global__ __launch_bounds__(kBlock) void k_spmv_csr_rows(int nrb, const int2 *_
 // panel slots; a colour-0 slot stores y[target], a colour-1 slot parks its
 // sum at part[target] for the row pass.  Fused epilogue: partial of x'y (linear in the line
 // sums, so x_target * sum per line).
-template <bool PANEL, int S, bool NT, class VT, class PT, class CT>
+// FUSED (CSR, FP64): the two-kernel iteration (FusedDir): x is unused, the
+// gathered operand is p_k formed from fd.pold and fd.r, and each line's row
+// gets its new direction and x update.
+template <bool PANEL, int S, bool NT, class VT, class PT, class CT, bool FUSED = false>
 __global__ __launch_bounds__(kBlock) void k_spmv_slices(int nl, int ns, const int32_t *__restrict__ off,
                                                         const CT *__restrict__ col, const VT *__restrict__ val,
                                                         const PT *__restrict__ x, double *__restrict__ y,
                                                         const int32_t *__restrict__ target, double *__restrict__ part,
-                                                        int first_parked, double *__restrict__ sig_part, DevState *st)
+                                                        int first_parked, double *__restrict__ sig_part, DevState *st,
+                                                        FusedDir fd = FusedDir{})
 {
 #pragma clang fp contract(off)
+    static_assert(!FUSED || (!PANEL && sizeof(PT) == 8), "the fused form is for FP64 CSR rows");
     // positions per round (values and gathered x stay in their stored type
     // until the multiply)
     constexpr int U = 8;
     __shared__ double red[kWaves];
     const int wg = xcd_remap(blockIdx.x, gridDim.x);
-    if (st != nullptr && !iter_gate(st))
-        return;
     const int s0 = (int)((int64_t)wg * ns / gridDim.x);
     const int s1 = (int)((int64_t)(wg + 1) * ns / gridDim.x);
+    FusedStep f{true, true, 0.0, 0.0};
+    if constexpr (FUSED) {
+        f = fused_gate<kBlock>(st, fd, red);
+        if (!f.run) {
+            // stopping: the x update this iteration owes, on this workgroup's rows
+            if (f.xupd)
+                for (int i = s0 * kSliceRows + (int)threadIdx.x; i < min(s1 * kSliceRows, nl); i += kBlock)
+                    fd.x[i] = fma(f.alpha, fd.pold[i], fd.x[i]);
+            return;
+        }
+    } else if (st != nullptr && !iter_gate(st)) {
+        return;
+    }
     const int lane = threadIdx.x & 63;
     double sig = 0.0;
     // S slices per wave at a time (sl, sl + kWaves, ...): their loads are
@@ -335,8 +418,12 @@ __global__ __launch_bounds__(kBlock) void k_spmv_slices(int nl, int ns, const in
 #pragma unroll
             for (int j = 0; j < S; ++j)
 #pragma unroll
-                for (int u = 0; u < U; ++u)
-                    xv[j][u] = gather0(x, c[j][u]);
+                for (int u = 0; u < U; ++u) {
+                    if constexpr (FUSED)
+                        xv[j][u] = fused_dir(fd, f.beta, c[j][u]);
+                    else
+                        xv[j][u] = gather0(x, c[j][u]);
+                }
 #pragma unroll
             for (int j = 0; j < S; ++j)
 #pragma unroll
@@ -351,7 +438,16 @@ __global__ __launch_bounds__(kBlock) void k_spmv_slices(int nl, int ns, const in
                     y[tg[j]] = a[j];
                 else
                     part[tg[j]] = a[j]; // parked by row: at most one colour-1 slot per row
-                sig = fma((double)x[tg[j]], a[j], sig);
+                if constexpr (FUSED) {
+                    // the row's new direction and the x update it owes
+                    const double po = fd.pold[l[j]];
+                    const double pk = fma(f.beta, po, fd.r[l[j]]);
+                    fd.pnew[l[j]] = pk;
+                    fd.x[l[j]] = fma(f.alpha, po, fd.x[l[j]]);
+                    sig = fma(pk, a[j], sig);
+                } else {
+                    sig = fma((double)x[tg[j]], a[j], sig);
+                }
             }
     }
     sig = block_sum(sig, red);
@@ -707,12 +803,16 @@ __global__ __launch_bounds__(kBlock) void k_scatter_slices(
 // owns those rows; nobody else stores them), the other slots park their sum
 // at its place in the by-row array of the row pass.  Fused epilogue: x'y as
 // sum_slots x_target * sum.
-template <int SU, bool NT, class VT, class PT>
+// FUSED (FP64): the two-kernel iteration (FusedDir), as in k_spmv_slices:
+// every x operand is p_k formed from fd.pold and fd.r, and each own line's
+// row gets its new direction and x update.
+template <int SU, bool NT, class VT, class PT, bool FUSED = false>
 __global__ __launch_bounds__(kCompactThreads) void k_scatter_compact(
     const int32_t *__restrict__ sidx, const VT *__restrict__ sval, const CompactBlock *__restrict__ blocks,
     int nblocks, const int32_t *__restrict__ slot_target, const uint16_t *__restrict__ seg,
     const uint16_t *__restrict__ rank, const int32_t *__restrict__ dest, const PT *__restrict__ x,
-    double *__restrict__ y, double *__restrict__ part, double *__restrict__ sig_part, DevState *st)
+    double *__restrict__ y, double *__restrict__ part, double *__restrict__ sig_part, DevState *st,
+    FusedDir fd = FusedDir{})
 {
 #pragma clang fp contract(off)
     constexpr int E = kStreamPerThread;
@@ -721,8 +821,13 @@ __global__ __launch_bounds__(kCompactThreads) void k_scatter_compact(
     __shared__ double sp[kCompactEntries];
     __shared__ __align__(16) uint16_t st16[kStarts];
     __shared__ double red[TB / 64];
-    if (st != nullptr && !iter_gate(st))
+    static_assert(!FUSED || sizeof(PT) == 8, "the fused form is FP64");
+    FusedStep f{true, true, 0.0, 0.0};
+    if constexpr (FUSED) {
+        f = fused_gate<TB>(st, fd, red);
+    } else if (st != nullptr && !iter_gate(st)) {
         return;
+    }
     const int t = threadIdx.x;
     // blocks of this XCD: one contiguous eighth; its workgroups take them in
     // turn (workgroup i of the XCD: blocks i, i + G, i + 2G, ...), so the
@@ -732,8 +837,21 @@ __global__ __launch_bounds__(kCompactThreads) void k_scatter_compact(
     const int xcd = blockIdx.x % nx, wi = blockIdx.x / nx;
     const int gx = ((int)gridDim.x - xcd + nx - 1) / nx;
     const int b1 = (int)((int64_t)(xcd + 1) * nblocks / nx);
+    const int bfirst = (int)((int64_t)xcd * nblocks / nx) + wi;
+    if constexpr (FUSED) {
+        if (!f.run) {
+            // stopping: the x update this iteration owes, on this workgroup's lines
+            if (f.xupd)
+                for (int b = bfirst; b < b1; b += gx) {
+                    const CompactBlock bk = blocks[b];
+                    if (t < bk.nl)
+                        fd.x[bk.line0 + t] = fma(f.alpha, fd.pold[bk.line0 + t], fd.x[bk.line0 + t]);
+                }
+            return;
+        }
+    }
     double sig = 0.0;
-    for (int b = (int)((int64_t)xcd * nblocks / nx) + wi; b < b1; b += gx) {
+    for (int b = bfirst; b < b1; b += gx) {
         const CompactBlock bk = blocks[b];
         const int nl = bk.nl, L = bk.len;
         const bool mine = t < nl;
@@ -788,16 +906,29 @@ __global__ __launch_bounds__(kCompactThreads) void k_scatter_compact(
             const int ps = matrix_load<NT>(dest + bk.park0 + min(max(s - nl, 0), max(npk - 1, 0)));
             pk[u] = parked ? ps : -1;
         }
-        // ---- gathers
-        const double xo = (double)gather0(x, mine ? line : -1);
-        double xg[E];
+        // ---- gathers (fused: p_k formed from the previous direction and r)
+        double xo, xg[E], xt[SU];
+        if constexpr (FUSED) {
+            xo = fused_dir(fd, f.beta, mine ? line : -1);
 #pragma unroll
-        for (int m = 0; m < E; ++m)
-            xg[m] = (double)gather0(x, c[m]);
-        double xt[SU];
+            for (int m = 0; m < E; ++m)
+                xg[m] = fused_dir(fd, f.beta, c[m]);
 #pragma unroll
-        for (int u = 0; u < SU; ++u)
-            xt[u] = t + u * TB < nl ? xo : (double)gather0(x, tg[u]);
+            for (int u = 0; u < SU; ++u)
+                xt[u] = t + u * TB < nl ? xo : fused_dir(fd, f.beta, tg[u]);
+            if (mine) { // the own line's new direction and the x update it owes
+                fd.pnew[line] = xo;
+                fd.x[line] = fma(f.alpha, fd.pold[line], fd.x[line]);
+            }
+        } else {
+            xo = (double)gather0(x, mine ? line : -1);
+#pragma unroll
+            for (int m = 0; m < E; ++m)
+                xg[m] = (double)gather0(x, c[m]);
+#pragma unroll
+            for (int u = 0; u < SU; ++u)
+                xt[u] = t + u * TB < nl ? xo : (double)gather0(x, tg[u]);
+        }
         // ---- slot starts to LDS (read after the barrier below)
         if (t < nchunk)
             *reinterpret_cast<uint4v *>(st16 + 8 * t) = sg0;
@@ -1020,8 +1151,11 @@ __device__ __forceinline__ void row_values(const double *__restrict__ q, const d
     }
 }
 
-// PPT: dot partials per thread (n_sig <= PPT * 256)
-template <int GATHER, int PPT>
+// PPT: dot partials per thread (n_sig <= PPT * 256).  FUSED: the r update
+// of the two-kernel iteration: r'r of the current residual is the one the
+// product published (rho_next), and a stop the product decided (conv_next)
+// is recorded here.
+template <int GATHER, int PPT, bool FUSED = false>
 __global__ __launch_bounds__(kBlock) void k_update_r(int n, int chunk, double *__restrict__ r,
                                                      const double *__restrict__ q, DevState *st,
                                                      const double *__restrict__ sig_part, int n_sig,
@@ -1031,7 +1165,8 @@ __global__ __launch_bounds__(kBlock) void k_update_r(int n, int chunk, double *_
     // the gate, the partials and the first vector elements are loaded
     // together (one memory round trip); nothing is stored before the gate
     const int status = st->status;
-    const double rho = st->rho;
+    const int stop = FUSED ? st->conv_next : 0;
+    const double rho = FUSED ? st->rho_next : st->rho;
     const int blk = xcd_remap(blockIdx.x, gridDim.x);
     const int i0 = blk * chunk, i1 = min(n, i0 + chunk);
     const int t = threadIdx.x;
@@ -1041,10 +1176,20 @@ __global__ __launch_bounds__(kBlock) void k_update_r(int n, int chunk, double *_
     row_values<GATHER>(q, r, g, n, i0 + t, i1, qv, rv);
     if (status != kRun)
         return;
-    const double sigma = partials_sum(pv, n_sig, red);
     const bool lead = blockIdx.x == 0 && t == 0;
+    if (FUSED && stop != 0) {
+        if (lead) {
+            st->rho = rho;
+            st->iters = st->k;
+            st->status = stop == 1 ? kConverged : kMaxit;
+        }
+        return;
+    }
+    const double sigma = partials_sum(pv, n_sig, red);
     if (!(sigma > 0.0) || !isfinite(sigma)) {
         if (lead) {
+            if (FUSED)
+                st->rho = rho;
             st->iters = st->k;
             st->sigma = sigma;
             st->status = kBreakdown;
@@ -1056,6 +1201,8 @@ __global__ __launch_bounds__(kBlock) void k_update_r(int n, int chunk, double *_
         st->alpha = alpha;
         st->sigma = sigma;
         st->k = st->k + 1;
+        if (FUSED)
+            st->rho = rho; // r'r of the residual this step starts from (the next beta's denominator)
     }
     double acc = 0.0;
 #pragma unroll
@@ -1396,10 +1543,37 @@ void scatter_slices_launch(const DevMatrix &m, const VT *val, const PT *x, doubl
                            m.rs_idx, m.has_c0, parked_buf(m, c), y, c.st);
 }
 
+inline FusedDir fused_dir_of(const IterCtx &c)
+{
+    FusedDir fd;
+    fd.pold = c.pold;
+    fd.r = c.r;
+    fd.pnew = c.pnew;
+    fd.x = c.x;
+    fd.rho_part = c.rho_part;
+    fd.n_rho = c.n_rho;
+    return fd;
+}
+
 template <int SU, class VT, class PT>
 void compact_launch(const DevMatrix &m, const VT *val, const PT *x, double *y, double *sig, const IterCtx &c,
                     hipStream_t s)
 {
+    if constexpr (sizeof(PT) == 8) {
+        if (c.fused) { // two kernels per iteration (the row pass stays with the r update)
+            if (m.matrix_cached)
+                hipLaunchKernelGGL((k_scatter_compact<SU, false, VT, PT, true>), dim3(m.scatter_wgs),
+                                   dim3(kCompactThreads), 0, s, m.ss_idx, sym_slice_vals(m, val), m.cblocks, m.nblocks,
+                                   m.slot_target, m.seg, m.cp_rank, m.cp_dest, x, y, parked_buf(m, c), sig, c.st,
+                                   fused_dir_of(c));
+            else
+                hipLaunchKernelGGL((k_scatter_compact<SU, true, VT, PT, true>), dim3(m.scatter_wgs),
+                                   dim3(kCompactThreads), 0, s, m.ss_idx, sym_slice_vals(m, val), m.cblocks, m.nblocks,
+                                   m.slot_target, m.seg, m.cp_rank, m.cp_dest, x, y, parked_buf(m, c), sig, c.st,
+                                   fused_dir_of(c));
+            return;
+        }
+    }
     if (m.matrix_cached)
         hipLaunchKernelGGL((k_scatter_compact<SU, false, VT, PT>), dim3(m.scatter_wgs), dim3(kCompactThreads), 0, s,
                            m.ss_idx,
@@ -1473,6 +1647,19 @@ template <bool PANEL, int S, bool NT, class VT, class PT>
 void slices_launch_nt(const DevMatrix &m, const VT *val, const PT *x, double *y, double *sig_part, const IterCtx &c,
                       hipStream_t s)
 {
+    if constexpr (!PANEL && sizeof(PT) == 8) {
+        if (c.fused) { // two kernels per iteration
+            if (m.sl_d16 != nullptr)
+                hipLaunchKernelGGL((k_spmv_slices<false, S, NT, VT, PT, int16_t, true>), dim3(m.csr_blocks),
+                                   dim3(kBlock), 0, s, m.sl_lines, m.nslices, m.sl_off, m.sl_d16, val, x, y, nullptr,
+                                   nullptr, 0, sig_part, c.st, fused_dir_of(c));
+            else
+                hipLaunchKernelGGL((k_spmv_slices<false, S, NT, VT, PT, int32_t, true>), dim3(m.csr_blocks),
+                                   dim3(kBlock), 0, s, m.sl_lines, m.nslices, m.sl_off, m.sl_col, val, x, y, nullptr,
+                                   nullptr, 0, sig_part, c.st, fused_dir_of(c));
+            return;
+        }
+    }
     if (m.sl_d16 != nullptr)
         hipLaunchKernelGGL((k_spmv_slices<PANEL, S, NT, VT, PT, int16_t>), dim3(m.csr_blocks), dim3(kBlock), 0, s,
                            m.sl_lines, m.nslices, m.sl_off, m.sl_d16, val, x, y,
@@ -1562,7 +1749,7 @@ void launch_spmv32(const DevMatrix &m, const float *x, double *y, double *sig_pa
 }
 
 void launch_update_r(const DevMatrix &m, double *r, const double *q, DevState *st, const double *sig_part,
-                     double *rho_part, hipStream_t s, bool rows_deferred)
+                     double *rho_part, hipStream_t s, bool rows_deferred, bool fused)
 {
     static_assert(kMaxSliceWgs <= 4 * kPartPerThread * kBlock, "slice partials fit four times the registers");
     // slices: up to kMaxSliceWgs dot partials (one slice per wavefront); the
@@ -1580,27 +1767,32 @@ void launch_update_r(const DevMatrix &m, double *r, const double *q, DevState *s
     g.part = m.part; // iterations use the handle's own buffer
     const int mode = rows_deferred && m.row_pass() ? (m.panel ? 2 : m.compact ? 3 : 1) : 0;
     const dim3 grid(m.vec_blocks), blk(kBlock);
-#define CGMI_UPDATE_R(G, P)                                                                                  \
-    hipLaunchKernelGGL((k_update_r<G, P>), grid, blk, 0, s, m.n, m.vec_chunk, r, q, st, sig_part, nsig, rho_part, g)
-#define CGMI_UPDATE_R_PPT(G)                                                                                 \
+#define CGMI_UPDATE_R(G, P, F)                                                                               \
+    hipLaunchKernelGGL((k_update_r<G, P, F>), grid, blk, 0, s, m.n, m.vec_chunk, r, q, st, sig_part, nsig, rho_part, \
+                       g)
+#define CGMI_UPDATE_R_PPT(G, F)                                                                              \
     do {                                                                                                     \
         switch (ppt) {                                                                                       \
-        case 1: CGMI_UPDATE_R(G, 1); break;                                                                  \
-        case 2: CGMI_UPDATE_R(G, 2); break;                                                                  \
-        case 4: CGMI_UPDATE_R(G, 4); break;                                                                  \
-        case 8: CGMI_UPDATE_R(G, 8); break;                                                                  \
-        case 16: CGMI_UPDATE_R(G, 16); break;                                                                \
-        default: CGMI_UPDATE_R(G, 32); break;                                                                \
+        case 1: CGMI_UPDATE_R(G, 1, F); break;                                                               \
+        case 2: CGMI_UPDATE_R(G, 2, F); break;                                                               \
+        case 4: CGMI_UPDATE_R(G, 4, F); break;                                                               \
+        case 8: CGMI_UPDATE_R(G, 8, F); break;                                                               \
+        case 16: CGMI_UPDATE_R(G, 16, F); break;                                                             \
+        default: CGMI_UPDATE_R(G, 32, F); break;                                                             \
         }                                                                                                    \
     } while (0)
-    if (mode == 3)
-        CGMI_UPDATE_R_PPT(3);
+    if (fused && mode == 3) // two kernels per iteration: compact blocks or CSR slices
+        CGMI_UPDATE_R_PPT(3, true);
+    else if (fused)
+        CGMI_UPDATE_R_PPT(0, true);
+    else if (mode == 3)
+        CGMI_UPDATE_R_PPT(3, false);
     else if (mode == 2)
-        CGMI_UPDATE_R_PPT(2);
+        CGMI_UPDATE_R_PPT(2, false);
     else if (mode == 1)
-        CGMI_UPDATE_R_PPT(1);
+        CGMI_UPDATE_R_PPT(1, false);
     else
-        CGMI_UPDATE_R_PPT(0);
+        CGMI_UPDATE_R_PPT(0, false);
 #undef CGMI_UPDATE_R_PPT
 #undef CGMI_UPDATE_R
 }

@@ -14,7 +14,7 @@ int64_t Plan::device_bytes() const
 {
     // slices: offsets + entry source, column (or 16-bit offset), value per position
     const int64_t sl = (int64_t)sl_off.size() * 4 + (int64_t)sl_src.size() * (4 + (sl_d16.empty() ? 4 : 2) + 8);
-    if (format == kCsr) // row-block starts or slices
+    if (format == kCsr || sym_expanded) // row-block starts or slices
         return (int64_t)csr_rb.size() * 4 + sl;
     if (panel && slices) // slices; slot targets; parked sums and flags by row
         return sl + (int64_t)pn_slot_target.size() * 4 + n * 9;
@@ -978,6 +978,51 @@ static bool plan_sym_compact(Plan &p, const int32_t *ptr, const int32_t *idx)
     return true;
 }
 
+// Symmetric CSR on a small system (vector kernels of at most 256
+// workgroups, n <= 65 536): there the product is bound by its launch and
+// its chain of dependent steps, not by the bytes the triangle saves, and the
+// scatter's mirror products through LDS and parked sums lengthen that chain.
+// The triangle is expanded into full rows -- an off-diagonal entry stored at
+// (i, j) and (j, i), both positions naming the caller's one entry -- and
+// sliced like CSR; row i's entries come in ascending column order (mirrored
+// ones first).  Experiments: CGMI_SYM_EXPAND=0 keeps the scatter plans.
+static bool plan_sym_expanded(Plan &p, const int32_t *ptr, const int32_t *idx)
+{
+    if (p.vec_blocks > kBlock)
+        return false;
+    if (const char *e = std::getenv("CGMI_SYM_EXPAND"))
+        if (std::strcmp(e, "0") == 0)
+            return false;
+    const int64_t n = p.n;
+    std::vector<int32_t> fptr((size_t)n + 1, 0);
+    for (int64_t i = 0; i < n; ++i)
+        for (int64_t k = ptr[i]; k < ptr[i + 1]; ++k) {
+            fptr[i + 1]++;
+            if (idx[k] != i)
+                fptr[idx[k] + 1]++;
+        }
+    for (int64_t i = 0; i < n; ++i)
+        fptr[i + 1] += fptr[i];
+    if (fptr[n] > INT32_MAX / 2)
+        return false;
+    std::vector<int32_t> fcol((size_t)fptr[n]), fsrc((size_t)fptr[n]), next(fptr.begin(), fptr.end() - 1);
+    for (int64_t i = 0; i < n; ++i)
+        for (int64_t k = ptr[i]; k < ptr[i + 1]; ++k) {
+            const int32_t j = idx[k];
+            fcol[next[i]] = j;
+            fsrc[next[i]++] = (int32_t)k;
+            if (j != i) {
+                fcol[next[j]] = (int32_t)i;
+                fsrc[next[j]++] = (int32_t)k;
+            }
+        }
+    if (!plan_slices(p, n, fptr.data(), fcol.data(), fsrc.data(), slice_mode()))
+        return false;
+    plan_col16(p, nullptr);
+    p.sym_expanded = true;
+    return true;
+}
+
 int build_plan(int fmt, int64_t n, const int32_t *ptr0, const int32_t *idx0, int target_entries, Plan &p,
                std::string &err)
 {
@@ -999,6 +1044,10 @@ int build_plan(int fmt, int64_t n, const int32_t *ptr0, const int32_t *idx0, int
         const int st = plan_panels(p, ptr0, idx0, err);
         p.cached = st == CG_OK && decide_cached(p);
         return st;
+    }
+    if (target_entries <= 0 && compact_allowed() && slice_mode() >= 0 && plan_sym_expanded(p, ptr0, idx0)) {
+        p.cached = decide_cached(p);
+        return CG_OK;
     }
     if (target_entries <= 0 && compact_allowed() && slice_mode() >= 0 && plan_sym_compact(p, ptr0, idx0)) {
         p.cached = decide_cached(p);

@@ -184,6 +184,10 @@ struct Plan {
     // symmetric CSR, compact blocks (plan.h); positions in ss_src / ss_idx,
     // contributions (local positions) in ss_tl, slots in slot_target / seg
     bool sym_compact = false;
+    // symmetric CSR on a small system: the triangle expanded into full rows
+    // and sliced like CSR (sl_src names the caller's entry of each position,
+    // an off-diagonal entry twice)
+    bool sym_expanded = false;
     std::vector<CompactBlock> cp_blocks;  // [nblocks] in block order
     std::vector<uint16_t> cp_rank;        // [8 n] LDS place of each entry's mirror product (0xffff: none)
     std::vector<int32_t> cp_perm;         // [n] block order: device row k is the caller's row cp_perm[k]

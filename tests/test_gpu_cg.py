@@ -196,6 +196,41 @@ def test_batch_size_does_not_change_bits(batch):
     assert np.array_equal(ref[0], cur[0]) and ref[1] == cur[1]
 
 
+@pytest.mark.parametrize("col16", ["1", "0"])
+@pytest.mark.parametrize("fmt", [CSR, SYM])
+def test_two_kernel_iteration_same_bits(monkeypatch, fmt, col16):
+    """Small systems run two kernels per iteration (the product forms the
+    search direction itself): the same arithmetic in the same order, so the
+    solution, the iteration count and every status match the three-kernel
+    iteration bit for bit -- converged, stopped by maxit, from x0 != 0, and
+    at a breakdown."""
+    import torch
+    monkeypatch.setenv("CGMI_COL16", col16)
+    s = W.fem_p1_system(14, 13, 12, nu_iron=1e-3, seed=11)
+    arrs = formats_of(s.rowptr, s.col, s.val)[fmt]
+    x0 = W.uniform_vector(s.n, seed=12)
+    n = 40
+    d = np.where(np.arange(n) % 3 == 2, -1.0, 2.0)  # indefinite: breaks down after a few steps
+    dptr, didx = np.arange(n + 1, dtype=np.int32), np.arange(n, dtype=np.int32)
+    bd = W.uniform_vector(n, seed=13)
+    out = {}
+    for fused in ("1", "0"):
+        monkeypatch.setenv("CGMI_FUSED", fused)
+        res = []
+        with cgmi.Solver(fmt, *arrs) as S:
+            for kw in (dict(tol=1e-10, maxit=5000), dict(tol=1e-14, maxit=37), dict(x0=to_dev(x0), tol=1e-9)):
+                x, info = S.solve(to_dev(s.b), kw.pop("x0", None), check=False, **kw)
+                res.append((x.cpu().numpy(), info["iters"], info["status"], info["relres"]))
+        with cgmi.Solver(fmt, dptr, didx, d) as S:
+            x, info = S.solve(to_dev(bd), check=False)
+            res.append((x.cpu().numpy(), info["iters"], info["status"], info["relres"]))
+        out[fused] = res
+    for (xa, ia, sa, ra), (xb, ib, sb, rb) in zip(out["1"], out["0"]):
+        assert np.array_equal(xa, xb) and ia == ib and sa == sb and ra == rb, (ia, ib, sa, sb, ra, rb)
+    assert [r[2] for r in out["1"]] == [cgmi.CG_OK, cgmi.CG_NOT_CONVERGED, cgmi.CG_OK, cgmi.CG_ERR_BREAKDOWN]
+    assert out["1"][1][1] == 37 and out["1"][3][1] > 0
+
+
 @pytest.mark.parametrize("fmt", [CSR, SYM, CSC])
 def test_deterministic(fmt):
     s = W.fem_p1_system(16, 15, 14, seed=6)

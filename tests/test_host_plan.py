@@ -518,3 +518,24 @@ def test_block_diagonal_helper():
     so, ptr, col, val = W.block_diagonal([(s1.rowptr, s1.col, s1.val), (s2.rowptr, s2.col, s2.val)])
     assert list(so) == [0, s1.n, s1.n + s2.n]
     assert ptr[-1] == s1.nnz + s2.nnz and col[ptr[s1.n]] >= s1.n
+
+
+@pytest.mark.sym_expanded
+def test_sym_expanded_plan_choice(monkeypatch):
+    # small symmetric systems (vector kernels of <= 256 workgroups): the
+    # triangle expanded into full rows, sliced like CSR -- the same positions
+    # and bytes as the CSR plan of the full matrix; larger ones keep the
+    # compact blocks; CGMI_SYM_EXPAND=0 keeps them on small ones too
+    s = W.fem_config("fem32x32x30")
+    up = W.upper_triangle(s.rowptr, s.col, s.val)
+    st, sym = cgmi.cg_analyze(cgmi.CG_FMT_SYM_CSR, s.n, *up)
+    st2, csr = cgmi.cg_analyze(cgmi.CG_FMT_CSR, s.n, s.rowptr, s.col, s.val)
+    assert st == st2 == 0 and sym["compact"] == 0 and sym["slices"] == 2 and sym["parked"] == 0
+    assert sym["plan_bytes"] == csr["plan_bytes"] and sym["spmv_blocks"] == csr["spmv_blocks"]
+    big = W.fem_p1_system(42, 42, 40, seed=3)
+    ub = W.upper_triangle(big.rowptr, big.col, big.val)
+    st, stats = cgmi.cg_analyze(cgmi.CG_FMT_SYM_CSR, big.n, *ub)
+    assert st == 0 and big.n > 65536 and stats["compact"] == 1
+    monkeypatch.setenv("CGMI_SYM_EXPAND", "0")
+    st, stats = cgmi.cg_analyze(cgmi.CG_FMT_SYM_CSR, s.n, *up)
+    assert st == 0 and stats["compact"] == 1
