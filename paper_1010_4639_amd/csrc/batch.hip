@@ -287,18 +287,32 @@ __global__ __launch_bounds__(kBlock) void k_bspmm(const WgDesc *__restrict__ wgs
     }
 }
 
+// Two-entry vectors for the paired loads of the slices.
+template <class T>
+struct Pair2 {
+    typedef T type __attribute__((ext_vector_type(2)));
+};
+
+// Column of a slice entry: as stored (int32_t, -1 = padding) or as the
+// 16-bit offset from its row (int16_t, kPad16 = padding).
+__device__ __forceinline__ int bcol_of(int32_t raw, int) { return raw; }
+__device__ __forceinline__ int bcol_of(int16_t raw, int row) { return raw == kPad16 ? -1 : row + raw; }
+
 // Q = A P for the R interleaved right-hand sides over the sliced layout (the
 // third schedule): each system's rows in slices of 64, lane l of a wave owns
-// row 64 s + l, and a slice stores the k-th entries of its rows contiguously
-// (padding: column -1).  The lanes of one load gather neighbouring rows of P
-// for a stencil-like matrix, each 8R bytes, so the gathers coalesce.  A row
-// is summed left to right from rounded products, the order of the LDS
-// schedule (same bits).  Waves of a workgroup take its slices in turn.
-template <int R, int U>
+// row 64 s + l, and a slice stores its rows' entries pairwise, k-th pair
+// first (entries 2j, 2j + 1 of lane l at off + 128 j + 2 l, the last entry of
+// an odd width at off + 64 (w - 1) + l; padding: column -1, or kPad16 for
+// CT = int16_t, columns stored as offsets from the row when every one is
+// within 32767).  The lanes of one load gather neighbouring rows of P for a
+// stencil-like matrix, each 8R bytes, so the gathers coalesce.  A row is
+// summed left to right from rounded products, the order of the LDS schedule
+// (same bits).  Waves of a workgroup take its slices in turn.
+template <int R, int U, class CT>
 __global__ __launch_bounds__(kBlock) void k_bspmm_slices(const WgDesc *__restrict__ wgs,
                                                          const int32_t *__restrict__ sl_row,
                                                          const int32_t *__restrict__ sl_off,
-                                                         const int32_t *__restrict__ col,
+                                                         const CT *__restrict__ col,
                                                          const double *__restrict__ val,
                                                          const double *__restrict__ P, double *__restrict__ Q,
                                                          double *__restrict__ sig_part, Inst *inst)
@@ -332,14 +346,31 @@ __global__ __launch_bounds__(kBlock) void k_bspmm_slices(const WgDesc *__restric
             for (int r = 0; r < R; ++r)
                 a[r] = 0.0;
             for (int k0 = 0; k0 < L; k0 += U) {
+                static_assert(U % 2 == 0, "entries come in pairs");
                 int c[U];
                 double v[U], pv[U][R];
+                // one 2-wide load per pair, unconditional: the single last
+                // entry of an odd width through the aligned pair holding it
+                // (the lane's parity picks the half), past the width positions
+                // 0 and 1 (discarded); then the entries are selected
+                typename Pair2<CT>::type craw[U / 2];
+                typename Pair2<double>::type vraw[U / 2];
 #pragma unroll
-                for (int u = 0; u < U; ++u) {
-                    const bool ok = k0 + u < L;
-                    const int e = e0 + (k0 + u) * 64 + lane;
-                    c[u] = ok ? __builtin_nontemporal_load(col + e) : -1;
-                    v[u] = ok ? __builtin_nontemporal_load(val + e) : 0.0;
+                for (int u = 0; u < U; u += 2) {
+                    const int k = k0 + u;
+                    const int e = k + 1 < L ? e0 + (k >> 1) * 128 + 2 * lane : k < L ? e0 + k * 64 + (lane & ~1) : 0;
+                    craw[u >> 1] = __builtin_nontemporal_load(reinterpret_cast<const typename Pair2<CT>::type *>(col + e));
+                    vraw[u >> 1] =
+                        __builtin_nontemporal_load(reinterpret_cast<const typename Pair2<double>::type *>(val + e));
+                }
+#pragma unroll
+                for (int u = 0; u < U; u += 2) {
+                    const int k = k0 + u;
+                    const bool pair = k + 1 < L, hi = !pair && (lane & 1);
+                    c[u] = k < L ? bcol_of(hi ? craw[u >> 1].y : craw[u >> 1].x, row) : -1;
+                    c[u + 1] = pair ? bcol_of(craw[u >> 1].y, row) : -1;
+                    v[u] = hi ? vraw[u >> 1].y : vraw[u >> 1].x;
+                    v[u + 1] = vraw[u >> 1].y;
                 }
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
@@ -647,6 +678,7 @@ struct cg_batch {
     // sliced layout (built once, on first use): per system, slices of 64 rows
     std::vector<int32_t> hsl_row, hsl_sys0; // first row of each slice; first slice of each system (+ end)
     int32_t *sl_row = nullptr, *sl_off = nullptr, *sl_col = nullptr;
+    int16_t *sl_d16 = nullptr; // columns as 16-bit offsets from the row (every one within 32767), else null
     double *sl_val = nullptr;
     // device
     std::vector<void *> allocs, plan_allocs;
@@ -791,11 +823,11 @@ int build_plan(cg_batch *h, int ept, int wg_target)
 }
 
 // The sliced layout of the block-diagonal matrix, once: each system's rows
-// in slices of 64 (the last one of a system may be short), positions
-// off + 64 k + lane, padded with column -1 / value 0.
+// in slices of 64 (the last one of a system may be short), entries paired as
+// in k_bspmm_slices (slice_position), padded with column -1 / value 0.
 int ensure_slices(cg_batch *h)
 {
-    if (h->sl_col)
+    if (h->sl_col || h->sl_d16)
         return CG_OK;
     const int32_t *ptr = h->hptr.data(), *idx = h->hidx.data();
     std::vector<int32_t> row0, off(1, 0), sys0(h->nsys + 1, 0);
@@ -817,15 +849,24 @@ int ensure_slices(cg_batch *h)
     sys0[h->nsys] = (int32_t)row0.size();
     const size_t npos = (size_t)off.back();
     std::vector<int32_t> col(npos, -1), src(npos, -1);
+    std::vector<int16_t> d16(npos, kPad16);
+    bool c16 = true; // every column within 32767 of its row (experiments: CGMI_COL16=0, never)
+    if (const char *e = std::getenv("CGMI_COL16"))
+        c16 = std::strcmp(e, "0") != 0;
     for (int s = 0; s < h->nsys; ++s) {
         const int64_t b = h->sys_off[s + 1];
-        for (int32_t q = sys0[s]; q < sys0[s + 1]; ++q)
+        for (int32_t q = sys0[s]; q < sys0[s + 1]; ++q) {
+            const int64_t w = (off[q + 1] - off[q]) / 64;
             for (int64_t i = row0[q]; i < std::min<int64_t>(b, (int64_t)row0[q] + 64); ++i)
                 for (int64_t k = ptr[i]; k < ptr[i + 1]; ++k) {
-                    const int64_t e = off[q] + (k - ptr[i]) * 64 + (i - row0[q]);
+                    const int64_t e = off[q] + slice_position(k - ptr[i], i - row0[q], w);
                     col[e] = idx[k];
                     src[e] = (int32_t)k;
+                    const int64_t d = (int64_t)idx[k] - i;
+                    c16 = c16 && d >= -32767 && d <= 32767;
+                    d16[e] = (int16_t)d;
                 }
+        }
     }
     // values: gathered on the device from the CSR copy through src
     std::vector<void *> tmp;
@@ -833,7 +874,8 @@ int ensure_slices(cg_batch *h)
     int st;
     if ((st = bupload(h, h->allocs, &h->sl_row, row0.data(), row0.size())) != CG_OK ||
         (st = bupload(h, h->allocs, &h->sl_off, off.data(), off.size())) != CG_OK ||
-        (st = bupload(h, h->allocs, &h->sl_col, col.data(), col.size())) != CG_OK ||
+        (c16 ? (st = bupload(h, h->allocs, &h->sl_d16, d16.data(), d16.size()))
+             : (st = bupload(h, h->allocs, &h->sl_col, col.data(), col.size()))) != CG_OK ||
         (st = balloc(h, h->allocs, &h->sl_val, npos)) != CG_OK || (st = bupload(h, tmp, &dsrc, src.data(), npos)) != CG_OK) {
         free_list(tmp);
         return st;
@@ -934,8 +976,12 @@ template <int R>
 void spmm_slices(cg_batch *h, const double *P, double *Q, Inst *inst, hipStream_t s)
 {
     constexpr int U = 8; // positions per round
-    hipLaunchKernelGGL((k_bspmm_slices<R, U>), dim3(h->G), dim3(kBlock), 0, s, h->wgs, h->sl_row, h->sl_off,
-                       h->sl_col, h->sl_val, P, Q, h->sig, inst);
+    if (h->sl_d16)
+        hipLaunchKernelGGL((k_bspmm_slices<R, U, int16_t>), dim3(h->G), dim3(kBlock), 0, s, h->wgs, h->sl_row,
+                           h->sl_off, h->sl_d16, h->sl_val, P, Q, h->sig, inst);
+    else
+        hipLaunchKernelGGL((k_bspmm_slices<R, U, int32_t>), dim3(h->G), dim3(kBlock), 0, s, h->wgs, h->sl_row,
+                           h->sl_off, h->sl_col, h->sl_val, P, Q, h->sig, inst);
 }
 
 // the product of the current plan and schedule

@@ -93,6 +93,28 @@ def test_batch_spmm_rowwise(lanes, monkeypatch):
             assert np.all(np.abs(Y[:, r] - yo) <= bound), float(np.max(np.abs(Y[:, r] - yo) - bound))
 
 
+@pytest.mark.parametrize("col16", ["1", "0"])
+def test_batch_slices_column_storage(col16, monkeypatch):
+    """Slices of the batch with columns as 16-bit offsets from the row (the
+    default for these banded systems) or as 32-bit indices: the product is
+    bit-identical to the oracle's either way (odd and even slice widths,
+    short last slices), and whole solves give the same bits."""
+    monkeypatch.setenv("CGMI_BATCH_LANES", "1")
+    systems, B = small_batch(2, seed=4)
+    so, ptr, col, val = W.block_diagonal(systems)
+    X = np.random.default_rng(5).uniform(-1, 1, size=(so[-1], 2))
+    out = {}
+    for c16 in ("1", "0"):
+        monkeypatch.setenv("CGMI_COL16", c16)
+        with cgmi.Batch(so, ptr, col, val, nrhs=2) as bt:
+            Y = bt.spmm(to_dev(X)).cpu().numpy()
+            Xs, info, iters, stat = bt.solve(to_dev(B), tol=1e-10, maxit=20000)
+            out[c16] = (Xs.cpu().numpy(), iters.copy())
+        for r in range(2):
+            assert np.array_equal(Y[:, r], oracle.spmv(0, ptr, col, val, X[:, r])), (c16, r)
+    assert np.array_equal(out["1"][0], out["0"][0]) and np.array_equal(out["1"][1], out["0"][1])
+
+
 def test_batch_statuses_per_pair():
     import torch
     sysA = W.fem_p1_system(6, 6, 5, seed=3)
