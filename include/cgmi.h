@@ -143,8 +143,10 @@ int cg_create(cg_handle **out, int format, int64_t n, const int32_t *ptr, const 
  * stream).  Always stream-ordered with the caller's own work on it. */
 int cg_set_stream(cg_handle *h, void *hip_stream);
 
-/* Iterations captured per graph launch in cg_solve (default 32, 1..4096).
- * Only affects scheduling, never the result. */
+/* Iterations captured per graph launch in cg_solve (default 32, 1..4096;
+ * rounded up to even where two kernels run per iteration, small systems).
+ * Only affects scheduling, never the result.  The inner solves of
+ * cg_solve_mixed use at most 8 per launch. */
 int cg_set_batch(cg_handle *h, int32_t iters_per_launch);
 
 /*
