@@ -104,7 +104,9 @@ typedef struct {
                                 it stays in the Infinity Cache between iterations (small enough);
                                 0 = non-temporal loads */
     int32_t compact;         /* symmetric CSR: 1 = compact blocks grown on the graph of A (each block
-                                stores its own rows, parks the rest); 0 = coloured line ranges */
+                                stores its own rows, parks the rest); 0 = coloured line ranges, or,
+                                with slices != 0, the triangle expanded into full-row slices (systems
+                                whose vector kernels have at most 256 workgroups, n <= 65 536) */
     int64_t slots;           /* scatter formats: total (block, target) write slots */
     int64_t plan_bytes;      /* device bytes of the plan beyond ptr / idx / vals */
     int64_t parked;          /* scatter formats: slot sums parked and added by the row pass */
