@@ -528,16 +528,30 @@ def parse_counters(a):
     w_scale = nb / (calib["WRITE_SIZE"]["copy_kib"] * 1024)
     for fmt in ("csr", "symcsr", "csc"):
         ks = PRODUCT_KERNELS[fmt]
-        fb = sum(v["mean_kib"] for k, v in calib["FETCH_SIZE"]["kernels"].items() if any(x in k for x in ks))
-        wb = sum(v["mean_kib"] for k, v in calib["WRITE_SIZE"]["kernels"].items() if any(x in k for x in ks))
-        per[fmt] = dict(fetch_bytes=round(fb * 1024 * f_scale), write_bytes=round(wb * 1024 * w_scale))
+        per[fmt] = dict(fetch_bytes=0, write_bytes=0, kernels={})
+        for k in calib["FETCH_SIZE"]["kernels"]:
+            if not any(x in k for x in ks):
+                continue
+            fk = round(calib["FETCH_SIZE"]["kernels"][k]["mean_kib"] * 1024 * f_scale)
+            wk = round(calib["WRITE_SIZE"]["kernels"].get(k, {"mean_kib": 0.0})["mean_kib"] * 1024 * w_scale)
+            per[fmt]["kernels"][short_kernel_name(k)] = dict(fetch_bytes=fk, write_bytes=wk)
+            per[fmt]["fetch_bytes"] += fk
+            per[fmt]["write_bytes"] += wk
         per[fmt]["total"] = per[fmt]["fetch_bytes"] + per[fmt]["write_bytes"]
+    run = ("cd /tmp && export TMPDIR=/tmp PYTHONPATH=$REPO && rocprofv3 --pmc {c} -d $REPO/gpurun_out/ctr_{w}_{c} "
+           "-o c --output-format csv -- python3 $REPO/bench.py --mode counters --workload {w} --spmv-reps {r}")
     out = dict(kernel_src_sha=kernel_source_sha(), workload=a.workload,
                calibration=dict(copy_bytes_each_way=nb, fetch_scale=f_scale, write_scale=w_scale),
                per_launch_bytes={k: v["total"] for k, v in per.items()}, detail=per,
-               command=f"rocprofv3 --pmc FETCH_SIZE -d <run1> -- python bench.py --mode counters --workload "
-                       f"{a.workload} --spmv-reps {a.spmv_reps}; the same with WRITE_SIZE -d <run2>; "
-                       f"python bench.py --mode parse-counters --workload {a.workload} --counter-dirs <run1>,<run2>")
+               command="; ".join([run.format(c=c, w=a.workload, r=a.spmv_reps) for c in ("FETCH_SIZE", "WRITE_SIZE")]
+                                 + [f"python3 $REPO/bench.py --mode parse-counters --workload {a.workload} "
+                                    f"--counter-dirs $REPO/gpurun_out/ctr_{a.workload}_FETCH_SIZE,"
+                                    f"$REPO/gpurun_out/ctr_{a.workload}_WRITE_SIZE"]),
+               note="HBM bytes per product launch (mean over its launches), each counter scaled by what it reads "
+                    "for a 1 GiB device copy in the same run (FETCH_SIZE counts 64-byte requests, hence the factor "
+                    "~2); symcsr and csc include their row-pass kernel (k_scatter_gather / k_panel_gather) of the "
+                    "lone product, which inside CG is folded into the r update; detail.<format>.kernels splits the "
+                    "bytes by kernel")
     with open(traffic_file(a.workload), "w") as f:
         json.dump(out, f, indent=1)
     print(json.dumps(out), flush=True)
