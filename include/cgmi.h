@@ -220,7 +220,8 @@ int cg_batch_spmm(cg_batch *h, const double *X, double *Y);
 /* Project-written autotuner: times the product for every schedule -- row
  * blocks of 256, 512 or 1024 entries summed through LDS, or 8 or 16 lanes
  * per row combined by butterflies, or one lane per row over 64-row slices of
- * each system stored k-th entry first -- x workgroup budget (1024, 2048,
+ * each system (entries paired side by side; columns as 16-bit offsets from
+ * the row when every one lies within 32767 of it) -- x workgroup budget (1024, 2048,
  * 4096; twice that for the slices), keeps the fastest plan and reports it
  * (outputs may be NULL; lanes_per_row = 0 means the LDS row-block schedule,
  * 1 the slices, whose entries_per_block is 0).  Uses the GPU. */
@@ -385,9 +386,10 @@ int cg_analyze_export(int format, int64_t n, const int32_t *ptr, const int32_t *
 
 /*
  * Host-only export of the compact-block plan of CG_FMT_SYM_CSR (chosen when
- * every stored row has at most 8 entries; cg_plan_stats.compact == 1).
+ * every stored row has at most 8 entries and, unless CGMI_SYM_EXPAND=0, the
+ * system has more than 65 536 rows; cg_plan_stats.compact == 1).
  * Blocks are grown on the graph of A (breadth first from the lowest free
- * row, at most 256 rows each); a block stores y for its own rows and parks
+ * row, at most 512 rows each, fewer on small systems); a block stores y for its own rows and parks
  * its sums for the other rows its mirrored products reach (the transpose
  * half of the symmetric product, section III of the paper), so no two
  * blocks write one location.  Sizes from cg_analyze: n, scatter_blocks,
