@@ -637,12 +637,20 @@ def main():
     kernel = {"csr": "k_spmv_slices (CSR product, 64-row slices)" if prod["sliced"] else "k_spmv_csr_rows",
               "symcsr": "symmetric-CSR product (scatter kernel + row pass)",
               "csc": "CSC product on column panels (slot kernel + row pass)"}[a.format]
-    roofline = dict(bound="hbm", achieved=prod["GBps"], peak=HBM_PEAK_GBPS, unit="GB/s",
-                    frac=round(prod["GBps"] / HBM_PEAK_GBPS, 4), traffic=load_traffic(a.workload, a.format),
-                    kernel=kernel, bytes_per_launch=nbytes, avg_us=prod["us"],
+    # a matrix that stays in the Infinity Cache between products is priced
+    # against HBM on its cold launches (after the 1 GiB read); its warm rate
+    # is an effective cache rate, reported beside it
+    resident = prod["matrix_cache_resident"]
+    use_us, use_gbps = (prod["cold_us"], prod["cold_GBps"]) if resident else (prod["us"], prod["GBps"])
+    roofline = dict(bound="hbm", achieved=use_gbps, peak=HBM_PEAK_GBPS, unit="GB/s",
+                    frac=round(use_gbps / HBM_PEAK_GBPS, 4), traffic=load_traffic(a.workload, a.format),
+                    kernel=kernel, bytes_per_launch=nbytes, avg_us=use_us,
+                    timing="cold launches (matrix cache-resident when warm)" if resident else "back to back",
                     cold_frac=round(prod["cold_GBps"] / HBM_PEAK_GBPS, 4),
-                    matrix_cache_resident=prod["matrix_cache_resident"],
-                    frac_of_copy=round(prod["GBps"] / copy_gbps, 4))
+                    matrix_cache_resident=resident,
+                    frac_of_copy=round(use_gbps / copy_gbps, 4))
+    if resident:
+        roofline["warm_cache_GBps"] = prod["GBps"]
 
     def room(name):
         if name not in a.extras:
