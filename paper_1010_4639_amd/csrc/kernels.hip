@@ -817,7 +817,11 @@ __global__ __launch_bounds__(kCompactThreads) void k_scatter_compact(
 #pragma clang fp contract(off)
     constexpr int E = kStreamPerThread;
     constexpr int TB = kCompactThreads;
-    constexpr int kStarts = ((TB + kCompactEntries + 1) + 7) / 8 * 8;
+    // slot starts: staged through LDS (16 bytes per thread) for a streamed
+    // matrix; for a cache-resident one each thread reads its slots' starts
+    // itself, which frees 9 KB of LDS for a 4th workgroup per CU (a latency-
+    // bound product gains from it, a bandwidth-bound one does not)
+    constexpr int kStarts = NT ? ((TB + kCompactEntries + 1) + 7) / 8 * 8 : 8;
     __shared__ double sp[kCompactEntries];
     __shared__ __align__(16) uint16_t st16[kStarts];
     __shared__ double red[TB / 64];
@@ -862,11 +866,21 @@ __global__ __launch_bounds__(kCompactThreads) void k_scatter_compact(
         //      issued: indices are clamped into the block and the values
         //      selected afterwards; branches on the block's sizes are uniform.
         const int nchunk = (bk.nslots + 8) / 8; // 16-byte chunks of the nslots + 1 slot starts
-        const uint4v *segv = reinterpret_cast<const uint4v *>(seg + bk.seg0);
-        const uint4v sg0 = matrix_load<NT>(segv + min(t, nchunk - 1));
-        uint4v sg1 = {0u, 0u, 0u, 0u};
-        if (nchunk > TB)
-            sg1 = matrix_load<NT>(segv + min(t + TB, nchunk - 1));
+        uint4v sg0 = {0u, 0u, 0u, 0u}, sg1 = {0u, 0u, 0u, 0u};
+        int s0[SU], s1[SU]; // cache-resident: the run [seg[s], seg[s + 1]) of each of the thread's slots
+        if constexpr (NT) {
+            const uint4v *segv = reinterpret_cast<const uint4v *>(seg + bk.seg0);
+            sg0 = matrix_load<NT>(segv + min(t, nchunk - 1));
+            if (nchunk > TB)
+                sg1 = matrix_load<NT>(segv + min(t + TB, nchunk - 1));
+        } else {
+#pragma unroll
+            for (int u = 0; u < SU; ++u) { // index clamped to the block's nslots + 1 starts, unused past them
+                const int s = t + u * TB;
+                s0[u] = seg[bk.seg0 + min(s, bk.nslots)];
+                s1[u] = seg[bk.seg0 + min(s + 1, bk.nslots)];
+            }
+        }
         const int tl = mine ? t : 0;
         const int line = mine ? bk.line0 + t : -1; // rows renumbered in block order
         const uint4v rk = matrix_load<NT>(reinterpret_cast<const uint4v *>(rank) + (bk.line0 + tl));
@@ -930,10 +944,12 @@ __global__ __launch_bounds__(kCompactThreads) void k_scatter_compact(
                 xt[u] = t + u * TB < nl ? xo : (double)gather0(x, tg[u]);
         }
         // ---- slot starts to LDS (read after the barrier below)
-        if (t < nchunk)
-            *reinterpret_cast<uint4v *>(st16 + 8 * t) = sg0;
-        if (nchunk > TB && t + TB < nchunk)
-            *reinterpret_cast<uint4v *>(st16 + 8 * (t + TB)) = sg1;
+        if constexpr (NT) {
+            if (t < nchunk)
+                *reinterpret_cast<uint4v *>(st16 + 8 * t) = sg0;
+            if (nchunk > TB && t + TB < nchunk)
+                *reinterpret_cast<uint4v *>(st16 + 8 * (t + TB)) = sg1;
+        }
         // ---- own row in registers; mirror products (not the diagonal) to their places
         const uint32_t rw[4] = {rk.x, rk.y, rk.z, rk.w};
         double own = 0.0;
@@ -954,8 +970,8 @@ __global__ __launch_bounds__(kCompactThreads) void k_scatter_compact(
             const int s = t + u * TB;
             const bool own_slot = s < nl; // implies u == 0 and s == t
             double a = own_slot ? own : 0.0;
-            const int hi = st16[s + 1];
-            for (int i = st16[s]; i < hi; ++i)
+            const int lo = NT ? (int)st16[s] : s0[u], hi = NT ? (int)st16[s + 1] : s1[u];
+            for (int i = lo; i < hi; ++i)
                 a += sp[i];
             if (own_slot)
                 y[tg[u]] = a;
