@@ -1046,10 +1046,10 @@ __global__ __launch_bounds__(kBlock) void k_panel_gather(int n, const uint8_t *_
 }
 
 // ------------------------------------------------------ vector kernels
-// Each workgroup owns a contiguous chunk (XCD-remapped).  The first kPre
+// Each workgroup owns a contiguous chunk (XCD-remapped).  The first KP
 // elements per thread are loaded before the dot partials of the previous
 // kernel are reduced, so the two memory round trips overlap.
-constexpr int kPre = 8;
+constexpr int kPre = 8; // KP at most: a chunk of more than 8 x 256 elements takes the rest in a loop
 
 // Rows finished by the row pass of a scatter product: GATHER folds that pass
 // (k_scatter_gather's sum, same terms, same order) into the r update, so the
@@ -1099,20 +1099,20 @@ __device__ __forceinline__ double q_value(const double *__restrict__ q, const Ro
 }
 
 // q (with the row pass of GATHER folded in: q_value's terms in q_value's
-// order) and r of a thread's first kPre rows (i0, i0 + kBlock, ...; rows from
+// order) and r of a thread's first KP rows (i0, i0 + kBlock, ...; rows from
 // i1 on give 0).  The loads go out in dependency order -- row-pass indices or
 // flags, then q and r, then the parked sums -- each group for every row before
 // anything waits (loads complete in issue order); a parked sum is read
 // unguarded (from element 0, or from q_i, when the row has none) and selected
 // afterwards, so no load shares a branch with its add and waits there.
-template <int GATHER>
+template <int GATHER, int KP>
 __device__ __forceinline__ void row_values(const double *__restrict__ q, const double *__restrict__ r,
-                                           const RowPass &g, int n, int i0, int i1, double (&qv)[kPre],
-                                           double (&rv)[kPre])
+                                           const RowPass &g, int n, int i0, int i1, double (&qv)[KP],
+                                           double (&rv)[KP])
 {
-    int k0[kPre], k1[kPre], fl[kPre];
+    int k0[KP], k1[KP], fl[KP];
 #pragma unroll
-    for (int u = 0; u < kPre; ++u) {
+    for (int u = 0; u < KP; ++u) {
         const int i = i0 + u * kBlock;
         const bool ok = i < i1;
         k0[u] = 0;
@@ -1128,7 +1128,7 @@ __device__ __forceinline__ void row_values(const double *__restrict__ q, const d
             fl[u] = ok ? (int)g.has_c0[i] : 0;
     }
 #pragma unroll
-    for (int u = 0; u < kPre; ++u) {
+    for (int u = 0; u < KP; ++u) {
         const int i = i0 + u * kBlock;
         const bool ok = i < i1;
         if (GATHER == 1)
@@ -1138,9 +1138,9 @@ __device__ __forceinline__ void row_values(const double *__restrict__ q, const d
         rv[u] = ok ? r[i] : 0.0;
     }
     if constexpr (GATHER == 2 || GATHER == 3) {
-        double p0[kPre], p1[kPre];
+        double p0[KP], p1[KP];
 #pragma unroll
-        for (int u = 0; u < kPre; ++u) {
+        for (int u = 0; u < KP; ++u) {
             if (GATHER == 3) { // part holds at least one element
                 p0[u] = g.part[k0[u] < k1[u] ? k0[u] : 0];
                 p1[u] = g.part[k0[u] + 1 < k1[u] ? k0[u] + 1 : 0];
@@ -1151,7 +1151,7 @@ __device__ __forceinline__ void row_values(const double *__restrict__ q, const d
             }
         }
 #pragma unroll
-        for (int u = 0; u < kPre; ++u) {
+        for (int u = 0; u < KP; ++u) {
             double a = qv[u];
             if (GATHER == 2) {
                 a = (fl[u] & 1) ? a : 0.0;
@@ -1171,7 +1171,9 @@ __device__ __forceinline__ void row_values(const double *__restrict__ q, const d
 // of the two-kernel iteration: r'r of the current residual is the one the
 // product published (rho_next), and a stop the product decided (conv_next)
 // is recorded here.
-template <int GATHER, int PPT, bool FUSED = false>
+// KP: elements per thread loaded up front (the chunk's, up to 8 x 256;
+// registers sized to the chunk, so small chunks keep more waves resident).
+template <int GATHER, int PPT, bool FUSED, int KP>
 __global__ __launch_bounds__(kBlock) void k_update_r(int n, int chunk, double *__restrict__ r,
                                                      const double *__restrict__ q, DevState *st,
                                                      const double *__restrict__ sig_part, int n_sig,
@@ -1188,8 +1190,8 @@ __global__ __launch_bounds__(kBlock) void k_update_r(int n, int chunk, double *_
     const int t = threadIdx.x;
     double pv[PPT];
     partials_load(sig_part, n_sig, pv);
-    double qv[kPre], rv[kPre];
-    row_values<GATHER>(q, r, g, n, i0 + t, i1, qv, rv);
+    double qv[KP], rv[KP];
+    row_values<GATHER, KP>(q, r, g, n, i0 + t, i1, qv, rv);
     if (status != kRun)
         return;
     const bool lead = blockIdx.x == 0 && t == 0;
@@ -1222,7 +1224,7 @@ __global__ __launch_bounds__(kBlock) void k_update_r(int n, int chunk, double *_
     }
     double acc = 0.0;
 #pragma unroll
-    for (int u = 0; u < kPre; ++u) {
+    for (int u = 0; u < KP; ++u) {
         const int i = i0 + t + u * kBlock;
         if (i < i1) {
             const double ri = fma(-alpha, qv[u], rv[u]);
@@ -1230,7 +1232,7 @@ __global__ __launch_bounds__(kBlock) void k_update_r(int n, int chunk, double *_
             acc = fma(ri, ri, acc);
         }
     }
-    for (int i = i0 + t + kPre * kBlock; i < i1; i += kBlock) {
+    for (int i = i0 + t + KP * kBlock; i < i1; i += kBlock) {
         const double ri = fma(-alpha, q_value<GATHER>(q, g, i), r[i]);
         r[i] = ri;
         acc = fma(ri, ri, acc);
@@ -1245,7 +1247,7 @@ __global__ __launch_bounds__(kBlock) void k_update_r(int n, int chunk, double *_
 // kernel reads those two fields).
 // PT: storage type of p (double; float for the inner solves of mixed
 // precision, where p is rounded to FP32 after the FP64 update).
-template <class PT, int PPT>
+template <class PT, int PPT, int KP>
 __global__ __launch_bounds__(kBlock) void k_update_xp(int n, int chunk, double *__restrict__ x,
                                                       PT *__restrict__ p, const double *__restrict__ r,
                                                       DevState *st, const double *__restrict__ rho_part,
@@ -1261,9 +1263,9 @@ __global__ __launch_bounds__(kBlock) void k_update_xp(int n, int chunk, double *
     const int t = threadIdx.x;
     double part[PPT];
     partials_load(rho_part, n_rho, part);
-    double pv[kPre], xv[kPre], rv[kPre];
+    double pv[KP], xv[KP], rv[KP];
 #pragma unroll
-    for (int u = 0; u < kPre; ++u) {
+    for (int u = 0; u < KP; ++u) {
         const int i = i0 + t + u * kBlock;
         const bool ok = i < i1;
         pv[u] = ok ? (double)p[i] : 0.0;
@@ -1282,7 +1284,7 @@ __global__ __launch_bounds__(kBlock) void k_update_xp(int n, int chunk, double *
         st->conv_next = sqrt(rho_new) <= st->tol_nb ? 1 : 0;
     }
 #pragma unroll
-    for (int u = 0; u < kPre; ++u) {
+    for (int u = 0; u < KP; ++u) {
         const int i = i0 + t + u * kBlock;
         if (i < i1) {
             x[i] = fma(alpha, pv[u], xv[u]);
@@ -1290,7 +1292,7 @@ __global__ __launch_bounds__(kBlock) void k_update_xp(int n, int chunk, double *
                 p[i] = (PT)fma(beta, pv[u], rv[u]);
         }
     }
-    for (int i = i0 + t + kPre * kBlock; i < i1; i += kBlock) {
+    for (int i = i0 + t + KP * kBlock; i < i1; i += kBlock) {
         const double pi = (double)p[i];
         x[i] = fma(alpha, pi, x[i]);
         if (!conv)
@@ -1764,6 +1766,16 @@ void launch_spmv32(const DevMatrix &m, const float *x, double *y, double *sig_pa
     spmv_any(m, m.val32, x, y, sig_part, c, s);
 }
 
+// Elements per thread loaded up front by the vector kernels: the smallest
+// power of two covering the chunk, at most kPre.
+static int prefetch_depth(int chunk)
+{
+    int kp = 1;
+    while (kp < kPre && kp * kBlock < chunk)
+        kp *= 2;
+    return kp;
+}
+
 void launch_update_r(const DevMatrix &m, double *r, const double *q, DevState *st, const double *sig_part,
                      double *rho_part, hipStream_t s, bool rows_deferred, bool fused)
 {
@@ -1783,9 +1795,19 @@ void launch_update_r(const DevMatrix &m, double *r, const double *q, DevState *s
     g.part = m.part; // iterations use the handle's own buffer
     const int mode = rows_deferred && m.row_pass() ? (m.panel ? 2 : m.compact ? 3 : 1) : 0;
     const dim3 grid(m.vec_blocks), blk(kBlock);
+    const int kp = prefetch_depth(m.vec_chunk);
+#define CGMI_UPDATE_R_KP(G, P, F, K)                                                                         \
+    hipLaunchKernelGGL((k_update_r<G, P, F, K>), grid, blk, 0, s, m.n, m.vec_chunk, r, q, st, sig_part, nsig,   \
+                       rho_part, g)
 #define CGMI_UPDATE_R(G, P, F)                                                                               \
-    hipLaunchKernelGGL((k_update_r<G, P, F>), grid, blk, 0, s, m.n, m.vec_chunk, r, q, st, sig_part, nsig, rho_part, \
-                       g)
+    do {                                                                                                     \
+        switch (kp) {                                                                                        \
+        case 1: CGMI_UPDATE_R_KP(G, P, F, 1); break;                                                         \
+        case 2: CGMI_UPDATE_R_KP(G, P, F, 2); break;                                                         \
+        case 4: CGMI_UPDATE_R_KP(G, P, F, 4); break;                                                         \
+        default: CGMI_UPDATE_R_KP(G, P, F, kPre); break;                                                     \
+        }                                                                                                    \
+    } while (0)
 #define CGMI_UPDATE_R_PPT(G, F)                                                                              \
     do {                                                                                                     \
         switch (ppt) {                                                                                       \
@@ -1811,6 +1833,7 @@ void launch_update_r(const DevMatrix &m, double *r, const double *q, DevState *s
         CGMI_UPDATE_R_PPT(0, false);
 #undef CGMI_UPDATE_R_PPT
 #undef CGMI_UPDATE_R
+#undef CGMI_UPDATE_R_KP
 }
 
 // x/p update with PPT partials per thread: the smallest power of two that
@@ -1821,8 +1844,18 @@ void update_xp_launch(const DevMatrix &m, double *x, PT *p, const double *r, Dev
 {
     static_assert(kMaxVecBlocks <= 8 * kBlock, "vector partials fit eight per thread");
     const dim3 grid(m.vec_blocks), blk(kBlock);
+    const int kp = prefetch_depth(m.vec_chunk);
+#define CGMI_UPDATE_XP_KP(P, K)                                                                              \
+    hipLaunchKernelGGL((k_update_xp<PT, P, K>), grid, blk, 0, s, m.n, m.vec_chunk, x, p, r, st, rho_part, m.vec_blocks)
 #define CGMI_UPDATE_XP(P)                                                                                    \
-    hipLaunchKernelGGL((k_update_xp<PT, P>), grid, blk, 0, s, m.n, m.vec_chunk, x, p, r, st, rho_part, m.vec_blocks)
+    do {                                                                                                     \
+        switch (kp) {                                                                                        \
+        case 1: CGMI_UPDATE_XP_KP(P, 1); break;                                                              \
+        case 2: CGMI_UPDATE_XP_KP(P, 2); break;                                                              \
+        case 4: CGMI_UPDATE_XP_KP(P, 4); break;                                                              \
+        default: CGMI_UPDATE_XP_KP(P, kPre); break;                                                          \
+        }                                                                                                    \
+    } while (0)
     if (m.vec_blocks <= kBlock)
         CGMI_UPDATE_XP(1);
     else if (m.vec_blocks <= 2 * kBlock)
@@ -1832,6 +1865,7 @@ void update_xp_launch(const DevMatrix &m, double *x, PT *p, const double *r, Dev
     else
         CGMI_UPDATE_XP(8);
 #undef CGMI_UPDATE_XP
+#undef CGMI_UPDATE_XP_KP
 }
 
 void launch_update_xp(const DevMatrix &m, double *x, double *p, const double *r, DevState *st,
