@@ -207,12 +207,13 @@ static int64_t block_entries(int64_t nnz, int64_t floor)
 
 static void plan_vectors(Plan &p)
 {
-    // 1024 elements per workgroup on large vectors (512 for the symmetric
-    // format, whose r update also finishes ~2 parked sums per row: measured
-    // 3 % faster there, 3 % slower for CSR); small vectors use down to 256
-    // per workgroup so that more compute units take part
+    // 1024 elements per workgroup on large vectors, in every format (at
+    // 100^3, with the vector kernels' registers sized to the chunk, 512 per
+    // workgroup measured 3-7 % slower per iteration in all three); small
+    // vectors use down to 256 per workgroup so that more compute units take
+    // part
     const int64_t n = p.n;
-    const int64_t per = p.format == kSymCsr ? 512 : 1024;
+    const int64_t per = 1024;
     int64_t g = std::max<int64_t>((n + per - 1) / per, std::min<int64_t>((n + 255) / 256, 512));
     g = std::max<int64_t>(1, std::min<int64_t>(g, kMaxVecBlocks));
     p.vec_blocks = (int)g;
