@@ -113,12 +113,19 @@ def test_fem_paper_sized(fmt):
     assert abs(spread2 - parity.stored_spread(ref)[0]) <= 1e-9 * spread2
 
 
+@pytest.mark.parametrize("dims", [(24, 22, 20), (60, 60, 60)])
 @pytest.mark.parametrize("fmt", [SYM, CSR, CSC])
-def test_fem_unit_coefficient_strict(fmt):
-    # no iron (kappa ~ 5e2): the 2-norm bar applies as is
-    s = W.fem_p1_system(24, 22, 20, iron_frac=0.0, seed=8)
+def test_fem_unit_coefficient_strict(fmt, dims):
+    # no iron (kappa ~ 5e2 at 24x22x20): the 2-norm bar applies as is.
+    # 60^3 (n 216 000): 512 vector workgroups of 422 elements, so the r and
+    # x/p updates load two elements per thread up front (their KP = 2 form)
+    s = W.fem_p1_system(*dims, iron_frac=0.0, seed=8)
     arrs = formats_of(s.rowptr, s.col, s.val)[fmt]
-    check_contract(fmt, arrs, s.b, *run_pair(fmt, arrs, s.b, label="fem24x22x20 nu=1"), label="fem24x22x20 nu=1")
+    label = "fem%dx%dx%d nu=1" % dims
+    if dims == (60, 60, 60):
+        with cgmi.Solver(fmt, *arrs) as S:
+            assert S.stats()["vec_blocks"] == 512
+    check_contract(fmt, arrs, s.b, *run_pair(fmt, arrs, s.b, label=label), label=label)
 
 
 @pytest.mark.parametrize("fmt", [CSR, SYM, CSC])
