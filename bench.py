@@ -538,15 +538,17 @@ def parse_counters(a):
             per[fmt]["fetch_bytes"] += fk
             per[fmt]["write_bytes"] += wk
         per[fmt]["total"] = per[fmt]["fetch_bytes"] + per[fmt]["write_bytes"]
-    run = ("cd /tmp && export TMPDIR=/tmp PYTHONPATH=$REPO && rocprofv3 --pmc {c} -d $REPO/gpurun_out/ctr_{w}_{c} "
-           "-o c --output-format csv -- python3 $REPO/bench.py --mode counters --workload {w} --spmv-reps {r}")
+    # the commands that made these numbers, with the run directories given
+    show = [os.path.abspath(d).replace(ROOT, "$REPO", 1) for d in dirs]
+    run = ("cd /tmp && export TMPDIR=/tmp PYTHONPATH=$REPO && rocprofv3 --pmc {c} -d {d} -o c --output-format csv "
+           "-- python3 $REPO/bench.py --mode counters --workload {w} --spmv-reps {r}")
     out = dict(kernel_src_sha=kernel_source_sha(), workload=a.workload,
                calibration=dict(copy_bytes_each_way=nb, fetch_scale=f_scale, write_scale=w_scale),
                per_launch_bytes={k: v["total"] for k, v in per.items()}, detail=per,
-               command="; ".join([run.format(c=c, w=a.workload, r=a.spmv_reps) for c in ("FETCH_SIZE", "WRITE_SIZE")]
+               command="; ".join([run.format(c=c, d=d, w=a.workload, r=a.spmv_reps)
+                                  for c, d in zip(("FETCH_SIZE", "WRITE_SIZE"), show)]
                                  + [f"python3 $REPO/bench.py --mode parse-counters --workload {a.workload} "
-                                    f"--counter-dirs $REPO/gpurun_out/ctr_{a.workload}_FETCH_SIZE,"
-                                    f"$REPO/gpurun_out/ctr_{a.workload}_WRITE_SIZE"]),
+                                    f"--spmv-reps {a.spmv_reps} --counter-dirs {show[0]},{show[1]}"]),
                note="HBM bytes per product launch (mean over its launches), each counter scaled by what it reads "
                     "for a 1 GiB device copy in the same run (FETCH_SIZE counts 64-byte requests, hence the factor "
                     "~2); symcsr and csc include their row-pass kernel (k_scatter_gather / k_panel_gather) of the "
