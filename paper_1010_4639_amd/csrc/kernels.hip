@@ -340,8 +340,9 @@ __global__ __launch_bounds__(kBlock) void k_spmv_slices(int nl, int ns, const in
 #pragma clang fp contract(off)
     static_assert(!FUSED || (!PANEL && sizeof(PT) == 8), "the fused form is for FP64 CSR rows");
     // positions per round (values and gathered x stay in their stored type
-    // until the multiply)
-    constexpr int U = 8;
+    // until the multiply); 16 in the two-kernel form of small systems, whose
+    // rows then take one round instead of two (latency, not bytes, bounds it)
+    constexpr int U = FUSED ? 16 : 8;
     __shared__ double red[kWaves];
     const int wg = xcd_remap(blockIdx.x, gridDim.x);
     const int s0 = (int)((int64_t)wg * ns / gridDim.x);
